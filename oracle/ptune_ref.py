@@ -1,0 +1,183 @@
+"""Reference oracle for portability tuning -- TEST INFRASTRUCTURE ONLY.
+
+Plain-Python statements of the host-side steps of the method, used only by
+the test suite to check the native implementation.  Nothing here is fast;
+everything is written to be read against the paper.
+
+An execution-time table is a 2-D array ``t[v][s]``: variant ``v`` on shape
+(input) ``s``, in any time unit; ``inf`` marks a variant that failed the
+correctness screen or could not run on that shape (Sec. V-C: such data are
+screened out).
+
+Readings of the paper taken here (also listed in the design notes):
+
+* Equation 1 prints ``max`` over the kernel set in the numerator; the text
+  around Fig. 1 says a set performs like its best member on each
+  environment, so the numerator is the *minimum* runtime over the selected
+  set.  The cost is the geometric mean of slowdowns (>= 1), minimised.
+* Ties (equal cost) are broken towards the lexicographically smallest tuple
+  of variant ids, as produced by ``itertools.combinations``.
+* The runtime dispatch rule for unseen shapes is not given by the paper
+  (Sec. V-I lists it as a limitation); this build uses the nearest training
+  shape in (log2 M, log2 N, log2 K) under the L1 distance, ties to the lower
+  training-shape index.
+"""
+from __future__ import annotations
+
+import itertools
+import math
+
+INF = float("inf")
+
+
+def _finite(x):
+    return x == x and x != INF
+
+
+# --- Sec. V-C: post-processing pass -------------------------------------------
+
+def postprocess(times):
+    """Per-shape best and worst, and each entry's slowdown and speedup.
+
+    Sec. V-C: a post-processing pass relates every kernel's time to the best
+    and the worst kernel for the same device and input.  Table VI prints the
+    results as "Slowdown vs Oracle" (time / best) and "Speedup vs Worst"
+    (worst / time).  Failed entries (inf) get slowdown inf and speedup 0.
+
+    Returns ``(best, worst, best_id, slowdown, speedup)``; ``best_id`` is the
+    lowest variant index attaining the best time, or -1 if none is finite.
+    """
+    nv = len(times)
+    ns = len(times[0]) if nv else 0
+    best, worst, best_id = [], [], []
+    for s in range(ns):
+        b, w, bi = INF, -INF, -1
+        for v in range(nv):
+            x = times[v][s]
+            if not _finite(x):
+                continue
+            if x < b:
+                b, bi = x, v
+            if x > w:
+                w = x
+        best.append(b)
+        worst.append(w if bi >= 0 else INF)
+        best_id.append(bi)
+    slowdown = [[INF] * ns for _ in range(nv)]
+    speedup = [[0.0] * ns for _ in range(nv)]
+    for v in range(nv):
+        for s in range(ns):
+            x = times[v][s]
+            if _finite(x) and best_id[s] >= 0:
+                slowdown[v][s] = x / best[s]
+                speedup[v][s] = worst[s] / x
+    return best, worst, best_id, slowdown, speedup
+
+
+def autotune(times, s):
+    """Sec. IV-A, AutoTune: the single best variant for one environment."""
+    best, _, best_id, _, _ = postprocess([[row[s]] for row in times])
+    return best_id[0]
+
+
+# --- Sec. IV-D-1, Eq. 1: library cost function ---------------------------------
+
+def library_cost(times, kappa, shapes=None):
+    """Eq. 1 (min reading): geomean over shapes of best-in-kappa / best-overall.
+
+    ``kappa`` is a collection of variant indices; ``shapes`` restricts the
+    environments summarised (default: all).  Returns inf if some shape has no
+    finite member of kappa.
+    """
+    ns = len(times[0])
+    shapes = list(range(ns)) if shapes is None else list(shapes)
+    best, _, _, _, _ = postprocess(times)
+    logsum = 0.0
+    for s in shapes:
+        m = min((times[v][s] for v in kappa), default=INF)
+        if not _finite(m) or not _finite(best[s]):
+            return INF
+        logsum += math.log(m / best[s])
+    return math.exp(logsum / len(shapes))
+
+
+def fraction_of_best(times, kappa, shapes=None):
+    """1 / cost: the geomean fraction of the per-shape best that kappa reaches."""
+    c = library_cost(times, kappa, shapes)
+    return 0.0 if c == INF else 1.0 / c
+
+
+# --- Sec. IV-B / IV-C-1: PortabilityTune by exhaustive search ------------------
+
+def portability_tune(times, k, shapes=None):
+    """kappa = argmin over all k-subsets of the variants of Eq. 1's cost.
+
+    Exhaustive enumeration of the subsets of size ``min(k, #variants)``; ties
+    go to the first subset in lexicographic order.  Returns
+    ``(kappa_tuple, cost)``; ``cost`` is inf if no subset covers every shape.
+    """
+    nv = len(times)
+    k = min(k, nv)
+    best_set, best_cost = None, INF
+    for kappa in itertools.combinations(range(nv), k):
+        c = library_cost(times, kappa, shapes)
+        if c < best_cost:
+            best_set, best_cost = kappa, c
+    if best_set is None:
+        best_set = tuple(range(k))
+    return best_set, best_cost
+
+
+def search_evaluations(n_inputs, n_devices, n_envs, n_variants, set_size):
+    """Sec. IV-C-1: evaluations bound |iota|*|delta|*|epsilon|*|K|^|kappa|."""
+    return n_inputs * n_devices * n_envs * n_variants ** set_size
+
+
+# --- Sec. IV-D-2, Eq. 2: fleet task rate ---------------------------------------
+
+def fleet_rate(runtime, qty_device, qty_input):
+    """Eq. 2: sum over devices of quantity(d) / sum over inputs of y' * quantity(i).
+
+    ``runtime[d][i]`` is y', the runtime of input i on device d.
+    """
+    rate = 0.0
+    for d, qd in enumerate(qty_device):
+        total = 0.0
+        for i, qi in enumerate(qty_input):
+            total += runtime[d][i] * qi
+        rate += qd / total
+    return rate
+
+
+# --- Runtime dispatch (Fig. 1 online step; rule of this build) -----------------
+
+def assign_winners(times, kappa, train_shapes_idx):
+    """For each training shape, the member of kappa with the lowest time
+    (ties to the lower variant id); -1 if no member is finite there."""
+    out = []
+    for s in train_shapes_idx:
+        bv, bt = -1, INF
+        for v in sorted(kappa):
+            x = times[v][s]
+            if _finite(x) and x < bt:
+                bv, bt = v, x
+        out.append(bv)
+    return out
+
+
+def nearest_training_shape(train_shapes, M, N, K):
+    """Index of the training shape nearest to (M,N,K) in L1 distance over
+    (log2 M, log2 N, log2 K); ties go to the lower index.  Sizes below 1 are
+    treated as 1."""
+    q = [math.log2(max(1, x)) for x in (M, N, K)]
+    best_i, best_d = -1, INF
+    for i, shp in enumerate(train_shapes):
+        d = sum(abs(q[j] - math.log2(max(1, shp[j]))) for j in range(3))
+        if d < best_d:
+            best_i, best_d = i, d
+    return best_i
+
+
+def dispatch(train_shapes, winners, M, N, K):
+    """Variant chosen for (M,N,K): the winner of its nearest training shape."""
+    return winners[nearest_training_shape(train_shapes, M, N, K)]

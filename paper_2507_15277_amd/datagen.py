@@ -1,0 +1,97 @@
+"""Seeded synthetic inputs shared by the tests, the tuner and the benchmark.
+
+This module only draws random numbers; it holds none of the arithmetic of
+the method.  Every generator is keyed by an explicit seed tuple so that the
+GPU path and the reference oracle are always fed the same host arrays.
+
+The paper's workloads are matrix *shapes* only (Sec. V-B: M, N, K taken from
+{256, 512, 1024, 4096}); there is no dataset to stand in for, so entries are
+drawn uniformly from [-1, 1).
+"""
+from __future__ import annotations
+
+import itertools
+
+import numpy as np
+
+# Operand tags used in seed tuples.
+OP_A, OP_B, OP_C = 0, 1, 2
+
+
+def uniform(seed, rows, cols, ld=None):
+    """FP32 matrix with entries uniform on [-1, 1), row stride ``ld``.
+
+    Drawn in FP32 (multiples of 2^-24 in [0,1)) and mapped by ``2x - 1``,
+    which is exact in FP32, so no value rounds to 1.0.  When ``ld > cols``
+    the padding columns are filled with NaN, so a kernel that reads past the
+    logical width poisons its own result.
+    Returns the logical ``rows x cols`` view (its base array has ``ld``
+    columns).
+    """
+    ld = cols if ld is None else ld
+    if ld < cols:
+        raise ValueError("ld < cols")
+    rng = np.random.default_rng(list(seed))
+    x = rng.random(rows * cols, dtype=np.float32) * np.float32(2) - np.float32(1)
+    if ld == cols:
+        return x.reshape(rows, cols)
+    base = np.full((rows, ld), np.nan, np.float32)
+    base[:, :cols] = x.reshape(rows, cols)
+    return base[:, :cols]
+
+
+def integers(seed, rows, cols, lo=-8, hi=8):
+    """FP32 matrix of integers drawn uniformly from [lo, hi]."""
+    rng = np.random.default_rng(list(seed))
+    return rng.integers(lo, hi + 1, size=(rows, cols)).astype(np.float32)
+
+
+def gemm_operands(cfg, M, N, K, beta=0.0, lda=None, ldb=None, ldc=None):
+    """(A, B, C0) for one GEMM problem, seeded by ``[cfg, M, N, K, op]``."""
+    A = uniform((cfg, M, N, K, OP_A), M, K, lda)
+    B = uniform((cfg, M, N, K, OP_B), K, N, ldb)
+    C0 = uniform((cfg, M, N, K, OP_C), M, N, ldc) if beta != 0.0 else None
+    return A, B, C0
+
+
+# --- Shape grids ---------------------------------------------------------------
+
+GRID_LEVELS = (256, 1024, 4096)
+SQUARE_SIZES = (512, 1024, 2048, 4096)
+# Shapes for which the paper reports the default kernel reaching under 15% of
+# the best on one device (Sec. I, footnote); two of them lie off the grid.
+SKEWED_EXTRA = ((512, 4096, 4096), (4096, 4096, 512))
+
+
+def grid27():
+    """All (M, N, K) with each size in {256, 1024, 4096}, lexicographic."""
+    return [tuple(s) for s in itertools.product(GRID_LEVELS, repeat=3)]
+
+
+def checkerboard_split(shapes=None):
+    """Split the 27-shape grid into 14 training and 13 held-out shapes.
+
+    Levels 256, 1024, 4096 are numbered 0, 1, 2; a shape is a training shape
+    iff the sum of its three levels is even.  This keeps all 8 corners and
+    the 6 shapes with two 1024s for training, and holds out the 12 shapes
+    with exactly one 1024 and the 1024^3 cube.
+    """
+    shapes = grid27() if shapes is None else shapes
+    lvl = {v: i for i, v in enumerate(GRID_LEVELS)}
+    train = [s for s in shapes if sum(lvl[x] for x in s) % 2 == 0]
+    held = [s for s in shapes if sum(lvl[x] for x in s) % 2 == 1]
+    return train, held
+
+
+def random_split(seed, n_train=14, shapes=None):
+    """A seeded random train/held-out split of the grid (robustness band)."""
+    shapes = grid27() if shapes is None else list(shapes)
+    rng = np.random.default_rng([7, seed])
+    idx = rng.permutation(len(shapes))
+    train = sorted(shapes[i] for i in idx[:n_train])
+    held = sorted(shapes[i] for i in idx[n_train:])
+    return train, held
+
+
+def square_shapes():
+    return [(s, s, s) for s in SQUARE_SIZES]

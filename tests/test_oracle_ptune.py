@@ -1,0 +1,205 @@
+"""Pins of the portability-tuning oracle against the paper's printed numbers,
+hand-derived small cases, and invariants of the definitions."""
+import itertools
+import math
+import os
+
+import numpy as np
+import pytest
+
+from oracle import ptune_ref as pr
+from paper_2507_15277_amd import datagen
+
+INF = float("inf")
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "table_vi.txt")
+
+
+def _table_vi():
+    rows = []
+    with open(GOLDEN) as f:
+        for line in f:
+            if line.startswith("#") or not line.strip():
+                continue
+            d, M, N, K, t, slow, speed = line.split()
+            rows.append((d, int(M), int(N), int(K), float(t), float(slow), float(speed)))
+    return rows
+
+
+def test_table_vi_quadro_pair():
+    # Table VI (Sec. V-C): two Quadro rows share input (1024,1024,256).  The
+    # faster (0.157 ms) has slowdown 1.0, so it is the best; the worst is
+    # implied by its speedup 474.71.  The other row's printed slowdown and
+    # speedup are then independent checks of the post-processing formulas.
+    rows = [r for r in _table_vi() if r[0] == "Quadro"]
+    slow_row, best_row = rows
+    worst = best_row[4] * best_row[6]
+    times = [[best_row[4]], [slow_row[4]], [worst]]
+    best, wst, best_id, slowdown, speedup = pr.postprocess(times)
+    assert best_id == [0] and best == [0.157]
+    assert round(slowdown[1][0], 2) == slow_row[5]          # 4.41
+    assert round(speedup[1][0], 2) == slow_row[6]           # 107.55
+    assert round(slowdown[0][0], 2) == best_row[5]          # 1.0
+    assert round(speedup[0][0], 2) == best_row[6]           # 474.71
+    assert slowdown[2][0] == pytest.approx(worst / 0.157) and speedup[2][0] == 1.0
+
+
+def test_table_vi_vega_rows_consistent():
+    # Each Vega row fixes best = t/slowdown and worst = t*speedup; feeding
+    # those back must reproduce the printed ratios to the printed precision.
+    for d, M, N, K, t, slow, speed in [r for r in _table_vi() if r[0] == "Vega"]:
+        times = [[t / slow], [t], [t * speed]]
+        _, _, _, slowdown, speedup = pr.postprocess(times)
+        assert round(slowdown[1][0], 2) == slow
+        assert round(speedup[1][0], 2) == speed
+
+
+def test_search_cost_count():
+    # Sec. IV-C-1: 1,343 Quadro variants, best 3 on 10 inputs needs
+    # "over 24 billion" evaluations under the |iota||delta||eps||K|^|kappa| bound.
+    n = pr.search_evaluations(10, 1, 1, 1343, 3)
+    assert n == 24_223_006_070
+    assert 24e9 < n < 25e9
+
+
+def test_hand_example():
+    # 3 variants x 2 shapes, worked by hand:
+    #   t = [[1, 4], [1.5, 1.5], [4, 1]], best = [1, 1]
+    #   k=1: v0 -> sqrt(1*4)=2, v1 -> sqrt(1.5*1.5)=1.5, v2 -> 2  => {1}, 1.5
+    #   k=2: {0,2} -> 1; {0,1} -> sqrt(1*1.5); {1,2} -> sqrt(1.5*1) => {0,2}, 1
+    t = [[1.0, 4.0], [1.5, 1.5], [4.0, 1.0]]
+    assert pr.portability_tune(t, 1) == ((1,), pytest.approx(1.5))
+    assert pr.portability_tune(t, 2) == ((0, 2), 1.0)
+    assert pr.library_cost(t, (0, 1)) == pytest.approx(math.sqrt(1.5))
+    assert pr.fraction_of_best(t, (1,)) == pytest.approx(1 / 1.5)
+
+
+def _block_table(groups, n_filler=3):
+    """Variant g is best (t=1) exactly on group g's shapes and 2 elsewhere;
+    filler variants are 3 everywhere.  Known answer by construction."""
+    ns = sum(groups)
+    owner = []
+    for g, n in enumerate(groups):
+        owner += [g] * n
+    t = [[1.0 if owner[s] == g else 2.0 for s in range(ns)] for g in range(len(groups))]
+    t += [[3.0] * ns for _ in range(n_filler)]
+    return t
+
+
+def test_block_structure_known_answer():
+    groups = [5, 3, 2]
+    t = _block_table(groups)
+    ns = sum(groups)
+    # k = #groups: the group owners, cost exactly 1.
+    kappa, c = pr.portability_tune(t, 3)
+    assert kappa == (0, 1, 2) and c == 1.0
+    # k = 1: owner of the largest group; cost 2^(shapes outside / all).
+    kappa, c = pr.portability_tune(t, 1)
+    assert kappa == (0,) and c == pytest.approx(2.0 ** ((ns - 5) / ns))
+    # k = 2: owners of the two largest groups.
+    kappa, c = pr.portability_tune(t, 2)
+    assert kappa == (0, 1) and c == pytest.approx(2.0 ** (2 / ns))
+
+
+def test_failed_entries_are_routed_around():
+    # v0 is best on both shapes it runs but failed the screen on shape 2.
+    t = [[1.0, 1.0, INF], [1.2, 1.2, 1.2], [3.0, 3.0, 1.0]]
+    kappa, c = pr.portability_tune(t, 1)
+    assert kappa == (1,) and c == pytest.approx(1.2 ** (2 / 3) * 1.2 ** (1 / 3))
+    kappa, c = pr.portability_tune(t, 2)
+    assert kappa == (0, 2) and c == 1.0
+    assert pr.library_cost(t, (0,)) == INF
+    best, worst, best_id, slowdown, speedup = pr.postprocess(t)
+    assert best_id == [0, 0, 2] and worst == [3.0, 3.0, 1.2]
+    assert slowdown[0][2] == INF and speedup[0][2] == 0.0
+
+
+def _rand_table(seed, nv, ns):
+    rng = np.random.default_rng(seed)
+    return (np.exp(rng.normal(0, 0.7, (nv, ns))) * rng.uniform(1, 5, ns)).tolist()
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_invariants(seed):
+    nv, ns = 9, 6
+    t = _rand_table(seed, nv, ns)
+    costs = [pr.portability_tune(t, k)[1] for k in range(1, nv + 1)]
+    # cost >= 1, non-increasing in k, and 1 once every per-shape winner fits.
+    assert all(c >= 1.0 - 1e-15 for c in costs)
+    assert all(costs[i + 1] <= costs[i] + 1e-15 for i in range(len(costs) - 1))
+    _, _, best_id, _, _ = pr.postprocess(t)
+    n_winners = len(set(best_id))
+    assert costs[n_winners - 1] == pytest.approx(1.0)
+    if n_winners > 1:
+        assert costs[n_winners - 2] > 1.0
+    # k = 1 is the variant with the smallest geomean slowdown.
+    best, _, _, _, _ = pr.postprocess(t)
+    g = [math.exp(np.mean([math.log(t[v][s] / best[s]) for s in range(ns)])) for v in range(nv)]
+    assert pr.portability_tune(t, 1)[1] == pytest.approx(min(g))
+    # Permuting shapes and variants permutes the answer and keeps the cost.
+    rng = np.random.default_rng(100 + seed)
+    pv, ps = rng.permutation(nv), rng.permutation(ns)
+    t2 = [[t[pv[v]][ps[s]] for s in range(ns)] for v in range(nv)]
+    for k in (1, 2, 3):
+        k1, c1 = pr.portability_tune(t, k)
+        k2, c2 = pr.portability_tune(t2, k)
+        assert c2 == pytest.approx(c1, rel=1e-12)
+        assert pr.library_cost(t, [pv[v] for v in k2]) == pytest.approx(c1, rel=1e-12)
+    # Scaling all times of one shape by a constant changes nothing.
+    t3 = [row[:] for row in t]
+    for v in range(nv):
+        t3[v][0] *= 7.0
+    assert pr.portability_tune(t3, 2)[1] == pytest.approx(pr.portability_tune(t, 2)[1])
+
+
+def test_cost_restricted_to_shapes():
+    t = [[1.0, 4.0, 2.0], [2.0, 1.0, 2.0]]
+    assert pr.library_cost(t, (0,), shapes=[0]) == 1.0
+    assert pr.library_cost(t, (0,), shapes=[1]) == 4.0
+    assert pr.library_cost(t, (1,), shapes=[0, 1]) == pytest.approx(math.sqrt(2.0))
+
+
+def test_fleet_rate_eq2():
+    # Two devices (2 and 1 units), two inputs (3 and 1 per task):
+    # device 0: 1*3 + 2*1 = 5 -> 2/5; device 1: 4*3 + 1*1 = 13 -> 1/13.
+    rate = pr.fleet_rate([[1.0, 2.0], [4.0, 1.0]], [2, 1], [3, 1])
+    assert rate == pytest.approx(2 / 5 + 1 / 13)
+
+
+def test_checkerboard_split():
+    train, held = datagen.checkerboard_split()
+    assert len(train) == 14 and len(held) == 13
+    assert set(train) | set(held) == set(datagen.grid27())
+    corners = [s for s in itertools.product((256, 4096), repeat=3)]
+    assert all(c in train for c in corners)
+    assert (1024, 1024, 1024) in held
+    assert sum(1 for s in train if s.count(1024) == 2) == 6
+    assert all(s.count(1024) == 1 for s in held if s != (1024, 1024, 1024))
+
+
+def test_dispatch_rule_hand_cases():
+    train, held = datagen.checkerboard_split()
+    winners = list(range(100, 100 + len(train)))
+    # Every training shape maps to itself.
+    for i, s in enumerate(train):
+        assert pr.nearest_training_shape(train, *s) == i
+        assert pr.dispatch(train, winners, *s) == winners[i]
+    # (256,256,1024): distance 2 to (256,256,256) and to (256,256,4096);
+    # the tie goes to the lower index, (256,256,256).
+    assert train[pr.nearest_training_shape(train, 256, 256, 1024)] == (256, 256, 256)
+    # 1024^3: distance 2 to each of the six two-1024 shapes; lowest index is
+    # (256,1024,1024).
+    assert train[pr.nearest_training_shape(train, 1024, 1024, 1024)] == (256, 1024, 1024)
+    # (4096,4096,1024): distance 2 to (1024,4096,1024), (4096,1024,1024),
+    # (4096,4096,256) and (4096,4096,4096), nothing closer; the first of
+    # these in lexicographic order is (1024,4096,1024).
+    assert train[pr.nearest_training_shape(train, 4096, 4096, 1024)] == (1024, 4096, 1024)
+    # (512,4096,4096): distance 1 to (256,4096,4096).
+    assert train[pr.nearest_training_shape(train, 512, 4096, 4096)] == (256, 4096, 4096)
+    # Degenerate sizes are clamped to 1.
+    assert train[pr.nearest_training_shape(train, 0, 1, 1)] == (256, 256, 256)
+
+
+def test_assign_winners():
+    t = [[1.0, 5.0, 2.0], [2.0, 1.0, 2.0], [3.0, 3.0, 1.0]]
+    assert pr.assign_winners(t, (0, 1), [0, 1, 2]) == [0, 1, 0]
+    assert pr.assign_winners(t, (1, 2), [0, 2]) == [1, 2]
