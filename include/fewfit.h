@@ -1,0 +1,227 @@
+/*
+ * fewfit -- multi-versioned single-precision GEMM with portability-tuned
+ * variant sets, for AMD Instinct MI355X (gfx950).
+ *
+ * C ABI of libfewfit.so.  Every entry point returns an int status (0 or a
+ * non-negative result on success, a negative FF_* code on failure), never
+ * throws, and takes plain pointers and sizes.  Device pointers are HIP
+ * device addresses; `stream` is a hipStream_t passed as void* (NULL = the
+ * default stream).  The text of the last error of the calling thread is
+ * available from fewfit_last_error().
+ *
+ * Method (arXiv 2507.15277, "A Few Fit Most"):
+ *   - a GEMM kernel whose tuning parameters are compile-time constants is
+ *     compiled ahead of time into a family of code variants (Sec. III-A,
+ *     Sec. III-B: runtime recompilation costs far more than a run, and
+ *     precompiling the whole space is too large);
+ *   - PortabilityTune selects a small set kappa of variants that is best by
+ *     a summary metric over a set of inputs (Sec. IV-B), scored by the
+ *     library cost function of Eq. 1 (Sec. IV-D-1);
+ *   - at run time one member of kappa is picked per input (Fig. 1, online
+ *     inference).
+ *
+ * All matrices are row-major FP32 with no transposes:
+ *   A is M x K with row stride lda >= max(1,K),
+ *   B is K x N with row stride ldb >= max(1,N),
+ *   C is M x N with row stride ldc >= max(1,N).
+ * Sizes M, N, K must fit in int32 (else FF_ERR_TOO_LARGE).
+ */
+#ifndef FEWFIT_H
+#define FEWFIT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Status codes.  -1 .. -11 name the invalid argument of sgemm() by
+ * position, in the manner of reference BLAS xerbla. */
+#define FF_OK 0
+#define FF_ERR_M (-1)          /* M < 0 */
+#define FF_ERR_N (-2)          /* N < 0 */
+#define FF_ERR_K (-3)          /* K < 0 */
+#define FF_ERR_A (-5)          /* A == NULL while A must be read */
+#define FF_ERR_LDA (-6)        /* lda < max(1,K) */
+#define FF_ERR_B (-7)          /* B == NULL while B must be read */
+#define FF_ERR_LDB (-8)        /* ldb < max(1,N) */
+#define FF_ERR_C (-10)         /* C == NULL while M*N > 0 */
+#define FF_ERR_LDC (-11)       /* ldc < max(1,N) */
+#define FF_ERR_NO_SET (-100)   /* no variant set loaded */
+#define FF_ERR_VARIANT (-101)  /* unknown variant id */
+#define FF_ERR_PARSE (-102)    /* malformed set file or manifest */
+#define FF_ERR_ARCH (-103)     /* set or code object built for another GPU */
+#define FF_ERR_HIP (-104)      /* a HIP runtime call failed */
+#define FF_ERR_IO (-105)       /* file missing or unreadable */
+#define FF_ERR_TOO_LARGE (-106)/* M, N or K above INT32_MAX */
+#define FF_ERR_ARG (-107)      /* other invalid argument (tuning ABI) */
+
+/* ---------------------------------------------------------------------
+ * Hot path
+ * ------------------------------------------------------------------- */
+
+/*
+ * C <- alpha * A * B + beta * C   (SGEMM; the operation the paper tunes,
+ * title and Sec. V).
+ *
+ * Dispatches to the member of the loaded variant set that variant_select()
+ * names for (M, N, K) and launches it on `stream`.  Asynchronous: returns
+ * after the launch is enqueued; kernel faults surface at the caller's next
+ * synchronisation.  Allocates nothing.
+ *
+ * Reference-BLAS semantics:
+ *   - M == 0 or N == 0, or ((alpha == 0 or K == 0) and beta == 1): returns
+ *     without touching C;
+ *   - alpha == 0 or K == 0: A and B are not read, C <- beta * C;
+ *   - beta == 0: C is not read (NaN or Inf in C does not propagate).
+ * Arguments are validated in order before any HIP call; the first invalid
+ * one is reported (FF_ERR_M ... FF_ERR_LDC).  Returns FF_ERR_NO_SET when no
+ * set is loaded and the call would launch a GEMM kernel.
+ *
+ * Each variant is deterministic: the same inputs give bitwise the same C.
+ * Different variants may round differently.  The result of every variant
+ * satisfies |C - C_exact| <= 4*K*2^-24*|alpha|*(|A||B|) elementwise, plus
+ * 2*2^-24*(|alpha*A*B| + |beta*C|) when the epilogue rounds.
+ */
+int sgemm(int64_t M, int64_t N, int64_t K, float alpha,
+          const float *A, int64_t lda, const float *B, int64_t ldb,
+          float beta, float *C, int64_t ldc, void *stream);
+
+/*
+ * Load a variant set file (the output of portability tuning, Sec. IV-B):
+ * the k member variants, their parameters, the GPU architecture they were
+ * built for, and the dispatch table of training shapes.  Only the k code
+ * objects of the set are loaded (Sec. III-B-3: pre-selection keeps the
+ * number of shipped variants small).  Replaces any previously loaded set.
+ * Not safe to call concurrently with sgemm() on another thread.
+ * Returns k on success; FF_ERR_IO, FF_ERR_PARSE, FF_ERR_ARCH, FF_ERR_HIP.
+ */
+int variant_set_load(const char *path);
+
+/*
+ * Variant id that sgemm() would run for (M, N, K) under the loaded set.
+ * Fig. 1 leaves the online picker open and Sec. V-I names unseen inputs as
+ * a limitation; the rule used here: the winner (within the set) of the
+ * training shape nearest to (M, N, K) in L1 distance over
+ * (log2 M, log2 N, log2 K), sizes below 1 counted as 1, ties to the
+ * training shape listed first.  Returns the id (>= 0), FF_ERR_NO_SET, or an
+ * argument error for negative sizes.
+ */
+int variant_select(int64_t M, int64_t N, int64_t K);
+
+/* Text of the calling thread's most recent error ("" if none). */
+const char *fewfit_last_error(void);
+
+/* ---------------------------------------------------------------------
+ * Tuning ABI: variant inspection, timing and screening (Sec. V-C)
+ * ------------------------------------------------------------------- */
+
+/*
+ * Load every variant listed in <dir>/manifest.txt (one descriptor line per
+ * variant, code object <dir>/<name>.co).  Returns the number of variants
+ * loaded; FF_ERR_IO, FF_ERR_PARSE, FF_ERR_HIP.
+ */
+int variant_manifest_load(const char *dir);
+
+/* Number of variants currently registered (manifest and set members). */
+int variant_count(void);
+
+/*
+ * Write variant `id`'s descriptor into buf (NUL-terminated, truncated to
+ * len): "<id> <name> <MWG> <NWG> <KWG> <MI> <WM> <WN> <SK> <VW> <LDS> <GM>".
+ * Returns the full length, or FF_ERR_VARIANT.
+ */
+int variant_info(int id, char *buf, size_t len);
+
+/* sgemm() with an explicit variant instead of dispatch; same semantics. */
+int sgemm_variant(int id, int64_t M, int64_t N, int64_t K, float alpha,
+                  const float *A, int64_t lda, const float *B, int64_t ldb,
+                  float beta, float *C, int64_t ldc, void *stream);
+
+/*
+ * Time variant `id` with HIP events on `stream`: `warmup` untimed launches,
+ * then `trials` trials of `reps` back-to-back launches each, bracketed by
+ * two events.  Writes the mean milliseconds per launch of each trial to
+ * trial_ms[0..trials).  C is overwritten (it is read as well when beta != 0).
+ * Synchronises the stream.  Returns 0, an sgemm() error or FF_ERR_HIP.
+ */
+int sgemm_time(int id, int64_t M, int64_t N, int64_t K, float alpha,
+               const float *A, int64_t lda, const float *B, int64_t ldb,
+               float beta, float *C, int64_t ldc, void *stream,
+               int warmup, int reps, int trials, float *trial_ms);
+
+/*
+ * Correctness screen (Sec. V-C: variants whose results do not match the
+ * reference kernels are dropped).  screen_reference() runs a plain
+ * one-thread-per-element GPU kernel that forms, in FP64,
+ *   ref[i][j] = alpha * sum_k A[i][k] B[k][j] + beta * C0[i][j]
+ *   tol[i][j] = 4*K*2^-24*|alpha|*sum_k |A[i][k]||B[k][j]|
+ *               (+ 2*2^-24*(|alpha*sum_k A B| + |beta*C0|) if alpha != 1 or beta != 0)
+ * into caller-owned device arrays ref and tol (M*N doubles each, dense
+ * row-major).  screen_compare() counts the elements of C (row stride ldc)
+ * with |C - ref| > tol or non-finite C, and the largest |C - ref| / tol.
+ * Both synchronise the stream.  Returns 0, FF_ERR_ARG or FF_ERR_HIP.
+ */
+int screen_reference(int64_t M, int64_t N, int64_t K, float alpha,
+                     const float *A, int64_t lda, const float *B, int64_t ldb,
+                     float beta, const float *C0, int64_t ldc0,
+                     double *ref, double *tol, void *stream);
+int screen_compare(int64_t M, int64_t N, const float *C, int64_t ldc,
+                   const double *ref, const double *tol,
+                   int64_t *nbad, double *max_ratio, void *stream);
+
+/* ---------------------------------------------------------------------
+ * Portability tuning on an execution-time table (host only, Sec. IV, V-C)
+ *
+ * A table is a dense row-major nv x ns array of doubles: t[v*ns + s] is the
+ * time of variant v on shape s; +inf marks a failed or missing entry.
+ * ------------------------------------------------------------------- */
+
+/*
+ * Post-processing pass (Sec. V-C; Table VI columns): per shape the best and
+ * worst finite time and the lowest variant index attaining the best
+ * (-1 if none); per entry slowdown = t / best and speedup = worst / t
+ * (inf and 0 for failed entries).  Output arrays: best, worst, best_id of
+ * length ns; slowdown, speedup of length nv*ns (either may be NULL).
+ */
+int ptune_postprocess(int nv, int ns, const double *t, double *best, double *worst,
+                      int *best_id, double *slowdown, double *speedup);
+
+/*
+ * Library cost function, Eq. 1 (Sec. IV-D-1), with the minimum runtime over
+ * the selected set in the numerator: the geometric mean over the chosen
+ * shapes of min_{v in kappa} t[v][s] / best[s], where best[s] is the minimum
+ * over all nv variants.  `shapes` lists nsel shape indices (NULL: all).
+ * Writes the cost (>= 1; +inf if some shape has no finite member) to *cost.
+ */
+int ptune_cost(int nv, int ns, const double *t, int k, const int *kappa,
+               int nsel, const int *shapes, double *cost);
+
+/*
+ * PortabilityTune (Sec. IV-B, Sec. IV-C-1): a set of min(k, nv) variants
+ * minimising ptune_cost over the chosen shapes.
+ *   method 0: exhaustive over all subsets of the variants left after
+ *             dominance pruning (exact);
+ *   method 1: greedy construction followed by single-swap local search;
+ *   method -1: exhaustive if at most 2e8 subsets remain, else method 1.
+ * Writes the set (ascending ids) to kappa_out[0..min(k,nv)), the cost to
+ * *cost_out and the number of subsets scored to *evals_out (any of the
+ * last two may be NULL).  Returns the set size or FF_ERR_ARG.
+ */
+int ptune_select(int nv, int ns, const double *t, int nsel, const int *shapes,
+                 int k, int method, int *kappa_out, double *cost_out, int64_t *evals_out);
+
+/*
+ * For each of the nsel shapes, the member of kappa with the lowest time
+ * (ties to the lower id; -1 if none is finite): the dispatch table that a
+ * set file records for its training shapes.
+ */
+int ptune_assign(int nv, int ns, const double *t, int k, const int *kappa,
+                 int nsel, const int *shapes, int *winners);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FEWFIT_H */

@@ -1,0 +1,222 @@
+"""Thin ctypes binding of libfewfit.so (C ABI in include/fewfit.h).
+
+Argument marshalling only: every function forwards to the native entry point
+of the same name.  Matrices may be given as torch tensors (their device
+address is passed) or as raw integer addresses; ``stream`` defaults to
+torch's current HIP stream.  A negative status raises :class:`FewfitError`
+carrying the library's error text.  If the library has not been built the
+first call raises: there is no fallback implementation.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libfewfit.so")
+
+_lib = None
+
+FF_OK = 0
+FF_ERR_M, FF_ERR_N, FF_ERR_K = -1, -2, -3
+FF_ERR_A, FF_ERR_LDA, FF_ERR_B, FF_ERR_LDB, FF_ERR_C, FF_ERR_LDC = -5, -6, -7, -8, -10, -11
+FF_ERR_NO_SET, FF_ERR_VARIANT, FF_ERR_PARSE = -100, -101, -102
+FF_ERR_ARCH, FF_ERR_HIP, FF_ERR_IO, FF_ERR_TOO_LARGE, FF_ERR_ARG = -103, -104, -105, -106, -107
+
+EXPORTS = ("sgemm", "variant_set_load", "variant_select", "fewfit_last_error",
+           "variant_manifest_load", "variant_count", "variant_info", "sgemm_variant",
+           "sgemm_time", "screen_reference", "screen_compare", "ptune_postprocess",
+           "ptune_cost", "ptune_select", "ptune_assign")
+
+
+class FewfitError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"fewfit error {code}: {msg}")
+        self.code = code
+
+
+def lib():
+    """Load libfewfit.so (torch first, so both share one HIP runtime)."""
+    global _lib
+    if _lib is None:
+        import torch  # noqa: F401  (loads the HIP runtime the library binds to)
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(
+                f"{LIB_PATH} is missing: build it with `python -m paper_2507_15277_amd.build` "
+                "(there is no fallback implementation)")
+        L = ctypes.CDLL(LIB_PATH)
+        i64, f32, f64, vp, i32 = ctypes.c_int64, ctypes.c_float, ctypes.c_double, ctypes.c_void_p, ctypes.c_int
+        gemm_args = [i64, i64, i64, f32, vp, i64, vp, i64, f32, vp, i64, vp]
+        L.sgemm.argtypes = gemm_args
+        L.sgemm_variant.argtypes = [i32] + gemm_args
+        L.sgemm_time.argtypes = [i32] + gemm_args + [i32, i32, i32, vp]
+        L.variant_set_load.argtypes = [ctypes.c_char_p]
+        L.variant_manifest_load.argtypes = [ctypes.c_char_p]
+        L.variant_select.argtypes = [i64, i64, i64]
+        L.variant_count.argtypes = []
+        L.variant_info.argtypes = [i32, ctypes.c_char_p, ctypes.c_size_t]
+        L.fewfit_last_error.argtypes = []
+        L.fewfit_last_error.restype = ctypes.c_char_p
+        L.screen_reference.argtypes = [i64, i64, i64, f32, vp, i64, vp, i64, f32, vp, i64, vp, vp, vp]
+        L.screen_compare.argtypes = [i64, i64, vp, i64, vp, vp, vp, vp, vp]
+        L.ptune_postprocess.argtypes = [i32, i32, vp, vp, vp, vp, vp, vp]
+        L.ptune_cost.argtypes = [i32, i32, vp, i32, vp, i32, vp, vp]
+        L.ptune_select.argtypes = [i32, i32, vp, i32, vp, i32, i32, vp, vp, vp]
+        L.ptune_assign.argtypes = [i32, i32, vp, i32, vp, i32, vp, vp]
+        for name in EXPORTS:
+            if name != "fewfit_last_error":
+                getattr(L, name).restype = i32
+        _lib = L
+    return _lib
+
+
+def last_error() -> str:
+    return lib().fewfit_last_error().decode()
+
+
+def _check(rc):
+    if rc < 0:
+        raise FewfitError(rc, last_error())
+    return rc
+
+
+def _ptr(x):
+    if x is None:
+        return None
+    if isinstance(x, int):
+        return x
+    return x.data_ptr()
+
+
+def _stream(stream):
+    if stream is None:
+        import torch
+        return torch.cuda.current_stream().cuda_stream if torch.cuda.is_available() else None
+    if isinstance(stream, int):
+        return stream
+    return stream.cuda_stream
+
+
+# --- hot path ------------------------------------------------------------------
+
+def sgemm(M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, stream=None):
+    return _check(lib().sgemm(M, N, K, alpha, _ptr(A), lda, _ptr(B), ldb, beta, _ptr(C), ldc,
+                              _stream(stream)))
+
+
+def variant_set_load(path):
+    return _check(lib().variant_set_load(os.fsencode(path)))
+
+
+def variant_select(M, N, K):
+    return _check(lib().variant_select(M, N, K))
+
+
+# --- tuning ABI ----------------------------------------------------------------
+
+def variant_manifest_load(directory):
+    return _check(lib().variant_manifest_load(os.fsencode(directory)))
+
+
+def variant_count():
+    return _check(lib().variant_count())
+
+
+def variant_info(vid):
+    buf = ctypes.create_string_buffer(512)
+    _check(lib().variant_info(vid, buf, len(buf)))
+    return buf.value.decode()
+
+
+def sgemm_variant(vid, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, stream=None):
+    return _check(lib().sgemm_variant(vid, M, N, K, alpha, _ptr(A), lda, _ptr(B), ldb, beta,
+                                      _ptr(C), ldc, _stream(stream)))
+
+
+def sgemm_time(vid, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, stream=None,
+               warmup=3, reps=10, trials=5):
+    out = (ctypes.c_float * trials)()
+    _check(lib().sgemm_time(vid, M, N, K, alpha, _ptr(A), lda, _ptr(B), ldb, beta, _ptr(C), ldc,
+                            _stream(stream), warmup, reps, trials, out))
+    return list(out)
+
+
+def screen_reference(M, N, K, alpha, A, lda, B, ldb, beta, C0, ldc0, ref, tol, stream=None):
+    return _check(lib().screen_reference(M, N, K, alpha, _ptr(A), lda, _ptr(B), ldb, beta,
+                                         _ptr(C0), ldc0, _ptr(ref), _ptr(tol), _stream(stream)))
+
+
+def screen_compare(M, N, C, ldc, ref, tol, stream=None):
+    nbad = ctypes.c_int64(0)
+    ratio = ctypes.c_double(0.0)
+    _check(lib().screen_compare(M, N, _ptr(C), ldc, _ptr(ref), _ptr(tol), ctypes.byref(nbad),
+                                ctypes.byref(ratio), _stream(stream)))
+    return nbad.value, ratio.value
+
+
+# --- portability tuning (host) -------------------------------------------------
+
+def _table(t):
+    import numpy as np
+    t = np.ascontiguousarray(t, dtype=np.float64)
+    if t.ndim != 2:
+        raise ValueError("table must be 2-D (variants x shapes)")
+    return t
+
+
+def _shapes(shapes):
+    import numpy as np
+    if shapes is None:
+        return None, 0
+    s = np.ascontiguousarray(shapes, dtype=np.int32)
+    return s, s.size
+
+
+def ptune_postprocess(t):
+    import numpy as np
+    t = _table(t)
+    nv, ns = t.shape
+    best, worst = np.empty(ns), np.empty(ns)
+    best_id = np.empty(ns, np.int32)
+    slow, speed = np.empty((nv, ns)), np.empty((nv, ns))
+    _check(lib().ptune_postprocess(nv, ns, t.ctypes.data, best.ctypes.data, worst.ctypes.data,
+                                   best_id.ctypes.data, slow.ctypes.data, speed.ctypes.data))
+    return best, worst, best_id, slow, speed
+
+
+def ptune_cost(t, kappa, shapes=None):
+    import numpy as np
+    t = _table(t)
+    nv, ns = t.shape
+    k = np.ascontiguousarray(kappa, dtype=np.int32)
+    s, nsel = _shapes(shapes)
+    out = ctypes.c_double(0.0)
+    _check(lib().ptune_cost(nv, ns, t.ctypes.data, k.size, k.ctypes.data, nsel,
+                            None if s is None else s.ctypes.data, ctypes.byref(out)))
+    return out.value
+
+
+def ptune_select(t, k, shapes=None, method=-1):
+    import numpy as np
+    t = _table(t)
+    nv, ns = t.shape
+    s, nsel = _shapes(shapes)
+    kap = np.empty(k, np.int32)
+    cost = ctypes.c_double(0.0)
+    evals = ctypes.c_int64(0)
+    n = _check(lib().ptune_select(nv, ns, t.ctypes.data, nsel, None if s is None else s.ctypes.data,
+                                  k, method, kap.ctypes.data, ctypes.byref(cost), ctypes.byref(evals)))
+    return tuple(int(x) for x in kap[:n]), cost.value, evals.value
+
+
+def ptune_assign(t, kappa, shapes=None):
+    import numpy as np
+    t = _table(t)
+    nv, ns = t.shape
+    k = np.ascontiguousarray(kappa, dtype=np.int32)
+    s, nsel = _shapes(shapes)
+    n_out = ns if s is None else nsel
+    win = np.empty(n_out, np.int32)
+    _check(lib().ptune_assign(nv, ns, t.ctypes.data, k.size, k.ctypes.data, nsel,
+                              None if s is None else s.ctypes.data, win.ctypes.data))
+    return [int(x) for x in win]

@@ -1,0 +1,349 @@
+// Portability tuning on an execution-time table (host code of libfewfit).
+//
+// Sec. IV-B: PortabilityTune returns a set kappa of variants that is best by a
+// summary metric over a set of inputs.  Sec. IV-D-1, Eq. 1: the metric for a
+// library is the geometric mean, over inputs, of the runtime the set achieves
+// relative to the best known variant for that input.  The set performs like
+// its best member on each input (Fig. 1), so the numerator is the minimum
+// runtime over kappa.
+//
+// Work is done in log space: L[v][s] = log(t[v][s] / best[s]) >= 0, so the
+// cost of a set is exp(mean_s min_{v in kappa} L[v][s]); log is monotone, so
+// the minimising member per shape is the same as for runtimes.
+//
+// Search (Sec. IV-C-1): the paper notes exhaustive search over |K|^|kappa|
+// combinations becomes intractable beyond |kappa| = 2 for 1,343 variants.
+// Two things keep it exact here for k <= 4 on a few hundred variants:
+//   * dominance pruning: a variant that is no faster than some other variant
+//     on every selected shape can be replaced by it in any set without raising
+//     the cost, so it is dropped (keeping the lower id among equals);
+//   * a depth-first walk over unordered subsets with running per-shape minima.
+// For larger k a greedy construction is refined by single swaps until no
+// swap lowers the cost (a local optimum).
+
+#include <algorithm>
+#include <cmath>
+#include <cstdint>
+#include <limits>
+#include <vector>
+
+#include "../../include/fewfit.h"
+
+#define FF_EXPORT extern "C" __attribute__((visibility("default")))
+
+namespace {
+
+const double kInf = std::numeric_limits<double>::infinity();
+
+bool finite_pos(double x) { return std::isfinite(x) && x > 0.0; }
+
+// Per-shape best over all variants (the paper's per-input "Oracle").
+void column_best(int nv, int ns, const double* t, std::vector<double>& best, std::vector<int>& best_id)
+{
+    best.assign(ns, kInf);
+    best_id.assign(ns, -1);
+    for (int s = 0; s < ns; ++s)
+        for (int v = 0; v < nv; ++v) {
+            const double x = t[(int64_t)v * ns + s];
+            if (finite_pos(x) && x < best[s]) {
+                best[s] = x;
+                best_id[s] = v;
+            }
+        }
+}
+
+struct LogTable {
+    int nv = 0, nsel = 0;
+    std::vector<double> L;  // nv x nsel, +inf for failed entries
+    bool ok = true;         // every selected shape has some finite entry
+    double at(int v, int j) const { return L[(size_t)v * nsel + j]; }
+};
+
+LogTable make_log_table(int nv, int ns, const double* t, const std::vector<int>& sel)
+{
+    std::vector<double> best;
+    std::vector<int> bid;
+    column_best(nv, ns, t, best, bid);
+    LogTable lt;
+    lt.nv = nv;
+    lt.nsel = (int)sel.size();
+    lt.L.assign((size_t)nv * lt.nsel, kInf);
+    for (int j = 0; j < lt.nsel; ++j) {
+        const int s = sel[j];
+        if (bid[s] < 0) lt.ok = false;
+        for (int v = 0; v < nv; ++v) {
+            const double x = t[(int64_t)v * ns + s];
+            if (finite_pos(x) && bid[s] >= 0) lt.L[(size_t)v * lt.nsel + j] = std::log(x / best[s]);
+        }
+    }
+    return lt;
+}
+
+double set_logsum(const LogTable& lt, const int* kappa, int k)
+{
+    double sum = 0.0;
+    for (int j = 0; j < lt.nsel; ++j) {
+        double m = kInf;
+        for (int i = 0; i < k; ++i) m = std::min(m, lt.at(kappa[i], j));
+        if (m == kInf) return kInf;
+        sum += m;
+    }
+    return sum;
+}
+
+double cost_of(const LogTable& lt, double logsum)
+{
+    return logsum == kInf ? kInf : std::exp(logsum / lt.nsel);
+}
+
+bool selection(int ns, int nsel, const int* shapes, std::vector<int>& sel)
+{
+    sel.clear();
+    if (shapes == nullptr) {
+        for (int s = 0; s < ns; ++s) sel.push_back(s);
+    } else {
+        for (int j = 0; j < nsel; ++j) {
+            if (shapes[j] < 0 || shapes[j] >= ns) return false;
+            sel.push_back(shapes[j]);
+        }
+    }
+    return !sel.empty();
+}
+
+// Variants not dominated on the selected shapes, in ascending id order.
+std::vector<int> undominated(const LogTable& lt)
+{
+    std::vector<int> keep;
+    for (int v = 0; v < lt.nv; ++v) {
+        bool any_finite = false;
+        for (int j = 0; j < lt.nsel; ++j) any_finite |= (lt.at(v, j) != kInf);
+        if (!any_finite) continue;
+        bool dominated = false;
+        for (int u = 0; u < lt.nv && !dominated; ++u) {
+            if (u == v) continue;
+            bool le = true, lt_strict = false;
+            for (int j = 0; j < lt.nsel && le; ++j) {
+                const double a = lt.at(u, j), b = lt.at(v, j);
+                if (a > b) le = false;
+                else if (a < b) lt_strict = true;
+            }
+            // u dominates v if no worse anywhere and better somewhere, or
+            // identical everywhere with a lower id.
+            if (le && (lt_strict || u < v)) dominated = true;
+        }
+        if (!dominated) keep.push_back(v);
+    }
+    return keep;
+}
+
+struct Exhaustive {
+    const LogTable& lt;
+    const std::vector<int>& cand;
+    int k;
+    std::vector<int> cur, best_set;
+    double best_sum = kInf;
+    int64_t evals = 0;
+    std::vector<std::vector<double>> mins;  // running per-shape minima by depth
+
+    Exhaustive(const LogTable& l, const std::vector<int>& c, int kk) : lt(l), cand(c), k(kk)
+    {
+        mins.assign(k + 1, std::vector<double>(lt.nsel, kInf));
+        cur.resize(k);
+    }
+    void run(int depth, int start)
+    {
+        if (depth == k) {
+            ++evals;
+            double sum = 0.0;
+            for (int j = 0; j < lt.nsel; ++j) sum += mins[depth][j];
+            if (sum < best_sum) {
+                best_sum = sum;
+                best_set = cur;
+            }
+            return;
+        }
+        const int n = (int)cand.size();
+        for (int i = start; i <= n - (k - depth); ++i) {
+            const int v = cand[i];
+            cur[depth] = v;
+            const std::vector<double>& prev = mins[depth];
+            std::vector<double>& next = mins[depth + 1];
+            for (int j = 0; j < lt.nsel; ++j) next[j] = std::min(prev[j], lt.at(v, j));
+            run(depth + 1, i + 1);
+        }
+    }
+};
+
+int64_t n_choose_k_capped(int64_t n, int64_t k, int64_t cap)
+{
+    if (k < 0 || k > n) return 0;
+    k = std::min(k, n - k);
+    double r = 1.0;
+    for (int64_t i = 1; i <= k; ++i) {
+        r = r * (double)(n - k + i) / (double)i;
+        if (r > (double)cap) return cap + 1;
+    }
+    return (int64_t)std::llround(r);
+}
+
+// Greedy: add the member that lowers the cost most; then single swaps.
+std::vector<int> greedy_swap(const LogTable& lt, const std::vector<int>& cand, int k, int64_t& evals)
+{
+    std::vector<int> set;
+    std::vector<double> mins(lt.nsel, kInf);
+    auto sum_with = [&](const std::vector<double>& m, int v) {
+        double sum = 0.0;
+        for (int j = 0; j < lt.nsel; ++j) sum += std::min(m[j], lt.at(v, j));
+        return sum;
+    };
+    for (int step = 0; step < k; ++step) {
+        int bv = -1;
+        double bs = kInf;
+        bool have = false;
+        for (int v : cand) {
+            if (std::find(set.begin(), set.end(), v) != set.end()) continue;
+            const double s = sum_with(mins, v);
+            ++evals;
+            if (!have || s < bs) {
+                have = true;
+                bs = s;
+                bv = v;
+            }
+        }
+        if (bv < 0) break;
+        set.push_back(bv);
+        for (int j = 0; j < lt.nsel; ++j) mins[j] = std::min(mins[j], lt.at(bv, j));
+    }
+    double cur = set_logsum(lt, set.data(), (int)set.size());
+    bool improved = true;
+    while (improved) {
+        improved = false;
+        for (size_t p = 0; p < set.size() && !improved; ++p) {
+            for (int v : cand) {
+                if (std::find(set.begin(), set.end(), v) != set.end()) continue;
+                std::vector<int> trial = set;
+                trial[p] = v;
+                const double s = set_logsum(lt, trial.data(), (int)trial.size());
+                ++evals;
+                if (s < cur - 1e-12 * std::max(1.0, std::fabs(cur))) {
+                    set = trial;
+                    cur = s;
+                    improved = true;
+                    break;
+                }
+            }
+        }
+    }
+    return set;
+}
+
+}  // namespace
+
+FF_EXPORT int ptune_postprocess(int nv, int ns, const double* t, double* best, double* worst, int* best_id,
+                                double* slowdown, double* speedup)
+{
+    if (nv < 0 || ns < 0 || (nv * ns > 0 && t == nullptr) || (ns > 0 && (!best || !worst || !best_id)))
+        return FF_ERR_ARG;
+    std::vector<double> b;
+    std::vector<int> bid;
+    column_best(nv, ns, t, b, bid);
+    for (int s = 0; s < ns; ++s) {
+        double w = -kInf;
+        for (int v = 0; v < nv; ++v) {
+            const double x = t[(int64_t)v * ns + s];
+            if (finite_pos(x)) w = std::max(w, x);
+        }
+        best[s] = b[s];
+        best_id[s] = bid[s];
+        worst[s] = bid[s] >= 0 ? w : kInf;
+    }
+    for (int v = 0; v < nv; ++v)
+        for (int s = 0; s < ns; ++s) {
+            const int64_t i = (int64_t)v * ns + s;
+            const double x = t[i];
+            const bool ok = finite_pos(x) && bid[s] >= 0;
+            if (slowdown) slowdown[i] = ok ? x / b[s] : kInf;
+            if (speedup) speedup[i] = ok ? worst[s] / x : 0.0;
+        }
+    return FF_OK;
+}
+
+FF_EXPORT int ptune_cost(int nv, int ns, const double* t, int k, const int* kappa, int nsel, const int* shapes,
+                         double* cost)
+{
+    std::vector<int> sel;
+    if (nv <= 0 || ns <= 0 || t == nullptr || k < 1 || kappa == nullptr || cost == nullptr ||
+        !selection(ns, nsel, shapes, sel))
+        return FF_ERR_ARG;
+    for (int i = 0; i < k; ++i)
+        if (kappa[i] < 0 || kappa[i] >= nv) return FF_ERR_ARG;
+    const LogTable lt = make_log_table(nv, ns, t, sel);
+    *cost = lt.ok ? cost_of(lt, set_logsum(lt, kappa, k)) : kInf;
+    return FF_OK;
+}
+
+FF_EXPORT int ptune_select(int nv, int ns, const double* t, int nsel, const int* shapes, int k, int method,
+                           int* kappa_out, double* cost_out, int64_t* evals_out)
+{
+    std::vector<int> sel;
+    if (nv <= 0 || ns <= 0 || t == nullptr || k < 1 || kappa_out == nullptr || method < -1 || method > 1 ||
+        !selection(ns, nsel, shapes, sel))
+        return FF_ERR_ARG;
+    const int kk = std::min(k, nv);
+    const LogTable lt = make_log_table(nv, ns, t, sel);
+    std::vector<int> cand = undominated(lt);
+    int64_t evals = 0;
+    std::vector<int> result;
+    if ((int)cand.size() <= kk) {
+        // Every undominated variant fits; fill up with the lowest other ids.
+        result = cand;
+        for (int v = 0; v < nv && (int)result.size() < kk; ++v)
+            if (std::find(result.begin(), result.end(), v) == result.end()) result.push_back(v);
+        evals = 1;
+    } else {
+        const int64_t cap = 200000000;
+        const bool exhaustive =
+            method == 0 || (method == -1 && n_choose_k_capped((int64_t)cand.size(), kk, cap) <= cap);
+        if (exhaustive) {
+            Exhaustive ex(lt, cand, kk);
+            ex.run(0, 0);
+            result = ex.best_set.empty() ? std::vector<int>(cand.begin(), cand.begin() + kk) : ex.best_set;
+            evals = ex.evals;
+        } else {
+            result = greedy_swap(lt, cand, kk, evals);
+            for (int v = 0; v < nv && (int)result.size() < kk; ++v)
+                if (std::find(result.begin(), result.end(), v) == result.end()) result.push_back(v);
+        }
+    }
+    std::sort(result.begin(), result.end());
+    for (int i = 0; i < kk; ++i) kappa_out[i] = result[i];
+    if (cost_out) *cost_out = lt.ok ? cost_of(lt, set_logsum(lt, result.data(), kk)) : kInf;
+    if (evals_out) *evals_out = evals;
+    return kk;
+}
+
+FF_EXPORT int ptune_assign(int nv, int ns, const double* t, int k, const int* kappa, int nsel, const int* shapes,
+                           int* winners)
+{
+    std::vector<int> sel;
+    if (nv <= 0 || ns <= 0 || t == nullptr || k < 1 || kappa == nullptr || winners == nullptr ||
+        !selection(ns, nsel, shapes, sel))
+        return FF_ERR_ARG;
+    std::vector<int> members(kappa, kappa + k);
+    for (int v : members)
+        if (v < 0 || v >= nv) return FF_ERR_ARG;
+    std::sort(members.begin(), members.end());
+    for (size_t j = 0; j < sel.size(); ++j) {
+        int bv = -1;
+        double bt = kInf;
+        for (int v : members) {
+            const double x = t[(int64_t)v * ns + sel[j]];
+            if (finite_pos(x) && x < bt) {
+                bt = x;
+                bv = v;
+            }
+        }
+        winners[j] = bv;
+    }
+    return FF_OK;
+}

@@ -1,0 +1,596 @@
+// libfewfit runtime: variant registry, variant-set files, dispatch, launch,
+// timing and the correctness screen.  C ABI declared in include/fewfit.h.
+//
+// Variants are separate code objects (one per parameter configuration, built
+// ahead of time from sgemm_variant.hip) loaded with hipModuleLoad; only the
+// members of the active set need to be loaded for sgemm() (Sec. III-B: the
+// full variant space is too large to precompile and ship, so a few are
+// pre-selected).
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <array>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <fstream>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <sstream>
+#include <string>
+#include <vector>
+
+#include "../../include/fewfit.h"
+
+#define FF_EXPORT extern "C" __attribute__((visibility("default")))
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char* fmt, ...)
+{
+    char buf[1024];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+int hip_fail(hipError_t e, const char* what)
+{
+    return fail(FF_ERR_HIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+// ---------------------------------------------------------------------------
+// Variant descriptors and registry
+
+struct Variant {
+    int id = -1;
+    std::string name;
+    int mwg = 0, nwg = 0, kwg = 0, mi = 0, wm = 0, wn = 0, sk = 0, vw = 0, lds = 0, gm = 0;
+    hipModule_t mod = nullptr;
+    hipFunction_t fvec = nullptr;  // VW-wide loads
+    hipFunction_t fsca = nullptr;  // scalar loads
+    int threads() const { return 64 * wm * wn * sk; }
+};
+
+// "<id> <name> MWG NWG KWG MI WM WN SK VW LDS GM"
+bool parse_descriptor(std::istringstream& is, Variant& v)
+{
+    if (!(is >> v.id >> v.name >> v.mwg >> v.nwg >> v.kwg >> v.mi >> v.wm >> v.wn >> v.sk >> v.vw >> v.lds >> v.gm))
+        return false;
+    if (v.id < 0 || v.mwg <= 0 || v.nwg <= 0 || v.kwg <= 0 || (v.mi != 16 && v.mi != 32) || v.wm <= 0 ||
+        v.wn <= 0 || v.sk <= 0 || (v.vw != 1 && v.vw != 2 && v.vw != 4) || (v.lds != 0 && v.lds != 1) ||
+        v.gm <= 0 || v.threads() > 1024)
+        return false;
+    for (char c : v.name)
+        if (!(isalnum((unsigned char)c) || c == '_')) return false;
+    return true;
+}
+
+struct VarSet {
+    std::vector<int> ids;                        // members
+    std::vector<std::array<int64_t, 3>> shapes;  // training shapes, file order
+    std::vector<std::array<double, 3>> lg;       // their log2 sizes
+    std::vector<int> winners;                    // member chosen per training shape
+};
+
+std::mutex g_mu;
+std::map<int, std::shared_ptr<Variant>> g_variants;
+std::shared_ptr<const VarSet> g_set;
+
+int load_code_object(Variant& v, const std::string& path)
+{
+    {
+        std::ifstream f(path, std::ios::binary);
+        if (!f) return fail(FF_ERR_IO, "cannot open code object %s", path.c_str());
+    }
+    hipModule_t mod = nullptr;
+    hipError_t e = hipModuleLoad(&mod, path.c_str());
+    if (e != hipSuccess) return hip_fail(e, ("hipModuleLoad " + path).c_str());
+    hipFunction_t fv = nullptr, fs = nullptr;
+    e = hipModuleGetFunction(&fv, mod, v.name.c_str());
+    if (e == hipSuccess) e = hipModuleGetFunction(&fs, mod, (v.name + "_v1").c_str());
+    if (e != hipSuccess) {
+        hipModuleUnload(mod);
+        return hip_fail(e, ("hipModuleGetFunction " + v.name).c_str());
+    }
+    v.mod = mod;
+    v.fvec = fv;
+    v.fsca = fs;
+    return FF_OK;
+}
+
+// Register a variant, loading its code object unless an identical
+// descriptor is already loaded under the same id.
+int register_variant(const Variant& d, const std::string& dir)
+{
+    auto it = g_variants.find(d.id);
+    if (it != g_variants.end()) {
+        const Variant& o = *it->second;
+        if (o.name == d.name) return FF_OK;
+        return fail(FF_ERR_PARSE, "variant id %d already registered as %s, not %s", d.id, o.name.c_str(),
+                    d.name.c_str());
+    }
+    auto v = std::make_shared<Variant>(d);
+    int rc = load_code_object(*v, dir + "/" + d.name + ".co");
+    if (rc != FF_OK) return rc;
+    g_variants[d.id] = v;
+    return FF_OK;
+}
+
+std::string dirname_of(const std::string& path)
+{
+    size_t p = path.find_last_of('/');
+    return p == std::string::npos ? std::string(".") : path.substr(0, p);
+}
+
+int device_arch(std::string& arch)
+{
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    hipDeviceProp_t prop;
+    e = hipGetDeviceProperties(&prop, dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDeviceProperties");
+    arch = prop.gcnArchName;
+    size_t colon = arch.find(':');
+    if (colon != std::string::npos) arch = arch.substr(0, colon);
+    return FF_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Argument validation shared by sgemm() and sgemm_variant(): reference-BLAS
+// order, before any HIP call.
+
+int validate(int64_t M, int64_t N, int64_t K, float alpha, const float* A, int64_t lda, const float* B,
+             int64_t ldb, float beta, const float* C, int64_t ldc)
+{
+    (void)beta;
+    if (M < 0) return fail(FF_ERR_M, "sgemm: M=%lld < 0", (long long)M);
+    if (N < 0) return fail(FF_ERR_N, "sgemm: N=%lld < 0", (long long)N);
+    if (K < 0) return fail(FF_ERR_K, "sgemm: K=%lld < 0", (long long)K);
+    const bool reads_ab = (alpha != 0.0f) && K > 0 && M > 0 && N > 0;
+    if (reads_ab && A == nullptr) return fail(FF_ERR_A, "sgemm: A is NULL");
+    if (lda < std::max<int64_t>(1, K)) return fail(FF_ERR_LDA, "sgemm: lda=%lld < max(1,K)", (long long)lda);
+    if (reads_ab && B == nullptr) return fail(FF_ERR_B, "sgemm: B is NULL");
+    if (ldb < std::max<int64_t>(1, N)) return fail(FF_ERR_LDB, "sgemm: ldb=%lld < max(1,N)", (long long)ldb);
+    if (M > 0 && N > 0 && C == nullptr) return fail(FF_ERR_C, "sgemm: C is NULL");
+    if (ldc < std::max<int64_t>(1, N)) return fail(FF_ERR_LDC, "sgemm: ldc=%lld < max(1,N)", (long long)ldc);
+    if (M > INT32_MAX || N > INT32_MAX || K > INT32_MAX)
+        return fail(FF_ERR_TOO_LARGE, "sgemm: sizes must fit in int32");
+    return FF_OK;
+}
+
+// C <- beta * C (beta == 0 writes zeros without reading C).
+__global__ void ff_scale_c(int64_t M, int64_t N, float beta, float* C, int64_t ldc)
+{
+    const int64_t total = M * N;
+    for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
+         idx += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t i = idx / N, j = idx - i * N;
+        float* p = C + i * ldc + j;
+        *p = (beta == 0.0f) ? 0.0f : beta * *p;
+    }
+}
+
+int launch_scale(int64_t M, int64_t N, float beta, float* C, int64_t ldc, hipStream_t s)
+{
+    const int64_t total = M * N;
+    const int64_t blocks = std::min<int64_t>((total + 255) / 256, 65536);
+    hipLaunchKernelGGL(ff_scale_c, dim3((unsigned)blocks), dim3(256), 0, s, M, N, beta, C, ldc);
+    hipError_t e = hipGetLastError();
+    return e == hipSuccess ? FF_OK : hip_fail(e, "launch scale kernel");
+}
+
+bool aligned_for(const void* p, int vw) { return (reinterpret_cast<uintptr_t>(p) % (4u * vw)) == 0; }
+
+int launch_variant(const Variant& v, int64_t M, int64_t N, int64_t K, float alpha, const float* A,
+                   int64_t lda, const float* B, int64_t ldb, float beta, float* C, int64_t ldc, hipStream_t s)
+{
+    const int64_t nbm = (M + v.mwg - 1) / v.mwg, nbn = (N + v.nwg - 1) / v.nwg;
+    const int64_t nb = nbm * nbn;
+    if (nb > INT32_MAX) return fail(FF_ERR_TOO_LARGE, "sgemm: %lld tiles exceed the grid limit", (long long)nb);
+    // The vector-load kernel needs whole, aligned vectors along K (A rows)
+    // and N (B rows); otherwise the scalar-load kernel of the same variant.
+    const int w = v.vw;
+    const bool vec = w > 1 && K % w == 0 && N % w == 0 && lda % w == 0 && ldb % w == 0 && aligned_for(A, w) &&
+                     aligned_for(B, w);
+    hipFunction_t f = vec ? v.fvec : v.fsca;
+    int Mi = (int)M, Ni = (int)N, Ki = (int)K;
+    long la = (long)lda, lb = (long)ldb, lc = (long)ldc;
+    void* args[] = {&Mi, &Ni, &Ki, &alpha, (void*)&A, &la, (void*)&B, &lb, &beta, (void*)&C, &lc};
+    hipError_t e = hipModuleLaunchKernel(f, (unsigned)nb, 1, 1, (unsigned)v.threads(), 1, 1, 0, s, args, nullptr);
+    return e == hipSuccess ? FF_OK : hip_fail(e, ("launch " + v.name).c_str());
+}
+
+// Shared body of sgemm() and sgemm_variant(); `v` may be null for the
+// dispatch path, in which case the set picks it.
+int gemm_common(const Variant* v, int64_t M, int64_t N, int64_t K, float alpha, const float* A, int64_t lda,
+                const float* B, int64_t ldb, float beta, float* C, int64_t ldc, void* stream)
+{
+    int rc = validate(M, N, K, alpha, A, lda, B, ldb, beta, C, ldc);
+    if (rc != FF_OK) return rc;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (M == 0 || N == 0) return FF_OK;
+    if (alpha == 0.0f || K == 0) {
+        if (beta == 1.0f) return FF_OK;
+        return launch_scale(M, N, beta, C, ldc, s);
+    }
+    std::shared_ptr<Variant> hold;
+    if (v == nullptr) {
+        int id = variant_select(M, N, K);
+        if (id < 0) return id;
+        std::lock_guard<std::mutex> lk(g_mu);
+        auto it = g_variants.find(id);
+        if (it == g_variants.end()) return fail(FF_ERR_VARIANT, "variant %d not loaded", id);
+        hold = it->second;
+        v = hold.get();
+    }
+    return launch_variant(*v, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, s);
+}
+
+std::shared_ptr<Variant> find_variant(int id)
+{
+    std::lock_guard<std::mutex> lk(g_mu);
+    auto it = g_variants.find(id);
+    return it == g_variants.end() ? nullptr : it->second;
+}
+
+// ---------------------------------------------------------------------------
+// Correctness screen kernels: a plain FP64 reference, one thread per element.
+
+constexpr double kU32 = 1.0 / 16777216.0;  // 2^-24
+
+__global__ void ff_screen_ref(int64_t M, int64_t N, int64_t K, double alpha, const float* A, int64_t lda,
+                              const float* B, int64_t ldb, double beta, const float* C0, int64_t ldc0,
+                              double* ref, double* tol, int epi)
+{
+    const int64_t total = M * N;
+    for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
+         idx += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t i = idx / N, j = idx - i * N;
+        double s = 0.0, t = 0.0;
+        if (alpha != 0.0) {
+            for (int64_t k = 0; k < K; ++k) {
+                const double a = A[i * lda + k], b = B[k * ldb + j];
+                s += a * b;
+                t += fabs(a) * fabs(b);
+            }
+        }
+        double r = (alpha != 0.0 && K > 0) ? alpha * s : 0.0;
+        double c0 = 0.0;
+        if (beta != 0.0) {
+            c0 = beta * (double)C0[i * ldc0 + j];
+            r += c0;
+        }
+        double tl = 4.0 * (double)K * kU32 * fabs(alpha) * t;
+        if (epi) tl += 2.0 * kU32 * (fabs(alpha * s) + fabs(c0));
+        ref[idx] = r;
+        tol[idx] = tl;
+    }
+}
+
+constexpr int kCmpThreads = 256, kCmpBlocks = 1024;
+
+__global__ void __launch_bounds__(kCmpThreads)
+ff_screen_cmp(int64_t M, int64_t N, const float* C, int64_t ldc, const double* ref, const double* tol,
+              long long* bad_out, double* ratio_out)
+{
+    __shared__ long long sb[kCmpThreads];
+    __shared__ double sr[kCmpThreads];
+    long long bad = 0;
+    double mr = 0.0;
+    const int64_t total = M * N;
+    for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
+         idx += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t i = idx / N, j = idx - i * N;
+        const double c = C[i * ldc + j];
+        const double d = fabs(c - ref[idx]);
+        const double tl = tol[idx];
+        double ratio;
+        if (!isfinite(c)) ratio = INFINITY;
+        else if (tl > 0.0) ratio = d / tl;
+        else ratio = (d == 0.0) ? 0.0 : INFINITY;
+        if (!(d <= tl) || !isfinite(c)) ++bad;
+        mr = fmax(mr, ratio);
+    }
+    sb[threadIdx.x] = bad;
+    sr[threadIdx.x] = mr;
+    __syncthreads();
+    for (int w = kCmpThreads / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) {
+            sb[threadIdx.x] += sb[threadIdx.x + w];
+            sr[threadIdx.x] = fmax(sr[threadIdx.x], sr[threadIdx.x + w]);
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        bad_out[blockIdx.x] = sb[0];
+        ratio_out[blockIdx.x] = sr[0];
+    }
+}
+
+}  // namespace
+
+// ===========================================================================
+// Exported C ABI
+
+FF_EXPORT const char* fewfit_last_error(void) { return g_err.c_str(); }
+
+FF_EXPORT int variant_manifest_load(const char* dir)
+{
+    if (dir == nullptr) return fail(FF_ERR_ARG, "variant_manifest_load: dir is NULL");
+    const std::string d(dir);
+    std::ifstream f(d + "/manifest.txt");
+    if (!f) return fail(FF_ERR_IO, "cannot open %s/manifest.txt", dir);
+    std::vector<Variant> list;
+    std::string line;
+    int lineno = 0;
+    while (std::getline(f, line)) {
+        ++lineno;
+        if (line.empty() || line[0] == '#') continue;
+        std::istringstream is(line);
+        Variant v;
+        if (!parse_descriptor(is, v)) return fail(FF_ERR_PARSE, "manifest line %d: bad descriptor", lineno);
+        list.push_back(v);
+    }
+    std::lock_guard<std::mutex> lk(g_mu);
+    for (const Variant& v : list) {
+        int rc = register_variant(v, d);
+        if (rc != FF_OK) return rc;
+    }
+    return (int)list.size();
+}
+
+FF_EXPORT int variant_count(void)
+{
+    std::lock_guard<std::mutex> lk(g_mu);
+    return (int)g_variants.size();
+}
+
+FF_EXPORT int variant_info(int id, char* buf, size_t len)
+{
+    auto v = find_variant(id);
+    if (!v) return fail(FF_ERR_VARIANT, "variant %d not registered", id);
+    char tmp[512];
+    int n = snprintf(tmp, sizeof tmp, "%d %s %d %d %d %d %d %d %d %d %d %d", v->id, v->name.c_str(), v->mwg,
+                     v->nwg, v->kwg, v->mi, v->wm, v->wn, v->sk, v->vw, v->lds, v->gm);
+    if (buf && len > 0) {
+        size_t c = std::min(len - 1, (size_t)n);
+        memcpy(buf, tmp, c);
+        buf[c] = '\0';
+    }
+    return n;
+}
+
+// Set file format (text, '#' comments):
+//   fewfit-set 1
+//   arch <gfx name>
+//   codedir <dir>          code objects, relative to the set file's directory
+//   variant <descriptor>   k lines, descriptor as in the manifest
+//   rule <M> <N> <K> <id>  one line per training shape, id must be a member
+//   end
+FF_EXPORT int variant_set_load(const char* path)
+{
+    if (path == nullptr) return fail(FF_ERR_ARG, "variant_set_load: path is NULL");
+    std::ifstream f(path);
+    if (!f) return fail(FF_ERR_IO, "cannot open set file %s", path);
+    auto set = std::make_shared<VarSet>();
+    std::vector<Variant> members;
+    std::string arch, codedir, line;
+    bool header = false, ended = false;
+    int lineno = 0;
+    while (std::getline(f, line)) {
+        ++lineno;
+        size_t h = line.find('#');
+        if (h != std::string::npos) line = line.substr(0, h);
+        std::istringstream is(line);
+        std::string key;
+        if (!(is >> key)) continue;
+        if (ended) return fail(FF_ERR_PARSE, "%s:%d: text after 'end'", path, lineno);
+        if (!header) {
+            int ver = 0;
+            if (key != "fewfit-set" || !(is >> ver) || ver != 1)
+                return fail(FF_ERR_PARSE, "%s:%d: expected 'fewfit-set 1'", path, lineno);
+            header = true;
+            continue;
+        }
+        std::string extra;
+        if (key == "arch") {
+            if (!(is >> arch)) return fail(FF_ERR_PARSE, "%s:%d: arch needs a value", path, lineno);
+        } else if (key == "codedir") {
+            if (!(is >> codedir)) return fail(FF_ERR_PARSE, "%s:%d: codedir needs a value", path, lineno);
+        } else if (key == "variant") {
+            Variant v;
+            if (!parse_descriptor(is, v)) return fail(FF_ERR_PARSE, "%s:%d: bad variant descriptor", path, lineno);
+            for (const Variant& o : members)
+                if (o.id == v.id) return fail(FF_ERR_PARSE, "%s:%d: duplicate variant %d", path, lineno, v.id);
+            members.push_back(v);
+            set->ids.push_back(v.id);
+        } else if (key == "rule") {
+            long long m, n, k;
+            int id;
+            if (!(is >> m >> n >> k >> id) || m < 1 || n < 1 || k < 1)
+                return fail(FF_ERR_PARSE, "%s:%d: bad rule", path, lineno);
+            if (std::find(set->ids.begin(), set->ids.end(), id) == set->ids.end())
+                return fail(FF_ERR_PARSE, "%s:%d: rule names variant %d outside the set", path, lineno, id);
+            set->shapes.push_back({m, n, k});
+            set->lg.push_back({std::log2((double)m), std::log2((double)n), std::log2((double)k)});
+            set->winners.push_back(id);
+        } else if (key == "end") {
+            ended = true;
+        } else {
+            return fail(FF_ERR_PARSE, "%s:%d: unknown key '%s'", path, lineno, key.c_str());
+        }
+        if (key != "end" && (is >> extra)) return fail(FF_ERR_PARSE, "%s:%d: trailing text", path, lineno);
+    }
+    if (!header) return fail(FF_ERR_PARSE, "%s: empty set file", path);
+    if (!ended) return fail(FF_ERR_PARSE, "%s: missing 'end' (truncated file?)", path);
+    if (arch.empty() || codedir.empty() || members.empty() || set->shapes.empty())
+        return fail(FF_ERR_PARSE, "%s: needs arch, codedir, at least one variant and one rule", path);
+
+    std::string dev;
+    int rc = device_arch(dev);
+    if (rc != FF_OK) return rc;
+    if (dev != arch) return fail(FF_ERR_ARCH, "set built for %s, device is %s", arch.c_str(), dev.c_str());
+
+    const std::string dir = codedir[0] == '/' ? codedir : dirname_of(path) + "/" + codedir;
+    std::lock_guard<std::mutex> lk(g_mu);
+    for (const Variant& v : members) {
+        rc = register_variant(v, dir);
+        if (rc != FF_OK) return rc;
+    }
+    g_set = set;
+    return (int)set->ids.size();
+}
+
+FF_EXPORT int variant_select(int64_t M, int64_t N, int64_t K)
+{
+    if (M < 0) return fail(FF_ERR_M, "variant_select: M < 0");
+    if (N < 0) return fail(FF_ERR_N, "variant_select: N < 0");
+    if (K < 0) return fail(FF_ERR_K, "variant_select: K < 0");
+    std::shared_ptr<const VarSet> set;
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        set = g_set;
+    }
+    if (!set) return fail(FF_ERR_NO_SET, "no variant set loaded");
+    const double q[3] = {std::log2((double)std::max<int64_t>(1, M)), std::log2((double)std::max<int64_t>(1, N)),
+                         std::log2((double)std::max<int64_t>(1, K))};
+    size_t best = 0;
+    double bd = INFINITY;
+    for (size_t i = 0; i < set->lg.size(); ++i) {
+        const double d = std::fabs(q[0] - set->lg[i][0]) + std::fabs(q[1] - set->lg[i][1]) +
+                         std::fabs(q[2] - set->lg[i][2]);
+        if (d < bd) {
+            bd = d;
+            best = i;
+        }
+    }
+    return set->winners[best];
+}
+
+FF_EXPORT int sgemm(int64_t M, int64_t N, int64_t K, float alpha, const float* A, int64_t lda, const float* B,
+                    int64_t ldb, float beta, float* C, int64_t ldc, void* stream)
+{
+    return gemm_common(nullptr, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, stream);
+}
+
+FF_EXPORT int sgemm_variant(int id, int64_t M, int64_t N, int64_t K, float alpha, const float* A, int64_t lda,
+                            const float* B, int64_t ldb, float beta, float* C, int64_t ldc, void* stream)
+{
+    int rc = validate(M, N, K, alpha, A, lda, B, ldb, beta, C, ldc);
+    if (rc != FF_OK) return rc;
+    auto v = find_variant(id);
+    if (!v) return fail(FF_ERR_VARIANT, "variant %d not registered", id);
+    return gemm_common(v.get(), M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, stream);
+}
+
+FF_EXPORT int sgemm_time(int id, int64_t M, int64_t N, int64_t K, float alpha, const float* A, int64_t lda,
+                         const float* B, int64_t ldb, float beta, float* C, int64_t ldc, void* stream, int warmup,
+                         int reps, int trials, float* trial_ms)
+{
+    if (warmup < 0 || reps < 1 || trials < 1 || trial_ms == nullptr)
+        return fail(FF_ERR_ARG, "sgemm_time: need warmup >= 0, reps >= 1, trials >= 1, trial_ms");
+    int rc = validate(M, N, K, alpha, A, lda, B, ldb, beta, C, ldc);
+    if (rc != FF_OK) return rc;
+    auto v = find_variant(id);
+    if (!v) return fail(FF_ERR_VARIANT, "variant %d not registered", id);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    for (int i = 0; i < warmup; ++i) {
+        rc = gemm_common(v.get(), M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, stream);
+        if (rc != FF_OK) return rc;
+    }
+    hipEvent_t e0, e1;
+    hipError_t e = hipEventCreate(&e0);
+    if (e != hipSuccess) return hip_fail(e, "hipEventCreate");
+    e = hipEventCreate(&e1);
+    if (e != hipSuccess) {
+        hipEventDestroy(e0);
+        return hip_fail(e, "hipEventCreate");
+    }
+    rc = FF_OK;
+    for (int t = 0; t < trials && rc == FF_OK; ++t) {
+        e = hipEventRecord(e0, s);
+        if (e != hipSuccess) { rc = hip_fail(e, "hipEventRecord"); break; }
+        for (int r = 0; r < reps && rc == FF_OK; ++r)
+            rc = gemm_common(v.get(), M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, stream);
+        if (rc != FF_OK) break;
+        e = hipEventRecord(e1, s);
+        if (e == hipSuccess) e = hipEventSynchronize(e1);
+        float ms = 0.0f;
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+        if (e != hipSuccess) { rc = hip_fail(e, "timing events"); break; }
+        trial_ms[t] = ms / (float)reps;
+    }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    return rc;
+}
+
+FF_EXPORT int screen_reference(int64_t M, int64_t N, int64_t K, float alpha, const float* A, int64_t lda,
+                               const float* B, int64_t ldb, float beta, const float* C0, int64_t ldc0,
+                               double* ref, double* tol, void* stream)
+{
+    if (M < 0 || N < 0 || K < 0 || lda < std::max<int64_t>(1, K) || ldb < std::max<int64_t>(1, N) ||
+        (beta != 0.0f && (C0 == nullptr || ldc0 < std::max<int64_t>(1, N))) ||
+        (alpha != 0.0f && K > 0 && M > 0 && N > 0 && (A == nullptr || B == nullptr)) ||
+        (M * N > 0 && (ref == nullptr || tol == nullptr)))
+        return fail(FF_ERR_ARG, "screen_reference: invalid arguments");
+    if (M == 0 || N == 0) return FF_OK;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const int64_t blocks = std::min<int64_t>((M * N + 255) / 256, 1 << 20);
+    const int epi = (alpha != 1.0f || beta != 0.0f) ? 1 : 0;
+    hipLaunchKernelGGL(ff_screen_ref, dim3((unsigned)blocks), dim3(256), 0, s, M, N, K, (double)alpha, A, lda, B,
+                       ldb, (double)beta, C0, ldc0, ref, tol, epi);
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    return e == hipSuccess ? FF_OK : hip_fail(e, "screen_reference");
+}
+
+FF_EXPORT int screen_compare(int64_t M, int64_t N, const float* C, int64_t ldc, const double* ref,
+                             const double* tol, int64_t* nbad, double* max_ratio, void* stream)
+{
+    if (M < 0 || N < 0 || ldc < std::max<int64_t>(1, N) || nbad == nullptr || max_ratio == nullptr ||
+        (M * N > 0 && (C == nullptr || ref == nullptr || tol == nullptr)))
+        return fail(FF_ERR_ARG, "screen_compare: invalid arguments");
+    *nbad = 0;
+    *max_ratio = 0.0;
+    if (M == 0 || N == 0) return FF_OK;
+    static long long* d_bad = nullptr;
+    static double* d_ratio = nullptr;
+    static std::mutex mu;
+    std::lock_guard<std::mutex> lk(mu);
+    hipError_t e = hipSuccess;
+    if (d_bad == nullptr) {
+        e = hipMalloc(&d_bad, kCmpBlocks * sizeof(long long));
+        if (e == hipSuccess) e = hipMalloc(&d_ratio, kCmpBlocks * sizeof(double));
+        if (e != hipSuccess) return hip_fail(e, "screen_compare alloc");
+    }
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    hipLaunchKernelGGL(ff_screen_cmp, dim3(kCmpBlocks), dim3(kCmpThreads), 0, s, M, N, C, ldc, ref, tol, d_bad,
+                       d_ratio);
+    std::vector<long long> hb(kCmpBlocks);
+    std::vector<double> hr(kCmpBlocks);
+    e = hipGetLastError();
+    if (e == hipSuccess) e = hipMemcpyAsync(hb.data(), d_bad, kCmpBlocks * sizeof(long long), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(hr.data(), d_ratio, kCmpBlocks * sizeof(double), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_fail(e, "screen_compare");
+    long long b = 0;
+    double r = 0.0;
+    for (int i = 0; i < kCmpBlocks; ++i) {
+        b += hb[i];
+        r = std::max(r, hr[i]);
+    }
+    *nbad = b;
+    *max_ratio = r;
+    return FF_OK;
+}

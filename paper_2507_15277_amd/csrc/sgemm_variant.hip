@@ -1,0 +1,439 @@
+// Parameterised single-precision GEMM variant for gfx950 (CDNA4).
+//
+//   C = alpha * A * B + beta * C      A: M x K, B: K x N, C: M x N, row-major FP32
+//
+// The paper's premise (Sec. III-A, Sec. III-B) is a kernel whose tuning
+// parameters are compile-time constants, compiled ahead of time into a family
+// of code variants from which a few are kept.  This file is that kernel: it is
+// compiled once per parameter configuration (the FF_* macros below) into its
+// own code object, which the runtime loads on demand.
+//
+// Parameters (compile-time):
+//   FF_MWG, FF_NWG   work-group tile of C (rows x columns)
+//   FF_KWG           K extent of one pipeline stage (slab)
+//   FF_MI            MFMA block edge: 32 -> v_mfma_f32_32x32x2_f32,
+//                                      16 -> v_mfma_f32_16x16x4_f32
+//   FF_WM, FF_WN     wave grid over the tile (each wave owns a
+//                    (MWG/WM) x (NWG/WN) sub-tile of RM x RN MFMA blocks)
+//   FF_SK            intra-work-group split of each slab's K range over SK
+//                    groups of waves, reduced through LDS at the end
+//   FF_VW            global-load vector width in floats (1, 2, 4)
+//   FF_LDS           1: slabs staged through double-buffered LDS shared by all
+//                    waves; 0: each wave loads its own operands straight from
+//                    global memory into registers (no LDS, no barriers)
+//   FF_GM            tile-order group height (tiles of M per group)
+//   FF_NAME          kernel symbol; a second kernel FF_NAME##_v1 is the same
+//                    configuration with scalar loads, for operands whose
+//                    alignment or leading dimension rules out vector loads
+//
+// Operand roles inside the MFMA.  The MFMA computes D[i][j] += sum_k X[i][k]
+// Y[k][j] with X held one value per lane as X[lane%MI][lane/MI] and Y as
+// Y[lane/MI][lane%MI].  The kernel feeds X from B (i indexes columns n of C)
+// and Y from A (j indexes rows m of C), so that each lane's accumulator
+// holds one row of C and runs of four consecutive columns, which are stored
+// as 16-byte vectors.  Within one slab the k values are assigned to lanes as
+// k = kgroup_base + (lane/MI)*S + s for step s < S: both operands use the
+// same assignment, so every product A[m][k]B[k][n] is formed once, and each
+// lane reads S consecutive k values of its A row as wide LDS reads.
+//
+// Edges: loads outside the matrices are replaced by zeros and stores are
+// masked, so M, N and K are arbitrary.  The vector-load kernel requires
+// K % VW == 0, N % VW == 0, lda % VW == 0, ldb % VW == 0 and VW-aligned A
+// and B; the runtime launches the scalar kernel otherwise.  alpha == 0 and K == 0 never reach
+// this kernel (the runtime handles them without reading A and B).  beta == 0
+// never reads C.
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#ifndef FF_MWG
+#define FF_MWG 64
+#define FF_NWG 64
+#define FF_KWG 16
+#define FF_MI 32
+#define FF_WM 2
+#define FF_WN 2
+#define FF_SK 1
+#define FF_VW 4
+#define FF_LDS 1
+#define FF_GM 8
+#define FF_NAME sgemm_m64n64k16_i32_w2x2_s1_v4_l1
+#endif
+
+#define FF_CAT2(a, b) a##b
+#define FF_CAT(a, b) FF_CAT2(a, b)
+
+namespace {
+
+constexpr int MWG = FF_MWG, NWG = FF_NWG, KWG = FF_KWG, MI = FF_MI;
+constexpr int WM = FF_WM, WN = FF_WN, SK = FF_SK, VW = FF_VW, GM = FF_GM;
+constexpr bool USE_LDS = FF_LDS != 0;
+
+constexpr int MK = (MI == 32) ? 2 : 4;   // k per MFMA instruction
+constexpr int WTM = MWG / WM;            // wave sub-tile rows
+constexpr int WTN = NWG / WN;            // wave sub-tile columns
+constexpr int RM = WTM / MI;             // MFMA blocks per wave along M
+constexpr int RN = WTN / MI;             // MFMA blocks per wave along N
+constexpr int NWAVE = WM * WN * SK;
+constexpr int NT = 64 * NWAVE;           // threads per work-group
+constexpr int KG = KWG / SK;             // k per split group per slab
+constexpr int S = KG / MK;               // MFMA steps per split group per slab
+constexpr int ACC = MI * MI / 64;        // accumulator floats per lane per block
+constexpr int AV = (S % 4 == 0) ? 4 : ((S % 2 == 0) ? 2 : 1);  // A read width
+
+// LDS rows are padded by 4 floats: the A row stride (KWG+4) is an odd
+// multiple of 4 floats for KWG in {8,16,32}, so 16-byte reads of 8
+// consecutive rows fall in disjoint banks.
+constexpr int PA = 4, PB = 4;
+constexpr int LDA_S = KWG + PA;          // LDS row stride of the A slab [m][k]
+constexpr int LDB_S = NWG + PB;          // LDS row stride of the B slab [k][n]
+constexpr int STAGE_FLOATS = MWG * LDA_S + KWG * LDB_S;
+constexpr int RED_FLOATS = (SK - 1) * MWG * NWG;
+constexpr int LDS_FLOATS = USE_LDS ? (2 * STAGE_FLOATS > RED_FLOATS ? 2 * STAGE_FLOATS : RED_FLOATS)
+                                   : (RED_FLOATS > 0 ? RED_FLOATS : 1);
+
+static_assert(MI == 32 || MI == 16, "MFMA block edge must be 16 or 32");
+static_assert(MWG % (WM * MI) == 0 && NWG % (WN * MI) == 0, "tile must split into MFMA blocks");
+static_assert(KWG % (SK * MK) == 0, "slab must split over groups and MFMA k");
+static_assert(VW == 1 || VW == 2 || VW == 4, "vector width");
+static_assert(NT <= 1024, "work-group size");
+static_assert(KWG % 4 == 0 && NWG % 4 == 0, "LDS vector alignment");
+
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+
+template <int E> struct AccT;
+template <> struct AccT<16> { typedef f32x16 T; };
+template <> struct AccT<4> { typedef f32x4 T; };
+typedef typename AccT<ACC>::T acc_t;
+
+__device__ __forceinline__ f32x16 mfma(float x, float y, f32x16 c)
+{
+    return __builtin_amdgcn_mfma_f32_32x32x2f32(x, y, c, 0, 0, 0);
+}
+__device__ __forceinline__ f32x4 mfma(float x, float y, f32x4 c)
+{
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(x, y, c, 0, 0, 0);
+}
+
+template <int V> struct VecT { typedef float T __attribute__((ext_vector_type(V))); };
+template <> struct VecT<1> { typedef float T; };
+
+template <int V>
+__device__ __forceinline__ float vget(const typename VecT<V>::T& v, int e)
+{
+    if constexpr (V == 1) { (void)e; return v; } else { return v[e]; }
+}
+template <int V>
+__device__ __forceinline__ void vset(typename VecT<V>::T& v, int e, float x)
+{
+    if constexpr (V == 1) { (void)e; v = x; } else { v[e] = x; }
+}
+
+// Edge handling is branch-free: an invalid lane loads V floats from `safe`
+// (any readable address aligned for V) instead of p, and the value is
+// replaced by zeros only where it is consumed (zsel), so that the loads of
+// the next slab stay in flight while the current slab is computed.  Vector
+// kernels (V > 1) are launched only when K and N are multiples of V and rows
+// are V-aligned, so a vector never straddles the edge of a matrix.
+template <int V>
+__device__ __forceinline__ typename VecT<V>::T load_raw(const float* p, bool ok, const float* safe)
+{
+    return *reinterpret_cast<const typename VecT<V>::T*>(ok ? p : safe);
+}
+template <int V>
+__device__ __forceinline__ typename VecT<V>::T zsel(const typename VecT<V>::T& v, bool ok)
+{
+    return ok ? v : typename VecT<V>::T(0.0f);
+}
+
+// Work-group index -> (tile row, tile column).  Work-groups are handed to the
+// 8 XCDs round-robin; the first step renumbers them so that each XCD gets a
+// contiguous range of tiles, the second walks tiles in groups of GM tile rows
+// (column-major inside a group) so that neighbours share A rows and B
+// columns in the XCD's L2.
+__device__ __forceinline__ void tile_of(int bid, int nbm, int nbn, int& tm, int& tn)
+{
+    const int nb = nbm * nbn;
+    const int q = nb >> 3, r = nb & 7;
+    const int x = bid & 7, i = bid >> 3;
+    const int lin = (x < r) ? x * (q + 1) + i : r * (q + 1) + (x - r) * q + i;
+    const int width = GM * nbn;
+    const int grp = lin / width;
+    const int first = grp * GM;
+    const int gsz = min(nbm - first, GM);
+    const int w = lin - grp * width;
+    tm = first + w % gsz;
+    tn = w / gsz;
+}
+
+template <int V>
+__device__ __forceinline__ void gemm_body(int M, int N, int K, float alpha,
+                                          const float* __restrict__ A, long lda,
+                                          const float* __restrict__ B, long ldb,
+                                          float beta, float* __restrict__ C, long ldc,
+                                          float* smem)
+{
+    const int nbm = (M + MWG - 1) / MWG, nbn = (N + NWG - 1) / NWG;
+    int tm, tn;
+    tile_of(blockIdx.x, nbm, nbn, tm, tn);
+    const int m0 = tm * MWG, n0 = tn * NWG;
+
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wid = tid >> 6;
+    const int grp = wid / (WM * WN);      // split-K group
+    const int wq = wid % (WM * WN);
+    const int wm = wq / WN, wn = wq % WN;
+    const int lr = lane % MI;             // lane's row within an MFMA block
+    const int lh = lane / MI;             // lane's k group
+    const int kg0 = grp * KG + lh * S;    // first k of this lane within a slab
+
+    acc_t acc[RM][RN];
+#pragma unroll
+    for (int i = 0; i < RM; ++i)
+#pragma unroll
+        for (int j = 0; j < RN; ++j)
+            acc[i][j] = acc_t{};
+
+    const int nkt = (K + KWG - 1) / KWG;
+
+    if constexpr (USE_LDS) {
+        // ---- cooperative slab loads: global -> registers -> LDS ----------
+        constexpr int AVEC_ROW = KWG / V;
+        constexpr int NVA = MWG * AVEC_ROW;
+        constexpr int LA = (NVA + NT - 1) / NT;
+        constexpr int BVEC_ROW = NWG / V;
+        constexpr int NVB = KWG * BVEC_ROW;
+        constexpr int LB = (NVB + NT - 1) / NT;
+        typedef typename VecT<V>::T vt;
+        vt ra[LA], rb[LB];
+        bool oka[LA], okb[LB];
+
+        float* sA0 = smem;
+        float* sB0 = smem + MWG * LDA_S;
+
+        auto gload = [&](int kt) {
+            const int kb = kt * KWG;
+#pragma unroll
+            for (int i = 0; i < LA; ++i) {
+                const int v = tid + i * NT;
+                if (NVA % NT == 0 || v < NVA) {
+                    const int row = v / AVEC_ROW, kk = (v % AVEC_ROW) * V;
+                    const int m = m0 + row, k = kb + kk;
+                    oka[i] = (m < M) && (k < K);
+                    ra[i] = load_raw<V>(A + (long)m * lda + k, oka[i], A);
+                }
+            }
+#pragma unroll
+            for (int i = 0; i < LB; ++i) {
+                const int v = tid + i * NT;
+                if (NVB % NT == 0 || v < NVB) {
+                    const int row = v / BVEC_ROW, nn = (v % BVEC_ROW) * V;
+                    const int k = kb + row, n = n0 + nn;
+                    okb[i] = (k < K) && (n < N);
+                    rb[i] = load_raw<V>(B + (long)k * ldb + n, okb[i], B);
+                }
+            }
+        };
+        auto sstore = [&](int st) {
+            float* sA = sA0 + st * STAGE_FLOATS;
+            float* sB = sB0 + st * STAGE_FLOATS;
+#pragma unroll
+            for (int i = 0; i < LA; ++i) {
+                const int v = tid + i * NT;
+                if (NVA % NT == 0 || v < NVA) {
+                    const int row = v / AVEC_ROW, kk = (v % AVEC_ROW) * V;
+                    *reinterpret_cast<vt*>(sA + row * LDA_S + kk) = zsel<V>(ra[i], oka[i]);
+                }
+            }
+#pragma unroll
+            for (int i = 0; i < LB; ++i) {
+                const int v = tid + i * NT;
+                if (NVB % NT == 0 || v < NVB) {
+                    const int row = v / BVEC_ROW, nn = (v % BVEC_ROW) * V;
+                    *reinterpret_cast<vt*>(sB + row * LDB_S + nn) = zsel<V>(rb[i], okb[i]);
+                }
+            }
+        };
+
+        gload(0);
+        sstore(0);
+        __syncthreads();
+
+        const int arow0 = (wm * WTM + lr) * LDA_S + kg0;
+        const int bcol0 = wn * WTN + lr;
+        for (int kt = 0; kt < nkt; ++kt) {
+            const int st = kt & 1;
+            if (kt + 1 < nkt) gload(kt + 1);
+            const float* sA = sA0 + st * STAGE_FLOATS;
+            const float* sB = sB0 + st * STAGE_FLOATS;
+#pragma unroll
+            for (int q = 0; q < S / AV; ++q) {
+                typename VecT<AV>::T av[RM];
+#pragma unroll
+                for (int i = 0; i < RM; ++i)
+                    av[i] = *reinterpret_cast<const typename VecT<AV>::T*>(
+                        sA + arow0 + i * MI * LDA_S + q * AV);
+#pragma unroll
+                for (int t = 0; t < AV; ++t) {
+                    const int s = q * AV + t;
+                    float bv[RN];
+#pragma unroll
+                    for (int j = 0; j < RN; ++j)
+                        bv[j] = sB[(kg0 + s) * LDB_S + bcol0 + j * MI];
+#pragma unroll
+                    for (int i = 0; i < RM; ++i)
+#pragma unroll
+                        for (int j = 0; j < RN; ++j)
+                            acc[i][j] = mfma(bv[j], vget<AV>(av[i], t), acc[i][j]);
+                }
+            }
+            if (kt + 1 < nkt) sstore(st ^ 1);
+            __syncthreads();
+        }
+    } else {
+        // ---- direct loads: every wave fetches its own operands -------------
+        // A operand: S consecutive k of one row per lane (vector loads);
+        // B operand: one column per lane for each of the S steps.
+        constexpr int AVV = (S % V == 0) ? V : 1;
+        typedef typename VecT<AVV>::T avt;
+        avt ra[2][RM][S / AVV];
+        float rb[2][RN][S];
+        bool oka[2][RM][S / AVV], okb[2][RN][S];
+        const int mrow = m0 + wm * WTM + lr;
+        const int ncol = n0 + wn * WTN + lr;
+
+        auto gload = [&](int kt, int b) {
+            const int kbase = kt * KWG + kg0;
+#pragma unroll
+            for (int i = 0; i < RM; ++i) {
+                const int m = mrow + i * MI;
+#pragma unroll
+                for (int q = 0; q < S / AVV; ++q) {
+                    const int k = kbase + q * AVV;
+                    oka[b][i][q] = (m < M) && (k < K);
+                    ra[b][i][q] = load_raw<AVV>(A + (long)m * lda + k, oka[b][i][q], A);
+                }
+            }
+#pragma unroll
+            for (int s = 0; s < S; ++s) {
+                const int k = kbase + s;
+#pragma unroll
+                for (int j = 0; j < RN; ++j) {
+                    const int n = ncol + j * MI;
+                    okb[b][j][s] = (k < K) && (n < N);
+                    rb[b][j][s] = load_raw<1>(B + (long)k * ldb + n, okb[b][j][s], B);
+                }
+            }
+        };
+
+        gload(0, 0);
+        for (int kt = 0; kt < nkt; kt += 2) {
+            // Two slabs per trip so that the register buffers are indexed by
+            // constants after unrolling.
+#pragma unroll
+            for (int b = 0; b < 2; ++b) {
+                if (kt + b < nkt) {
+                    if (kt + b + 1 < nkt) gload(kt + b + 1, b ^ 1);
+#pragma unroll
+                    for (int s = 0; s < S; ++s) {
+#pragma unroll
+                        for (int i = 0; i < RM; ++i) {
+                            const float y = oka[b][i][s / AVV] ? vget<AVV>(ra[b][i][s / AVV], s % AVV) : 0.0f;
+#pragma unroll
+                            for (int j = 0; j < RN; ++j)
+                                acc[i][j] = mfma(okb[b][j][s] ? rb[b][j][s] : 0.0f, y, acc[i][j]);
+                        }
+                    }
+                }
+            }
+        }
+    }
+
+    // ---- reduce split-K groups through LDS ---------------------------------
+    if constexpr (SK > 1) {
+        if constexpr (USE_LDS) __syncthreads();
+        constexpr int PER_WAVE = RM * RN * ACC * 64;
+        if (grp > 0) {
+            float* dst = smem + ((grp - 1) * (WM * WN) + wq) * PER_WAVE;
+#pragma unroll
+            for (int i = 0; i < RM; ++i)
+#pragma unroll
+                for (int j = 0; j < RN; ++j)
+#pragma unroll
+                    for (int e = 0; e < ACC; ++e)
+                        dst[((i * RN + j) * ACC + e) * 64 + lane] = acc[i][j][e];
+        }
+        __syncthreads();
+        if (grp > 0) return;
+#pragma unroll
+        for (int g = 1; g < SK; ++g) {
+            const float* src = smem + ((g - 1) * (WM * WN) + wq) * PER_WAVE;
+#pragma unroll
+            for (int i = 0; i < RM; ++i)
+#pragma unroll
+                for (int j = 0; j < RN; ++j)
+#pragma unroll
+                    for (int e = 0; e < ACC; ++e)
+                        acc[i][j][e] += src[((i * RN + j) * ACC + e) * 64 + lane];
+        }
+    }
+
+    // ---- epilogue: C = alpha*acc + beta*C ----------------------------------
+    // Lane holds row m0+wm*WTM+i*MI+lr and, per group of 4 accumulators, the
+    // columns n0+wn*WTN+j*MI + (MI==32 ? 8*g : 0) + 4*lh + {0,1,2,3}.
+    const bool cvec = ((reinterpret_cast<uintptr_t>(C) & 15) == 0) && ((ldc & 3) == 0);
+    const bool use_beta = (beta != 0.0f);
+#pragma unroll
+    for (int i = 0; i < RM; ++i) {
+        const int m = m0 + wm * WTM + i * MI + lr;
+        if (m >= M) continue;
+        float* crow = C + (long)m * ldc;
+#pragma unroll
+        for (int j = 0; j < RN; ++j) {
+#pragma unroll
+            for (int g = 0; g < ACC / 4; ++g) {
+                const int n = n0 + wn * WTN + j * MI + (MI == 32 ? 8 * g : 0) + 4 * lh;
+                f32x4 v;
+                v[0] = acc[i][j][4 * g + 0];
+                v[1] = acc[i][j][4 * g + 1];
+                v[2] = acc[i][j][4 * g + 2];
+                v[3] = acc[i][j][4 * g + 3];
+                if (cvec && n + 4 <= N) {
+                    f32x4 o = alpha * v;
+                    if (use_beta) o += beta * *reinterpret_cast<const f32x4*>(crow + n);
+                    *reinterpret_cast<f32x4*>(crow + n) = o;
+                } else {
+#pragma unroll
+                    for (int c = 0; c < 4; ++c) {
+                        if (n + c < N) {
+                            float o = alpha * v[c];
+                            if (use_beta) o += beta * crow[n + c];
+                            crow[n + c] = o;
+                        }
+                    }
+                }
+            }
+        }
+    }
+}
+
+}  // namespace
+
+extern "C" __global__ void __launch_bounds__(NT)
+FF_NAME(int M, int N, int K, float alpha, const float* __restrict__ A, long lda,
+        const float* __restrict__ B, long ldb, float beta, float* __restrict__ C, long ldc)
+{
+    __shared__ __attribute__((aligned(16))) float smem[LDS_FLOATS];
+    gemm_body<VW>(M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, smem);
+}
+
+extern "C" __global__ void __launch_bounds__(NT)
+FF_CAT(FF_NAME, _v1)(int M, int N, int K, float alpha, const float* __restrict__ A, long lda,
+                     const float* __restrict__ B, long ldb, float beta, float* __restrict__ C, long ldc)
+{
+    __shared__ __attribute__((aligned(16))) float smem[LDS_FLOATS];
+    gemm_body<1>(M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, smem);
+}

@@ -1,0 +1,186 @@
+"""Variant space of the SGEMM kernel and the family that is compiled.
+
+Sec. III-A: tuning parameters are compile-time constants and each parameter
+combination compiled is a code variant.  Sec. V-C: the parameter space is too
+large to explore fully, so the paper times the library's hand-tuned defaults
+plus a random selection from the space.  This module does the same for the
+gfx950 kernel in ``csrc/sgemm_variant.hip``: it enumerates every legal
+configuration of the axes below, then keeps a fixed default, a hand-picked
+set and a seeded sample stratified by work-group tile shape.
+
+Axes (names match the kernel's FF_* macros):
+  MWG, NWG  work-group tile; KWG slab depth; MI MFMA block edge (32: 32x32x2,
+  16: 16x16x4); WM x WN wave grid; SK intra-work-group split of K; VW
+  global-load vector width; LDS staging on/off; GM tile-order group height.
+"""
+from __future__ import annotations
+
+import itertools
+from dataclasses import dataclass, asdict
+
+import numpy as np
+
+# Per-lane register budgets used to reject configurations that would spill
+# or leave no room for the pipeline (gfx950: 512 VGPR+AGPR per lane at one
+# wave per SIMD).
+MAX_ACC = 128            # accumulator floats per lane
+MAX_DIRECT_OPERANDS = 64  # double-buffered operand registers, direct loads
+MAX_LDS_BYTES = 80 * 1024  # keeps >= 2 work-groups per CU possible (160 KB LDS)
+MAX_THREADS = 512
+
+
+@dataclass(frozen=True)
+class Variant:
+    mwg: int
+    nwg: int
+    kwg: int
+    mi: int
+    wm: int
+    wn: int
+    sk: int
+    vw: int
+    lds: int
+    gm: int = 8
+
+    @property
+    def mk(self):
+        return 2 if self.mi == 32 else 4
+
+    @property
+    def threads(self):
+        return 64 * self.wm * self.wn * self.sk
+
+    @property
+    def rm(self):
+        return self.mwg // (self.wm * self.mi)
+
+    @property
+    def rn(self):
+        return self.nwg // (self.wn * self.mi)
+
+    @property
+    def steps(self):
+        """MFMA steps per split group per slab."""
+        return self.kwg // (self.sk * self.mk)
+
+    @property
+    def acc_regs(self):
+        return self.rm * self.rn * self.mi * self.mi // 64
+
+    @property
+    def lds_bytes(self):
+        stage = self.mwg * (self.kwg + 4) + self.kwg * (self.nwg + 4)
+        red = (self.sk - 1) * self.mwg * self.nwg
+        return 4 * (max(2 * stage, red) if self.lds else max(red, 1))
+
+    @property
+    def name(self):
+        n = (f"sgemm_m{self.mwg}n{self.nwg}k{self.kwg}_i{self.mi}_w{self.wm}x{self.wn}"
+             f"_s{self.sk}_v{self.vw}_l{self.lds}")
+        return n if self.gm == 8 else n + f"_g{self.gm}"
+
+    def defines(self):
+        return {"FF_MWG": self.mwg, "FF_NWG": self.nwg, "FF_KWG": self.kwg, "FF_MI": self.mi,
+                "FF_WM": self.wm, "FF_WN": self.wn, "FF_SK": self.sk, "FF_VW": self.vw,
+                "FF_LDS": self.lds, "FF_GM": self.gm, "FF_NAME": self.name}
+
+    def descriptor(self, vid):
+        """Manifest / set-file descriptor: id name MWG NWG KWG MI WM WN SK VW LDS GM."""
+        return (f"{vid} {self.name} {self.mwg} {self.nwg} {self.kwg} {self.mi} {self.wm} {self.wn} "
+                f"{self.sk} {self.vw} {self.lds} {self.gm}")
+
+    def as_dict(self):
+        return asdict(self)
+
+
+def legal(v: Variant) -> bool:
+    """Constraints of the kernel template plus resource budgets."""
+    if v.mi not in (16, 32) or v.vw not in (1, 2, 4) or v.lds not in (0, 1):
+        return False
+    if v.mwg % (v.wm * v.mi) or v.nwg % (v.wn * v.mi):
+        return False
+    if v.kwg % (v.sk * v.mk) or v.kwg % 4 or v.nwg % 4:
+        return False
+    if v.threads > MAX_THREADS or v.acc_regs > MAX_ACC or v.lds_bytes > MAX_LDS_BYTES:
+        return False
+    if max(v.mwg, v.nwg) > 4 * min(v.mwg, v.nwg):
+        return False  # elongated tiles re-read the long operand too often
+    if not v.lds and 2 * v.steps * (v.rm + v.rn) > MAX_DIRECT_OPERANDS:
+        return False
+    if v.lds:
+        # Every thread should have at least one vector of each slab to stage.
+        if v.mwg * v.kwg < v.threads * v.vw or v.kwg * v.nwg < v.threads * v.vw:
+            return False
+    return True
+
+
+TILES = (16, 32, 64, 128, 256)
+
+
+def enumerate_space():
+    """All legal configurations, in a fixed order."""
+    out = []
+    for mi, mwg, nwg, kwg, wm, wn, sk, vw, lds in itertools.product(
+            (32, 16), TILES, TILES, (8, 16, 32), (1, 2, 4), (1, 2, 4), (1, 2, 4), (1, 2, 4), (1, 0)):
+        v = Variant(mwg, nwg, kwg, mi, wm, wn, sk, vw, lds)
+        if legal(v):
+            out.append(v)
+    return out
+
+
+# The fixed single variant of the first workload: 64x64 tile, K-step 16.
+DEFAULT = Variant(64, 64, 16, 32, 2, 2, 1, 4, 1)
+
+# Hand-picked configurations that cover large, skinny and tiny shapes.
+HAND = [
+    Variant(128, 128, 16, 32, 2, 2, 1, 4, 1),
+    Variant(128, 128, 32, 32, 2, 2, 1, 4, 1),
+    Variant(128, 128, 16, 32, 2, 2, 2, 4, 1),
+    Variant(256, 128, 16, 32, 4, 2, 1, 4, 1),
+    Variant(128, 256, 16, 32, 2, 4, 1, 4, 1),
+    Variant(256, 128, 16, 32, 2, 2, 1, 4, 1),
+    Variant(128, 256, 16, 32, 2, 2, 1, 4, 1),
+    Variant(256, 256, 8, 32, 2, 4, 1, 4, 1),
+    Variant(128, 64, 16, 32, 2, 2, 1, 4, 1),
+    Variant(64, 128, 16, 32, 2, 2, 1, 4, 1),
+    Variant(64, 64, 32, 32, 2, 2, 2, 4, 1),
+    Variant(64, 64, 32, 32, 1, 1, 4, 4, 1),
+    Variant(64, 64, 16, 16, 2, 2, 1, 4, 1),
+    Variant(32, 32, 32, 32, 1, 1, 4, 4, 1),
+    Variant(32, 32, 16, 16, 2, 2, 1, 1, 1),
+    Variant(32, 32, 32, 16, 1, 1, 4, 4, 0),
+    Variant(32, 64, 16, 32, 1, 2, 2, 2, 1),
+    Variant(64, 32, 16, 32, 2, 1, 2, 2, 1),
+    Variant(16, 16, 32, 16, 1, 1, 4, 4, 0),
+    Variant(32, 32, 16, 32, 1, 1, 1, 4, 0),
+    Variant(64, 64, 16, 32, 2, 2, 1, 4, 0),
+    Variant(128, 128, 16, 16, 2, 2, 1, 4, 1),
+]
+
+
+def family(n=200, seed=0):
+    """The compiled family: DEFAULT, HAND, then a seeded sample stratified by
+    (MWG, NWG) tile shape, up to ``n`` variants.  Deterministic for a seed."""
+    space = enumerate_space()
+    legal_set = set(space)
+    chosen = [DEFAULT] + [v for v in HAND if v in legal_set and v != DEFAULT]
+    seen = set(chosen)
+    strata = {}
+    for v in space:
+        if v not in seen:
+            strata.setdefault((v.mwg, v.nwg), []).append(v)
+    rng = np.random.default_rng([11, seed])
+    keys = sorted(strata)
+    for k in keys:
+        order = rng.permutation(len(strata[k]))
+        strata[k] = [strata[k][i] for i in order]
+    # Round-robin over strata so every tile shape is represented.
+    idx = 0
+    while len(chosen) < n and any(strata[k] for k in keys):
+        k = keys[idx % len(keys)]
+        if strata[k]:
+            v = strata[k].pop()
+            chosen.append(v)
+            seen.add(v)
+        idx += 1
+    return chosen[:n]

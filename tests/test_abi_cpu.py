@@ -1,0 +1,185 @@
+"""C-ABI checks that need no GPU: the library loads, exports every symbol the
+header declares, validates arguments before touching HIP, parses set files,
+and its host-side portability tuning agrees with the oracle."""
+import itertools
+import os
+import re
+
+import numpy as np
+import pytest
+
+from oracle import ptune_ref as pr
+from paper_2507_15277_amd import abi, space
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "fewfit.h")
+INF = float("inf")
+
+
+@pytest.fixture(scope="module")
+def L():
+    if not os.path.exists(abi.LIB_PATH):
+        pytest.fail("libfewfit.so not built (run __graft_entry__.build())")
+    return abi.lib()
+
+
+def _declared():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return set(re.findall(r"^\s*(?:const\s+)?\w+\s*\*?\s*(\w+)\s*\(", text, flags=re.M))
+
+
+def test_exports_every_declared_symbol(L):
+    declared = _declared()
+    assert declared == set(abi.EXPORTS), declared ^ set(abi.EXPORTS)
+    for name in declared:
+        assert hasattr(L, name), name
+
+
+def test_header_error_codes_match_binding():
+    text = open(HEADER).read()
+    codes = dict(re.findall(r"#define (FF_\w+) \((-?\d+)\)", text))
+    for name, val in codes.items():
+        assert getattr(abi, name) == int(val), name
+
+
+@pytest.mark.parametrize("args,code", [
+    ((-1, 4, 4, 1.0, 8, 4, 8, 4, 0.0, 8, 4), abi.FF_ERR_M),
+    ((4, -1, 4, 1.0, 8, 4, 8, 4, 0.0, 8, 4), abi.FF_ERR_N),
+    ((4, 4, -1, 1.0, 8, 4, 8, 4, 0.0, 8, 4), abi.FF_ERR_K),
+    ((4, 4, 4, 1.0, None, 4, 8, 4, 0.0, 8, 4), abi.FF_ERR_A),
+    ((4, 4, 4, 1.0, 8, 3, 8, 4, 0.0, 8, 4), abi.FF_ERR_LDA),
+    ((4, 4, 4, 1.0, 8, 4, None, 4, 0.0, 8, 4), abi.FF_ERR_B),
+    ((4, 4, 4, 1.0, 8, 4, 8, 3, 0.0, 8, 4), abi.FF_ERR_LDB),
+    ((4, 4, 4, 1.0, 8, 4, 8, 4, 0.0, None, 4), abi.FF_ERR_C),
+    ((4, 4, 4, 1.0, 8, 4, 8, 4, 0.0, 8, 3), abi.FF_ERR_LDC),
+    ((4, 4, 0, 1.0, 8, 0, 8, 4, 0.0, 8, 4), abi.FF_ERR_LDA),   # lda >= max(1, K)
+    ((2 ** 31, 4, 4, 1.0, 8, 4, 8, 4, 0.0, 8, 4), abi.FF_ERR_TOO_LARGE),
+])
+def test_argument_errors_before_any_hip_call(L, args, code):
+    M, N, K, al, A, lda, B, ldb, be, C, ldc = args
+    rc = L.sgemm(M, N, K, al, A, lda, B, ldb, be, C, ldc, None)
+    assert rc == code, abi.last_error()
+    rc = L.sgemm_variant(0, M, N, K, al, A, lda, B, ldb, be, C, ldc, None)
+    assert rc == code
+
+
+def test_null_operands_allowed_when_not_read(L):
+    # alpha == 0 and beta == 1, or M == 0: quick return with NULL A/B.
+    assert L.sgemm(4, 4, 4, 0.0, None, 4, None, 4, 1.0, 8, 4, None) == 0
+    assert L.sgemm(0, 4, 4, 1.0, None, 4, None, 4, 0.0, None, 4, None) == 0
+    assert L.sgemm(4, 4, 0, 1.0, None, 1, None, 4, 1.0, 8, 4, None) == 0
+
+
+def test_no_set_loaded(L):
+    assert L.variant_select(256, 256, 256) == abi.FF_ERR_NO_SET
+    assert L.sgemm(4, 4, 4, 1.0, 8, 4, 8, 4, 0.0, 8, 4, None) == abi.FF_ERR_NO_SET
+    assert L.variant_select(-1, 1, 1) == abi.FF_ERR_M
+    assert L.sgemm_variant(10 ** 6, 4, 4, 4, 1.0, 8, 4, 8, 4, 0.0, 8, 4, None) == abi.FF_ERR_VARIANT
+
+
+GOOD_VARIANT = space.DEFAULT.descriptor(0)
+
+
+@pytest.mark.parametrize("body,code", [
+    ("", abi.FF_ERR_PARSE),
+    ("fewfit-set 2\n", abi.FF_ERR_PARSE),
+    ("fewfit-set 1\narch gfx950\ncodedir .\nvariant 0 bad\nrule 1 1 1 0\nend\n", abi.FF_ERR_PARSE),
+    (f"fewfit-set 1\narch gfx950\ncodedir .\nvariant {GOOD_VARIANT}\nrule 1 1 1 5\nend\n", abi.FF_ERR_PARSE),
+    (f"fewfit-set 1\narch gfx950\ncodedir .\nvariant {GOOD_VARIANT}\nrule 1 1 1 0\n", abi.FF_ERR_PARSE),
+    (f"fewfit-set 1\narch gfx950\ncodedir .\nvariant {GOOD_VARIANT}\nend\n", abi.FF_ERR_PARSE),
+    (f"fewfit-set 1\narch gfx950\ncodedir .\nvariant {GOOD_VARIANT}\nvariant {GOOD_VARIANT}\n"
+     "rule 1 1 1 0\nend\n", abi.FF_ERR_PARSE),
+    (f"fewfit-set 1\narch gfx950\ncodedir .\nvariant {GOOD_VARIANT}\nrule 1 1 1 0 9\nend\n", abi.FF_ERR_PARSE),
+    (f"fewfit-set 1\nfoo 1\nend\n", abi.FF_ERR_PARSE),
+])
+def test_set_file_parse_errors(L, tmp_path, body, code):
+    p = tmp_path / "set.txt"
+    p.write_text(body)
+    assert L.variant_set_load(os.fsencode(str(p))) == code, abi.last_error()
+
+
+def test_set_file_missing(L, tmp_path):
+    assert L.variant_set_load(os.fsencode(str(tmp_path / "nope.txt"))) == abi.FF_ERR_IO
+    assert L.variant_manifest_load(os.fsencode(str(tmp_path))) == abi.FF_ERR_IO
+
+
+# --- host portability tuning vs the oracle ------------------------------------
+
+def _rand_table(seed, nv, ns, fail_frac=0.0):
+    rng = np.random.default_rng([3, seed])
+    t = np.exp(rng.normal(0, 0.6, (nv, ns))) * rng.uniform(0.5, 20, ns)
+    if fail_frac:
+        t[rng.random((nv, ns)) < fail_frac] = INF
+    return t
+
+
+@pytest.mark.parametrize("seed", range(8))
+def test_postprocess_matches_oracle(seed):
+    t = _rand_table(seed, 7, 5, fail_frac=0.15)
+    best, worst, best_id, slow, speed = abi.ptune_postprocess(t)
+    b2, w2, bi2, s2, sp2 = pr.postprocess(t.tolist())
+    assert list(best_id) == bi2
+    assert np.array_equal(best, np.array(b2)) and np.array_equal(worst, np.array(w2))
+    assert np.array_equal(slow, np.array(s2)) and np.array_equal(speed, np.array(sp2))
+
+
+@pytest.mark.parametrize("seed", range(10))
+@pytest.mark.parametrize("k", [1, 2, 3, 4])
+def test_exhaustive_select_matches_bruteforce(seed, k):
+    nv, ns = 11, 7
+    t = _rand_table(100 + seed, nv, ns, fail_frac=0.1 if seed % 2 else 0.0)
+    shapes = list(range(0, ns, 1)) if seed % 3 else [0, 2, 3, 5]
+    kap, cost, evals = abi.ptune_select(t, k, shapes=shapes, method=0)
+    kap_ref, cost_ref = pr.portability_tune(t.tolist(), k, shapes)
+    # Several sets may tie; parity is on the objective value.
+    if cost_ref == INF:
+        assert cost == INF
+    else:
+        assert cost == pytest.approx(cost_ref, rel=1e-12)
+        assert pr.library_cost(t.tolist(), kap, shapes) == pytest.approx(cost, rel=1e-12)
+    assert len(kap) == k and len(set(kap)) == k
+    assert abi.ptune_cost(t, kap, shapes) == pytest.approx(cost, rel=1e-12) or cost == INF
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_greedy_swap_is_a_local_optimum(seed):
+    nv, ns = 12, 8
+    t = _rand_table(200 + seed, nv, ns)
+    for k in (2, 3, 5):
+        kap, cost, _ = abi.ptune_select(t, k, method=1)
+        _, best_cost = pr.portability_tune(t.tolist(), k)
+        assert cost >= best_cost * (1 - 1e-12)
+        # No single swap improves the set.
+        for p, v in itertools.product(range(k), range(nv)):
+            if v in kap:
+                continue
+            trial = list(kap)
+            trial[p] = v
+            assert pr.library_cost(t.tolist(), trial) >= cost * (1 - 1e-12)
+
+
+def test_select_known_block_answer():
+    # Variant g is best (1.0) on its own group of shapes and 2.0 elsewhere;
+    # three fillers at 3.0.  k = 3 must return the three owners at cost 1.
+    groups = [4, 3, 2]
+    owner = sum(([g] * n for g, n in enumerate(groups)), [])
+    t = np.array([[1.0 if o == g else 2.0 for o in owner] for g in range(3)] + [[3.0] * 9] * 3)
+    assert abi.ptune_select(t, 3, method=0)[:2] == ((0, 1, 2), 1.0)
+    assert abi.ptune_select(t, 1, method=0)[0] == (0,)
+
+
+def test_assign_matches_oracle():
+    t = _rand_table(9, 9, 6, fail_frac=0.2)
+    kap = (1, 4, 7)
+    assert abi.ptune_assign(t, kap, [0, 2, 5]) == pr.assign_winners(t.tolist(), kap, [0, 2, 5])
+
+
+def test_select_argument_errors():
+    t = _rand_table(1, 3, 3)
+    with pytest.raises(abi.FewfitError):
+        abi.ptune_select(t, 0)
+    with pytest.raises(abi.FewfitError):
+        abi.ptune_select(t, 2, shapes=[0, 9])
+    with pytest.raises(abi.FewfitError):
+        abi.ptune_cost(t, [5])
