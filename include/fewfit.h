@@ -220,6 +220,14 @@ int ptune_select(int nv, int ns, const double *t, int nsel, const int *shapes,
 int ptune_assign(int nv, int ns, const double *t, int k, const int *kappa,
                  int nsel, const int *shapes, int *winners);
 
+/*
+ * The dispatch rule of variant_select() on an explicit table: the index of
+ * the training shape (ntrain triples M,N,K in train_mnk) nearest to
+ * (M, N, K) in L1 distance over log2 sizes (sizes below 1 count as 1), ties
+ * to the lower index.  Returns the index, or FF_ERR_ARG.
+ */
+int ptune_nearest(int ntrain, const int64_t *train_mnk, int64_t M, int64_t N, int64_t K);
+
 #ifdef __cplusplus
 }
 #endif

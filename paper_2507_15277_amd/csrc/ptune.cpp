@@ -347,3 +347,21 @@ FF_EXPORT int ptune_assign(int nv, int ns, const double* t, int k, const int* ka
     }
     return FF_OK;
 }
+
+FF_EXPORT int ptune_nearest(int ntrain, const int64_t* train_mnk, int64_t M, int64_t N, int64_t K)
+{
+    if (ntrain < 1 || train_mnk == nullptr) return FF_ERR_ARG;
+    auto lg = [](int64_t x) { return std::log2((double)std::max<int64_t>(1, x)); };
+    const double q[3] = {lg(M), lg(N), lg(K)};
+    int best = 0;
+    double bd = kInf;
+    for (int i = 0; i < ntrain; ++i) {
+        const double d = std::fabs(q[0] - lg(train_mnk[3 * i])) + std::fabs(q[1] - lg(train_mnk[3 * i + 1])) +
+                         std::fabs(q[2] - lg(train_mnk[3 * i + 2]));
+        if (d < bd) {
+            bd = d;
+            best = i;
+        }
+    }
+    return best;
+}

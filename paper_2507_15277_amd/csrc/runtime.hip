@@ -77,7 +77,7 @@ bool parse_descriptor(std::istringstream& is, Variant& v)
 struct VarSet {
     std::vector<int> ids;                        // members
     std::vector<std::array<int64_t, 3>> shapes;  // training shapes, file order
-    std::vector<std::array<double, 3>> lg;       // their log2 sizes
+    std::vector<int64_t> flat;                   // the same, as M,N,K triples
     std::vector<int> winners;                    // member chosen per training shape
 };
 
@@ -422,7 +422,7 @@ FF_EXPORT int variant_set_load(const char* path)
             if (std::find(set->ids.begin(), set->ids.end(), id) == set->ids.end())
                 return fail(FF_ERR_PARSE, "%s:%d: rule names variant %d outside the set", path, lineno, id);
             set->shapes.push_back({m, n, k});
-            set->lg.push_back({std::log2((double)m), std::log2((double)n), std::log2((double)k)});
+            set->flat.insert(set->flat.end(), {(int64_t)m, (int64_t)n, (int64_t)k});
             set->winners.push_back(id);
         } else if (key == "end") {
             ended = true;
@@ -462,18 +462,8 @@ FF_EXPORT int variant_select(int64_t M, int64_t N, int64_t K)
         set = g_set;
     }
     if (!set) return fail(FF_ERR_NO_SET, "no variant set loaded");
-    const double q[3] = {std::log2((double)std::max<int64_t>(1, M)), std::log2((double)std::max<int64_t>(1, N)),
-                         std::log2((double)std::max<int64_t>(1, K))};
-    size_t best = 0;
-    double bd = INFINITY;
-    for (size_t i = 0; i < set->lg.size(); ++i) {
-        const double d = std::fabs(q[0] - set->lg[i][0]) + std::fabs(q[1] - set->lg[i][1]) +
-                         std::fabs(q[2] - set->lg[i][2]);
-        if (d < bd) {
-            bd = d;
-            best = i;
-        }
-    }
+    const int best = ptune_nearest((int)set->shapes.size(), set->flat.data(), M, N, K);
+    if (best < 0) return fail(FF_ERR_NO_SET, "variant set has no training shapes");
     return set->winners[best];
 }
 

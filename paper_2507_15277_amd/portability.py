@@ -1,0 +1,213 @@
+"""Portability tuning on the measured table, set files, and evaluation.
+
+Steps (Sec. IV, Sec. V-C, Sec. V-E), all arithmetic in libfewfit:
+
+* post-processing: per-shape best (AutoTune, Sec. IV-A) and worst, slowdown
+  and speedup of every entry (Sec. V-C, Table VI columns);
+* PortabilityTune (Sec. IV-B): for k in {1, 2, 4, 8}, the set minimising
+  Eq. 1 over the training shapes (exhaustive where feasible, greedy + swap
+  otherwise);
+* the dispatch table for the set file: the in-set winner of each training
+  shape; unseen shapes go to the nearest training shape;
+* evaluation (Sec. V-E figures of merit): fraction of the per-shape best
+  (1 / slowdown-over-best, geometric mean) on the held-out shapes as
+  realised by the dispatch rule, and over all 27 shapes with a perfect
+  in-set pick (how the paper evaluates, Fig. 1); geomean TFLOP/s.
+
+Usage: python -m paper_2507_15277_amd.portability --table T.jsonl [--write-sets]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import time
+
+import numpy as np
+
+from . import abi, datagen, space, tuned
+from .tune import load_rows, kernel_hash
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+DATA_DIR = os.path.join(PKG, "data")
+TABLE = os.path.join(DATA_DIR, "mi355x_table.jsonl")
+KS = (1, 2, 4, 8)
+
+
+def read_variants(directory=tuned.VARIANT_DIR):
+    """{id: space.Variant} from the manifest."""
+    out = {}
+    with open(os.path.join(directory, "manifest.txt")) as f:
+        for line in f:
+            if line.strip() and not line.startswith("#"):
+                p = line.split()
+                vals = [int(x) for x in p[2:]]
+                out[int(p[0])] = space.Variant(*vals)
+    return out
+
+
+def matrix(rows, shapes, beta=0.0, nv=None):
+    """Time matrix t[v][s] (ms); +inf where a variant failed or is missing."""
+    nv = nv if nv is not None else 1 + max(r["variant"] for r in rows)
+    idx = {tuple(s): j for j, s in enumerate(shapes)}
+    t = np.full((nv, len(shapes)), np.inf)
+    for r in rows:
+        j = idx.get((r["M"], r["N"], r["K"]))
+        if j is None or r["beta"] != beta or r.get("status") != "ok":
+            continue
+        t[r["variant"], j] = r["ms"]
+    return t
+
+
+def geomean(xs):
+    xs = list(xs)
+    return math.exp(sum(math.log(x) for x in xs) / len(xs))
+
+
+def tflops(shape, ms):
+    M, N, K = shape
+    return 2.0 * M * N * K / ms / 1e9
+
+
+def evaluate(t, shapes, train_idx, kappa):
+    """Figures of merit of one set on the grid."""
+    best, _, _, _, _ = abi.ptune_postprocess(t)
+    train = [shapes[j] for j in train_idx]
+    winners = abi.ptune_assign(t, kappa, train_idx)
+    held_idx = [j for j in range(len(shapes)) if j not in set(train_idx)]
+    realised = {}
+    for j, s in enumerate(shapes):
+        i = abi.ptune_nearest(train, *s)
+        realised[j] = winners[i]
+    frac = lambda idx, pick: geomean(best[j] / t[pick(j), j] for j in idx)  # noqa: E731
+    in_set = lambda j: min(kappa, key=lambda v: (t[v, j], v))  # noqa: E731
+    return {
+        "kappa": list(kappa),
+        "winners": winners,
+        "frac_heldout_realised": frac(held_idx, lambda j: realised[j]),
+        "frac_heldout_inset": frac(held_idx, in_set),
+        "frac_train": frac(train_idx, in_set),
+        "frac_all_inset": frac(range(len(shapes)), in_set),
+        "frac_all_realised": frac(range(len(shapes)), lambda j: realised[j]),
+        "geomean_tflops_realised": geomean(tflops(s, t[realised[j], j]) for j, s in enumerate(shapes)),
+        "per_shape": [{"M": s[0], "N": s[1], "K": s[2], "variant": int(realised[j]),
+                       "tflops": tflops(s, t[realised[j], j]),
+                       "best_tflops": tflops(s, best[j]), "frac": best[j] / t[realised[j], j],
+                       "held_out": j not in set(train_idx)}
+                      for j, s in enumerate(shapes)],
+    }
+
+
+def run(table=TABLE, write_sets=False, splits=5, log=print):
+    rows = load_rows(table, kernel_hash())
+    if not rows:
+        raise RuntimeError(f"no rows for the current kernel source in {table}")
+    variants = read_variants()
+    nv = len(variants)
+    shapes = datagen.grid27()
+    t = matrix(rows, shapes, 0.0, nv)
+    train, held = datagen.checkerboard_split(shapes)
+    train_idx = [shapes.index(s) for s in train]
+    best, worst, best_id, slow, speed = abi.ptune_postprocess(t)
+    report = {"device": rows[0].get("device"), "n_variants": nv,
+              "n_rows": len(rows), "kernel_build": kernel_hash(),
+              "per_shape_best": [{"M": s[0], "N": s[1], "K": s[2], "variant": int(best_id[j]),
+                                  "name": variants[int(best_id[j])].name,
+                                  "tflops": tflops(s, best[j])} for j, s in enumerate(shapes)],
+              "geomean_tflops_best": geomean(tflops(s, best[j]) for j, s in enumerate(shapes)),
+              "distinct_winners": len(set(int(b) for b in best_id)),
+              "sets": {}}
+    # Middle 50% of variant slowdowns per shape (the paper quotes this band
+    # to describe how sensitive a device is to tuning, Sec. IV-D-1).
+    q25, q75 = [], []
+    for j in range(len(shapes)):
+        col = slow[:, j][np.isfinite(slow[:, j])]
+        q25.append(float(np.percentile(col, 25)))
+        q75.append(float(np.percentile(col, 75)))
+    report["slowdown_middle50_median"] = [float(np.median(q25)), float(np.median(q75))]
+    # The fixed single variant (id 0) as the one-variant baseline.
+    report["fixed_variant"] = evaluate(t, shapes, train_idx, (0,))
+    for k in KS:
+        t0 = time.perf_counter()
+        kappa, cost, evals = abi.ptune_select(t, k, shapes=train_idx, method=-1)
+        dt = time.perf_counter() - t0
+        ev = evaluate(t, shapes, train_idx, kappa)
+        ev.update(train_cost=cost, evals=int(evals), select_seconds=dt,
+                  names=[variants[v].name for v in kappa])
+        report["sets"][str(k)] = ev
+        log(f"[select] k={k}: kappa={list(kappa)} train F={1 / cost:.4f} held-out realised "
+            f"F={ev['frac_heldout_realised']:.4f} all in-set F={ev['frac_all_inset']:.4f} "
+            f"geomean {ev['geomean_tflops_realised']:.2f} TFLOP/s ({evals} subsets, {dt:.2f} s)")
+        if write_sets:
+            members = [(v, variants[v]) for v in kappa]
+            rules = [(*shapes[j], w) for j, w in zip(train_idx, ev["winners"])]
+            tuned.write_set_file(
+                tuned.set_path(k), members, rules,
+                comments=(f"PortabilityTune k={k} on the 14 checkerboard training shapes of the "
+                          f"{{256,1024,4096}}^3 grid, MI355X table {os.path.basename(table)}",
+                          f"train fraction of per-shape best {1 / cost:.4f}; held-out realised "
+                          f"{ev['frac_heldout_realised']:.4f}"))
+    # Robustness band: seeded random 14/13 splits.
+    band = {str(k): [] for k in KS}
+    for seed in range(splits):
+        tr, _ = datagen.random_split(seed, 14, shapes)
+        tri = [shapes.index(s) for s in tr]
+        for k in KS:
+            kappa, cost, _ = abi.ptune_select(t, k, shapes=tri, method=-1)
+            band[str(k)].append(evaluate(t, shapes, tri, kappa)["frac_heldout_realised"])
+    report["random_split_heldout_realised"] = band
+    # Shapes from the paper's default-kernel example, two of them off the grid.
+    extra_shapes = [(512, 4096, 4096), (4096, 4096, 512), (1024, 1024, 4096), (4096, 1024, 4096)]
+    te = matrix(rows, extra_shapes, 0.0, nv)
+    if np.isfinite(te).any(axis=0).all():
+        be, _, _, _, _ = abi.ptune_postprocess(te)
+        ex = {"fixed_variant": [float(be[j] / te[0, j]) for j in range(len(extra_shapes))]}
+        for k in KS:
+            ev = report["sets"][str(k)]
+            trs = [shapes[j] for j in train_idx]
+            picks = [ev["winners"][abi.ptune_nearest(trs, *s)] for s in extra_shapes]
+            ex[f"k{k}"] = [float(be[j] / te[p, j]) for j, p in enumerate(picks)]
+        report["default_example_shapes"] = {"shapes": extra_shapes, "frac_of_best": ex}
+    # Square sweep (beta 0 and 0.5): per-shape best and whether beta moves it.
+    sq = datagen.square_shapes()
+    sq_out = []
+    for beta in (0.0, 0.5):
+        ts = matrix(rows, sq, beta, nv)
+        if not np.isfinite(ts).any():
+            continue
+        b, _, bid, sl, _ = abi.ptune_postprocess(ts)
+        for j, s in enumerate(sq):
+            col = sl[:, j][np.isfinite(sl[:, j])]
+            sq_out.append({"M": s[0], "beta": beta, "best_variant": int(bid[j]),
+                           "best_tflops": tflops(s, b[j]),
+                           "fixed_variant_tflops": tflops(s, ts[0, j]),
+                           "slowdown_q25": float(np.percentile(col, 25)),
+                           "slowdown_q75": float(np.percentile(col, 75)),
+                           "n_ok": int(np.isfinite(ts[:, j]).sum())})
+    report["square_sweep"] = sq_out
+    report["screen"] = {
+        "ok": sum(1 for r in rows if r.get("status") == "ok"),
+        "wrong": sum(1 for r in rows if r.get("status") == "wrong"),
+        "launch_fail": sum(1 for r in rows if r.get("status") == "launch_fail"),
+        "max_err_ratio": max((r.get("err_ratio") or 0.0) for r in rows if r.get("status") == "ok"),
+    }
+    return report
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
+    ap.add_argument("--table", default=TABLE)
+    ap.add_argument("--write-sets", action="store_true")
+    ap.add_argument("--report", default=os.path.join(DATA_DIR, "mi355x_report.json"))
+    args = ap.parse_args(argv)
+    rep = run(args.table, write_sets=args.write_sets, log=lambda s: print(s, flush=True))
+    os.makedirs(os.path.dirname(args.report), exist_ok=True)
+    with open(args.report, "w") as f:
+        json.dump(rep, f, indent=1)
+    print(f"geomean TFLOP/s of per-shape best: {rep['geomean_tflops_best']:.2f}; "
+          f"distinct winners {rep['distinct_winners']}; screen {rep['screen']}")
+
+
+if __name__ == "__main__":
+    main()
