@@ -68,6 +68,23 @@ def cpu_baseline(shapes, budget_s=15.0):
                        f"{t_total:.1f} s total; FP64 triple loop with |A||B|, OpenMP over rows")}
 
 
+def measured_traffic(kernel, k, khash):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    summary of this workload, or None if there is none for this kernel source."""
+    path = os.path.join(ROOT, "profiles", f"{kernel}__grid27_k{k}.md")
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    with open(path) as f:
+        for line in f:
+            if ":" in line:
+                key, _, val = line.partition(":")
+                vals[key.strip().strip("`- ")] = val.strip().strip("`")
+    if vals.get("kernel_build") != khash or "traffic_bytes_per_launch" not in vals:
+        return None
+    return float(vals["traffic_bytes_per_launch"])
+
+
 def main():
     ap = argparse.ArgumentParser(description="fewfit SGEMM grid benchmark")
     ap.add_argument("--gpus", type=int, default=1)
@@ -75,6 +92,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--k", type=int, default=4)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--phase", choices=("all", "dispatch"), default="all",
+                    help="dispatch: only the timed dispatch steps (for profiler runs)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -147,26 +166,34 @@ def main():
     tf = [2.0 * M * N * K / ms / 1e9 for (M, N, K), ms in zip(shapes, ms_shape)]
     value = geomean(tf)
 
-    # Per-shape best variant, same protocol, for the fraction of best.
-    ms_best, _ = timed(best_ids, max(2, args.steps // 2), 1)
-    frac = geomean(min(b, d) / d for b, d in zip(ms_best, ms_shape))
-    frac_raw = geomean(b / d for b, d in zip(ms_best, ms_shape))
+    if args.phase == "all":
+        # Per-shape best variant, same protocol, for the fraction of best.
+        ms_best, _ = timed(best_ids, max(2, args.steps // 2), 1)
+        frac = geomean(min(b, d) / d for b, d in zip(ms_best, ms_shape))
+        frac_raw = geomean(b / d for b, d in zip(ms_best, ms_shape))
+    else:
+        ms_best = np.array([t_table[best_ids[j], j] for j in range(len(shapes))])
+        frac = frac_raw = geomean(min(b, d) / d for b, d in zip(ms_best, ms_shape))
 
     # Dominant kernel: the set member with the most time in a step.
+    # Algorithmic work per launch: 2MNK flops; bytes 4(MK + KN + MN) with
+    # beta = 0 (A and B read once, C written once).
     share = {}
     for j, (M, N, K) in enumerate(shapes):
         v = picks[j]
-        fl, tm = share.get(v, (0.0, 0.0))
-        share[v] = (fl + reps[j] * 2.0 * M * N * K, tm + reps[j] * ms_shape[j])
+        fl, tm, by = share.get(v, (0.0, 0.0, 0.0))
+        share[v] = (fl + reps[j] * 2.0 * M * N * K, tm + reps[j] * ms_shape[j],
+                    by + reps[j] * 4.0 * (M * K + K * N + M * N))
     dom = max(share, key=lambda v: share[v][1])
-    fl, tm = share[dom]
+    fl, tm, by = share[dom]
     launches = sum(reps[j] for j in range(len(shapes)) if picks[j] == dom)
     achieved = fl / tm / 1e9
     dom_name = abi.variant_info(dom).split()[1]
-    traffic = None
     roofline = {"bound": "mfma", "achieved": achieved, "peak": FP32_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s",
-                "frac": achieved / FP32_MFMA_PEAK_TFLOPS, "traffic": traffic, "kernel": dom_name,
-                "flop_per_launch": fl / launches, "ms_per_launch": tm / launches,
+                "frac": achieved / FP32_MFMA_PEAK_TFLOPS,
+                "traffic": measured_traffic(dom_name, args.k, kernel_hash()), "kernel": dom_name,
+                "launches_per_step": launches, "flop_per_launch": fl / launches,
+                "algorithmic_bytes_per_launch": by / launches, "ms_per_launch": tm / launches,
                 "shapes": ["x".join(map(str, s)) for j, s in enumerate(shapes) if picks[j] == dom]}
 
     out = {
@@ -184,7 +211,7 @@ def main():
                    "per_shape_tflops": {"x".join(map(str, s)): round(x, 3) for s, x in zip(shapes, tf)}},
         "roofline": roofline,
     }
-    if not args.no_cpu_baseline:
+    if not args.no_cpu_baseline and args.phase == "all":
         out["cpu_baseline"] = cpu_baseline(shapes)
     print(json.dumps(out), flush=True)
 
