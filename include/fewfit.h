@@ -79,6 +79,11 @@ extern "C" {
  * one is reported (FF_ERR_M ... FF_ERR_LDC).  Returns FF_ERR_NO_SET when no
  * set is loaded and the call would launch a GEMM kernel.
  *
+ * Variants that split K over work-groups write their partial products to
+ * one workspace per device (allocated when such a variant is first loaded)
+ * and a second kernel sums them; such calls on one device must not overlap
+ * in time (issue them on one stream, or order the streams).
+ *
  * Each variant is deterministic: the same inputs give bitwise the same C.
  * Different variants may round differently.  The result of every variant
  * satisfies |C - C_exact| <= 4*K*2^-24*|alpha|*(|A||B|) elementwise, plus
@@ -102,10 +107,12 @@ int variant_set_load(const char *path);
 /*
  * Variant id that sgemm() would run for (M, N, K) under the loaded set.
  * Fig. 1 leaves the online picker open and Sec. V-I names unseen inputs as
- * a limitation; the rule used here: the winner (within the set) of the
- * training shape nearest to (M, N, K) in L1 distance over
- * (log2 M, log2 N, log2 K), sizes below 1 counted as 1, ties to the
- * training shape listed first.  Returns the id (>= 0), FF_ERR_NO_SET, or an
+ * a limitation; the rule used here (ptune_dispatch): find the training
+ * shapes nearest to (M, N, K) in L1 distance over (log2 M, log2 N, log2 K),
+ * sizes below 1 counted as 1; with one nearest shape take its winner, with
+ * several take the member whose log-slowdowns summed over them is
+ * smallest (ties to the member listed first).  A training shape therefore
+ * always gets its own winner.  Returns the id (>= 0), FF_ERR_NO_SET, or an
  * argument error for negative sizes.
  */
 int variant_select(int64_t M, int64_t N, int64_t K);
@@ -129,7 +136,7 @@ int variant_count(void);
 
 /*
  * Write variant `id`'s descriptor into buf (NUL-terminated, truncated to
- * len): "<id> <name> <MWG> <NWG> <KWG> <MI> <WM> <WN> <SK> <VW> <LDS> <GM>".
+ * len): "<id> <name> <MWG> <NWG> <KWG> <MI> <WM> <WN> <SK> <VW> <LDS> <GM> <SG>".
  * Returns the full length, or FF_ERR_VARIANT.
  */
 int variant_info(int id, char *buf, size_t len);
@@ -221,12 +228,22 @@ int ptune_assign(int nv, int ns, const double *t, int k, const int *kappa,
                  int nsel, const int *shapes, int *winners);
 
 /*
- * The dispatch rule of variant_select() on an explicit table: the index of
- * the training shape (ntrain triples M,N,K in train_mnk) nearest to
- * (M, N, K) in L1 distance over log2 sizes (sizes below 1 count as 1), ties
- * to the lower index.  Returns the index, or FF_ERR_ARG.
+ * Index of the first training shape (ntrain triples M,N,K in train_mnk)
+ * nearest to (M, N, K) in L1 distance over log2 sizes (sizes below 1 count
+ * as 1).  Returns the index, or FF_ERR_ARG.
  */
 int ptune_nearest(int ntrain, const int64_t *train_mnk, int64_t M, int64_t N, int64_t K);
+
+/*
+ * The dispatch rule of variant_select() on explicit data: members[0..k) are
+ * the set's variant ids, cost[i*k + j] = log(t[members[j]][i] / best[i])
+ * on training shape i (+inf where member j failed there).  Among the
+ * training shapes at the smallest distance (as in ptune_nearest, equal
+ * within 1e-9), returns the member id with the smallest summed cost, ties
+ * to the lower j.  Returns the id, or FF_ERR_ARG.
+ */
+int ptune_dispatch(int ntrain, const int64_t *train_mnk, int k, const int *members,
+                   const double *cost, int64_t M, int64_t N, int64_t K);
 
 #ifdef __cplusplus
 }

@@ -18,9 +18,10 @@ Readings of the paper taken here (also listed in the design notes):
 * Ties (equal cost) are broken towards the lexicographically smallest tuple
   of variant ids, as produced by ``itertools.combinations``.
 * The runtime dispatch rule for unseen shapes is not given by the paper
-  (Sec. V-I lists it as a limitation); this build uses the nearest training
-  shape in (log2 M, log2 N, log2 K) under the L1 distance, ties to the lower
-  training-shape index.
+  (Sec. V-I lists it as a limitation); this build takes the training shapes
+  nearest in (log2 M, log2 N, log2 K) under the L1 distance and, among the
+  members of kappa, the one with the smallest summed log-slowdown over them
+  (ties to the member listed first); a training shape gets its own winner.
 """
 from __future__ import annotations
 
@@ -178,6 +179,25 @@ def nearest_training_shape(train_shapes, M, N, K):
     return best_i
 
 
-def dispatch(train_shapes, winners, M, N, K):
-    """Variant chosen for (M,N,K): the winner of its nearest training shape."""
-    return winners[nearest_training_shape(train_shapes, M, N, K)]
+def _dist(a, b):
+    return sum(abs(math.log2(max(1, a[j])) - math.log2(max(1, b[j]))) for j in range(3))
+
+
+def dispatch(train_shapes, members, cost, M, N, K):
+    """Variant chosen for (M,N,K).
+
+    ``cost[i][j]`` is log(t / best) of member j on training shape i.  All
+    training shapes at the smallest distance vote: the member with the
+    smallest total cost over them wins (first member on ties).  If every
+    member is infinite somewhere among them, the member cheapest on the
+    first nearest shape is taken.
+    """
+    d = [_dist((M, N, K), s) for s in train_shapes]
+    dmin = min(d)
+    near = [i for i in range(len(train_shapes)) if d[i] <= dmin + 1e-9]
+    totals = [sum(cost[i][j] for i in near) for j in range(len(members))]
+    best_j = min(range(len(members)), key=lambda j: (totals[j], j))
+    if totals[best_j] == INF:
+        i0 = near[0]
+        best_j = min(range(len(members)), key=lambda j: (cost[i0][j], j))
+    return members[best_j]

@@ -26,7 +26,7 @@ FF_ERR_ARCH, FF_ERR_HIP, FF_ERR_IO, FF_ERR_TOO_LARGE, FF_ERR_ARG = -103, -104, -
 EXPORTS = ("sgemm", "variant_set_load", "variant_select", "fewfit_last_error",
            "variant_manifest_load", "variant_count", "variant_info", "sgemm_variant",
            "sgemm_time", "screen_reference", "screen_compare", "ptune_postprocess",
-           "ptune_cost", "ptune_select", "ptune_assign", "ptune_nearest")
+           "ptune_cost", "ptune_select", "ptune_assign", "ptune_nearest", "ptune_dispatch")
 
 
 class FewfitError(RuntimeError):
@@ -64,6 +64,7 @@ def lib():
         L.ptune_select.argtypes = [i32, i32, vp, i32, vp, i32, i32, vp, vp, vp]
         L.ptune_assign.argtypes = [i32, i32, vp, i32, vp, i32, vp, vp]
         L.ptune_nearest.argtypes = [i32, vp, i64, i64, i64]
+        L.ptune_dispatch.argtypes = [i32, vp, i32, vp, vp, i64, i64, i64]
         for name in EXPORTS:
             if name != "fewfit_last_error":
                 getattr(L, name).restype = i32
@@ -227,3 +228,13 @@ def ptune_nearest(train_shapes, M, N, K):
     import numpy as np
     tr = np.ascontiguousarray(train_shapes, dtype=np.int64).reshape(-1, 3)
     return _check(lib().ptune_nearest(tr.shape[0], tr.ctypes.data, M, N, K))
+
+
+def ptune_dispatch(train_shapes, members, cost, M, N, K):
+    """cost: ntrain x k log-slowdowns of the members on the training shapes."""
+    import numpy as np
+    tr = np.ascontiguousarray(train_shapes, dtype=np.int64).reshape(-1, 3)
+    mem = np.ascontiguousarray(members, dtype=np.int32)
+    c = np.ascontiguousarray(cost, dtype=np.float64).reshape(tr.shape[0], mem.size)
+    return _check(lib().ptune_dispatch(tr.shape[0], tr.ctypes.data, mem.size, mem.ctypes.data,
+                                       c.ctypes.data, M, N, K))

@@ -348,20 +348,59 @@ FF_EXPORT int ptune_assign(int nv, int ns, const double* t, int k, const int* ka
     return FF_OK;
 }
 
+namespace {
+
+// L1 distance over log2 sizes (sizes below 1 count as 1).
+void shape_distances(int ntrain, const int64_t* train_mnk, int64_t M, int64_t N, int64_t K,
+                     std::vector<double>& d)
+{
+    auto lg = [](int64_t x) { return std::log2((double)std::max<int64_t>(1, x)); };
+    const double q[3] = {lg(M), lg(N), lg(K)};
+    d.resize(ntrain);
+    for (int i = 0; i < ntrain; ++i)
+        d[i] = std::fabs(q[0] - lg(train_mnk[3 * i])) + std::fabs(q[1] - lg(train_mnk[3 * i + 1])) +
+               std::fabs(q[2] - lg(train_mnk[3 * i + 2]));
+}
+
+}  // namespace
+
 FF_EXPORT int ptune_nearest(int ntrain, const int64_t* train_mnk, int64_t M, int64_t N, int64_t K)
 {
     if (ntrain < 1 || train_mnk == nullptr) return FF_ERR_ARG;
-    auto lg = [](int64_t x) { return std::log2((double)std::max<int64_t>(1, x)); };
-    const double q[3] = {lg(M), lg(N), lg(K)};
+    std::vector<double> d;
+    shape_distances(ntrain, train_mnk, M, N, K, d);
     int best = 0;
-    double bd = kInf;
-    for (int i = 0; i < ntrain; ++i) {
-        const double d = std::fabs(q[0] - lg(train_mnk[3 * i])) + std::fabs(q[1] - lg(train_mnk[3 * i + 1])) +
-                         std::fabs(q[2] - lg(train_mnk[3 * i + 2]));
-        if (d < bd) {
-            bd = d;
-            best = i;
+    for (int i = 1; i < ntrain; ++i)
+        if (d[i] < d[best]) best = i;
+    return best;
+}
+
+FF_EXPORT int ptune_dispatch(int ntrain, const int64_t* train_mnk, int k, const int* members, const double* cost,
+                             int64_t M, int64_t N, int64_t K)
+{
+    if (ntrain < 1 || train_mnk == nullptr || k < 1 || members == nullptr || cost == nullptr) return FF_ERR_ARG;
+    std::vector<double> d;
+    shape_distances(ntrain, train_mnk, M, N, K, d);
+    const double dmin = *std::min_element(d.begin(), d.end());
+    int bj = -1;
+    double bs = kInf;
+    for (int j = 0; j < k; ++j) {
+        double sum = 0.0;
+        for (int i = 0; i < ntrain; ++i)
+            if (d[i] <= dmin + 1e-9) sum += cost[(size_t)i * k + j];
+        if (bj < 0 || sum < bs) {
+            bj = j;
+            bs = sum;
         }
     }
-    return best;
+    if (bs == kInf) {
+        // No member is finite on every nearest shape: the member that is
+        // finite on the first nearest shape with the lowest cost there.
+        int i0 = 0;
+        while (d[i0] > dmin + 1e-9) ++i0;
+        bj = 0;
+        for (int j = 1; j < k; ++j)
+            if (cost[(size_t)i0 * k + j] < cost[(size_t)i0 * k + bj]) bj = j;
+    }
+    return members[bj];
 }

@@ -14,6 +14,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <fstream>
 #include <map>
@@ -53,21 +54,22 @@ int hip_fail(hipError_t e, const char* what)
 struct Variant {
     int id = -1;
     std::string name;
-    int mwg = 0, nwg = 0, kwg = 0, mi = 0, wm = 0, wn = 0, sk = 0, vw = 0, lds = 0, gm = 0;
+    int mwg = 0, nwg = 0, kwg = 0, mi = 0, wm = 0, wn = 0, sk = 0, vw = 0, lds = 0, gm = 0, sg = 0;
     hipModule_t mod = nullptr;
     hipFunction_t fvec = nullptr;  // VW-wide loads
     hipFunction_t fsca = nullptr;  // scalar loads
     int threads() const { return 64 * wm * wn * sk; }
 };
 
-// "<id> <name> MWG NWG KWG MI WM WN SK VW LDS GM"
+// "<id> <name> MWG NWG KWG MI WM WN SK VW LDS GM SG"
 bool parse_descriptor(std::istringstream& is, Variant& v)
 {
-    if (!(is >> v.id >> v.name >> v.mwg >> v.nwg >> v.kwg >> v.mi >> v.wm >> v.wn >> v.sk >> v.vw >> v.lds >> v.gm))
+    if (!(is >> v.id >> v.name >> v.mwg >> v.nwg >> v.kwg >> v.mi >> v.wm >> v.wn >> v.sk >> v.vw >> v.lds >> v.gm >>
+          v.sg))
         return false;
     if (v.id < 0 || v.mwg <= 0 || v.nwg <= 0 || v.kwg <= 0 || (v.mi != 16 && v.mi != 32) || v.wm <= 0 ||
         v.wn <= 0 || v.sk <= 0 || (v.vw != 1 && v.vw != 2 && v.vw != 4) || (v.lds != 0 && v.lds != 1) ||
-        v.gm <= 0 || v.threads() > 1024)
+        v.gm <= 0 || v.sg < 1 || v.sg > 64 || v.threads() > 1024)
         return false;
     for (char c : v.name)
         if (!(isalnum((unsigned char)c) || c == '_')) return false;
@@ -79,11 +81,38 @@ struct VarSet {
     std::vector<std::array<int64_t, 3>> shapes;  // training shapes, file order
     std::vector<int64_t> flat;                   // the same, as M,N,K triples
     std::vector<int> winners;                    // member chosen per training shape
+    std::vector<double> cost;                    // ntrain x k log-slowdowns of the members
 };
 
 std::mutex g_mu;
 std::map<int, std::shared_ptr<Variant>> g_variants;
 std::shared_ptr<const VarSet> g_set;
+
+// Workspace of the K-split variants: one M x N slice of partial products per
+// split, per device.  Allocated once, when the first K-split variant is
+// registered on that device (never inside sgemm()).
+constexpr size_t kWsBytes = size_t(128) << 20;
+constexpr int kMaxDevices = 16;
+struct Workspace {
+    float* ws = nullptr;
+};
+Workspace g_ws[kMaxDevices];
+
+int ensure_workspace()
+{
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    if (dev < 0 || dev >= kMaxDevices) return fail(FF_ERR_ARG, "device %d beyond the supported %d", dev, kMaxDevices);
+    Workspace& w = g_ws[dev];
+    if (w.ws != nullptr) return FF_OK;
+    e = hipMalloc(&w.ws, kWsBytes);
+    if (e != hipSuccess) {
+        w = Workspace{};
+        return hip_fail(e, "allocate split-K workspace");
+    }
+    return FF_OK;
+}
 
 int load_code_object(Variant& v, const std::string& path)
 {
@@ -121,6 +150,10 @@ int register_variant(const Variant& d, const std::string& dir)
     auto v = std::make_shared<Variant>(d);
     int rc = load_code_object(*v, dir + "/" + d.name + ".co");
     if (rc != FF_OK) return rc;
+    if (d.sg > 1) {
+        rc = ensure_workspace();
+        if (rc != FF_OK) return rc;
+    }
     g_variants[d.id] = v;
     return FF_OK;
 }
@@ -191,6 +224,34 @@ int launch_scale(int64_t M, int64_t N, float beta, float* C, int64_t ldc, hipStr
 
 bool aligned_for(const void* p, int vw) { return (reinterpret_cast<uintptr_t>(p) % (4u * vw)) == 0; }
 
+// C = alpha * sum_{q < splits} P[q] + beta * C, P[q] the q-th M x N slice of
+// partial products; the splits are added in index order (deterministic).
+// Each thread handles four consecutive columns of one row.
+__global__ void __launch_bounds__(256)
+ff_splitk_reduce(int64_t M, int64_t N, int splits, const float* __restrict__ P, float alpha, float beta,
+                 float* __restrict__ C, int64_t ldc)
+{
+    const int64_t nq = (N + 3) / 4;
+    const int64_t total = M * nq;
+    const int64_t slice = M * N;
+    for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
+         idx += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t i = idx / nq, j0 = (idx - i * nq) * 4;
+        const int w = (int)std::min<int64_t>(4, N - j0);
+        float s[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+        for (int q = 0; q < splits; ++q) {
+            const float* p = P + q * slice + i * N + j0;
+            for (int c = 0; c < w; ++c) s[c] += p[c];
+        }
+        float* crow = C + i * ldc + j0;
+        for (int c = 0; c < w; ++c) {
+            float o = alpha * s[c];
+            if (beta != 0.0f) o += beta * crow[c];
+            crow[c] = o;
+        }
+    }
+}
+
 int launch_variant(const Variant& v, int64_t M, int64_t N, int64_t K, float alpha, const float* A,
                    int64_t lda, const float* B, int64_t ldb, float beta, float* C, int64_t ldc, hipStream_t s)
 {
@@ -203,11 +264,40 @@ int launch_variant(const Variant& v, int64_t M, int64_t N, int64_t K, float alph
     const bool vec = w > 1 && K % w == 0 && N % w == 0 && lda % w == 0 && ldb % w == 0 && aligned_for(A, w) &&
                      aligned_for(B, w);
     hipFunction_t f = vec ? v.fvec : v.fsca;
+    // K split over work-groups: as many as the variant allows, no more than
+    // there are slabs, every split non-empty, and within the workspace.
+    const int64_t nkt = (K + v.kwg - 1) / v.kwg;
+    int splits = 1;
+    float* ws = nullptr;
+    if (v.sg > 1 && nkt > 1) {
+        int dev = 0;
+        if (hipGetDevice(&dev) == hipSuccess && dev >= 0 && dev < kMaxDevices && g_ws[dev].ws != nullptr) {
+            int64_t sp = std::min<int64_t>(v.sg, nkt);
+            sp = std::min<int64_t>(sp, (int64_t)(kWsBytes / (size_t)(M * N * 4)));
+            if (sp >= 2 && nb * sp <= INT32_MAX) {
+                const int64_t per = (nkt + sp - 1) / sp;
+                splits = (int)((nkt + per - 1) / per);
+                ws = g_ws[dev].ws;
+            }
+        }
+    }
+    int kper = (int)((nkt + splits - 1) / splits);
     int Mi = (int)M, Ni = (int)N, Ki = (int)K;
     long la = (long)lda, lb = (long)ldb, lc = (long)ldc;
-    void* args[] = {&Mi, &Ni, &Ki, &alpha, (void*)&A, &la, (void*)&B, &lb, &beta, (void*)&C, &lc};
-    hipError_t e = hipModuleLaunchKernel(f, (unsigned)nb, 1, 1, (unsigned)v.threads(), 1, 1, 0, s, args, nullptr);
-    return e == hipSuccess ? FF_OK : hip_fail(e, ("launch " + v.name).c_str());
+    void* args[] = {&Mi, &Ni, &Ki, &alpha, (void*)&A, &la, (void*)&B, &lb, &beta, (void*)&C, &lc,
+                    (void*)&ws, &splits, &kper};
+    hipError_t e = hipModuleLaunchKernel(f, (unsigned)(nb * splits), 1, 1, (unsigned)v.threads(), 1, 1, 0, s, args,
+                                         nullptr);
+    if (e != hipSuccess) return hip_fail(e, ("launch " + v.name).c_str());
+    if (splits > 1) {
+        const int64_t work = M * ((N + 3) / 4);
+        const int64_t blocks = std::min<int64_t>((work + 255) / 256, 8192);
+        hipLaunchKernelGGL(ff_splitk_reduce, dim3((unsigned)blocks), dim3(256), 0, s, M, N, splits,
+                           (const float*)ws, alpha, beta, C, ldc);
+        e = hipGetLastError();
+        if (e != hipSuccess) return hip_fail(e, "launch split-K reduction");
+    }
+    return FF_OK;
 }
 
 // Shared body of sgemm() and sgemm_variant(); `v` may be null for the
@@ -360,8 +450,8 @@ FF_EXPORT int variant_info(int id, char* buf, size_t len)
     auto v = find_variant(id);
     if (!v) return fail(FF_ERR_VARIANT, "variant %d not registered", id);
     char tmp[512];
-    int n = snprintf(tmp, sizeof tmp, "%d %s %d %d %d %d %d %d %d %d %d %d", v->id, v->name.c_str(), v->mwg,
-                     v->nwg, v->kwg, v->mi, v->wm, v->wn, v->sk, v->vw, v->lds, v->gm);
+    int n = snprintf(tmp, sizeof tmp, "%d %s %d %d %d %d %d %d %d %d %d %d %d", v->id, v->name.c_str(), v->mwg,
+                     v->nwg, v->kwg, v->mi, v->wm, v->wn, v->sk, v->vw, v->lds, v->gm, v->sg);
     if (buf && len > 0) {
         size_t c = std::min(len - 1, (size_t)n);
         memcpy(buf, tmp, c);
@@ -375,7 +465,10 @@ FF_EXPORT int variant_info(int id, char* buf, size_t len)
 //   arch <gfx name>
 //   codedir <dir>          code objects, relative to the set file's directory
 //   variant <descriptor>   k lines, descriptor as in the manifest
-//   rule <M> <N> <K> <id>  one line per training shape, id must be a member
+//   rule <M> <N> <K> <id> <c_1> ... <c_k>
+//                          one line per training shape (after the variant
+//                          lines): its winner, a member, and every member's
+//                          log-slowdown on it ("inf" where it failed)
 //   end
 FF_EXPORT int variant_set_load(const char* path)
 {
@@ -412,6 +505,8 @@ FF_EXPORT int variant_set_load(const char* path)
             if (!parse_descriptor(is, v)) return fail(FF_ERR_PARSE, "%s:%d: bad variant descriptor", path, lineno);
             for (const Variant& o : members)
                 if (o.id == v.id) return fail(FF_ERR_PARSE, "%s:%d: duplicate variant %d", path, lineno, v.id);
+            if (!set->shapes.empty())
+                return fail(FF_ERR_PARSE, "%s:%d: variant lines must precede the rules", path, lineno);
             members.push_back(v);
             set->ids.push_back(v.id);
         } else if (key == "rule") {
@@ -419,11 +514,24 @@ FF_EXPORT int variant_set_load(const char* path)
             int id;
             if (!(is >> m >> n >> k >> id) || m < 1 || n < 1 || k < 1)
                 return fail(FF_ERR_PARSE, "%s:%d: bad rule", path, lineno);
-            if (std::find(set->ids.begin(), set->ids.end(), id) == set->ids.end())
+            const auto pos = std::find(set->ids.begin(), set->ids.end(), id);
+            if (pos == set->ids.end())
                 return fail(FF_ERR_PARSE, "%s:%d: rule names variant %d outside the set", path, lineno, id);
+            std::vector<double> c(set->ids.size());
+            for (size_t j = 0; j < c.size(); ++j) {
+                std::string tok;
+                if (!(is >> tok)) return fail(FF_ERR_PARSE, "%s:%d: rule needs %zu member costs", path, lineno, c.size());
+                char* end = nullptr;
+                c[j] = (tok == "inf") ? INFINITY : std::strtod(tok.c_str(), &end);
+                if (tok != "inf" && (end == tok.c_str() || *end != '\0' || !(c[j] >= 0.0)))
+                    return fail(FF_ERR_PARSE, "%s:%d: bad member cost '%s'", path, lineno, tok.c_str());
+            }
+            if (c[pos - set->ids.begin()] != *std::min_element(c.begin(), c.end()))
+                return fail(FF_ERR_PARSE, "%s:%d: rule winner is not the cheapest member", path, lineno);
             set->shapes.push_back({m, n, k});
             set->flat.insert(set->flat.end(), {(int64_t)m, (int64_t)n, (int64_t)k});
             set->winners.push_back(id);
+            set->cost.insert(set->cost.end(), c.begin(), c.end());
         } else if (key == "end") {
             ended = true;
         } else {
@@ -462,9 +570,10 @@ FF_EXPORT int variant_select(int64_t M, int64_t N, int64_t K)
         set = g_set;
     }
     if (!set) return fail(FF_ERR_NO_SET, "no variant set loaded");
-    const int best = ptune_nearest((int)set->shapes.size(), set->flat.data(), M, N, K);
-    if (best < 0) return fail(FF_ERR_NO_SET, "variant set has no training shapes");
-    return set->winners[best];
+    const int id = ptune_dispatch((int)set->shapes.size(), set->flat.data(), (int)set->ids.size(), set->ids.data(),
+                                  set->cost.data(), M, N, K);
+    if (id < 0) return fail(FF_ERR_NO_SET, "variant set has no training shapes");
+    return id;
 }
 
 FF_EXPORT int sgemm(int64_t M, int64_t N, int64_t K, float alpha, const float* A, int64_t lda, const float* B,

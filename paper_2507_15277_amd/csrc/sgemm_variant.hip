@@ -22,6 +22,13 @@
 //                    waves; 0: each wave loads its own operands straight from
 //                    global memory into registers (no LDS, no barriers)
 //   FF_GM            tile-order group height (tiles of M per group)
+//   FF_SG            largest number of work-groups that split one tile's K
+//                    range (1: no split).  The runtime passes the split count
+//                    actually used (<= FF_SG); with more than one split each
+//                    work-group writes its raw partial product (row-major,
+//                    M x N per split) to a workspace instead of C, and a
+//                    separate reduction kernel of the runtime sums the splits
+//                    in a fixed order (deterministic) and applies alpha, beta
 //   FF_NAME          kernel symbol; a second kernel FF_NAME##_v1 is the same
 //                    configuration with scalar loads, for operands whose
 //                    alignment or leading dimension rules out vector loads
@@ -57,6 +64,7 @@
 #define FF_VW 4
 #define FF_LDS 1
 #define FF_GM 8
+#define FF_SG 1
 #define FF_NAME sgemm_m64n64k16_i32_w2x2_s1_v4_l1
 #endif
 
@@ -66,7 +74,7 @@
 namespace {
 
 constexpr int MWG = FF_MWG, NWG = FF_NWG, KWG = FF_KWG, MI = FF_MI;
-constexpr int WM = FF_WM, WN = FF_WN, SK = FF_SK, VW = FF_VW, GM = FF_GM;
+constexpr int WM = FF_WM, WN = FF_WN, SK = FF_SK, VW = FF_VW, GM = FF_GM, SG = FF_SG;
 constexpr bool USE_LDS = FF_LDS != 0;
 
 constexpr int MK = (MI == 32) ? 2 : 4;   // k per MFMA instruction
@@ -98,6 +106,7 @@ static_assert(KWG % (SK * MK) == 0, "slab must split over groups and MFMA k");
 static_assert(VW == 1 || VW == 2 || VW == 4, "vector width");
 static_assert(NT <= 1024, "work-group size");
 static_assert(KWG % 4 == 0 && NWG % 4 == 0, "LDS vector alignment");
+static_assert(SG >= 1, "split count");
 
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
@@ -148,17 +157,20 @@ __device__ __forceinline__ typename VecT<V>::T zsel(const typename VecT<V>::T& v
     return ok ? v : typename VecT<V>::T(0.0f);
 }
 
-// Work-group index -> (tile row, tile column).  Work-groups are handed to the
-// 8 XCDs round-robin; the first step renumbers them so that each XCD gets a
-// contiguous range of tiles, the second walks tiles in groups of GM tile rows
+// Work-group index -> (tile row, tile column, K split).  Work-groups are
+// handed to the 8 XCDs round-robin; the first step renumbers them so that
+// each XCD gets a contiguous range, whose consecutive entries are the splits
+// of one tile and then neighbouring tiles, walked in groups of GM tile rows
 // (column-major inside a group) so that neighbours share A rows and B
 // columns in the XCD's L2.
-__device__ __forceinline__ void tile_of(int bid, int nbm, int nbn, int& tm, int& tn)
+__device__ __forceinline__ void tile_of(int bid, int nbm, int nbn, int splits, int& tm, int& tn, int& part)
 {
-    const int nb = nbm * nbn;
+    const int nb = nbm * nbn * splits;
     const int q = nb >> 3, r = nb & 7;
     const int x = bid & 7, i = bid >> 3;
-    const int lin = (x < r) ? x * (q + 1) + i : r * (q + 1) + (x - r) * q + i;
+    const int lin2 = (x < r) ? x * (q + 1) + i : r * (q + 1) + (x - r) * q + i;
+    const int lin = lin2 / splits;
+    part = lin2 - lin * splits;
     const int width = GM * nbn;
     const int grp = lin / width;
     const int first = grp * GM;
@@ -173,11 +185,11 @@ __device__ __forceinline__ void gemm_body(int M, int N, int K, float alpha,
                                           const float* __restrict__ A, long lda,
                                           const float* __restrict__ B, long ldb,
                                           float beta, float* __restrict__ C, long ldc,
-                                          float* smem)
+                                          float* __restrict__ ws, int splits, int kper, float* smem)
 {
     const int nbm = (M + MWG - 1) / MWG, nbn = (N + NWG - 1) / NWG;
-    int tm, tn;
-    tile_of(blockIdx.x, nbm, nbn, tm, tn);
+    int tm, tn, part;
+    tile_of(blockIdx.x, nbm, nbn, SG > 1 ? splits : 1, tm, tn, part);
     const int m0 = tm * MWG, n0 = tn * NWG;
 
     const int tid = threadIdx.x;
@@ -198,6 +210,9 @@ __device__ __forceinline__ void gemm_body(int M, int N, int K, float alpha,
             acc[i][j] = acc_t{};
 
     const int nkt = (K + KWG - 1) / KWG;
+    // This work-group's slabs [kt0, kt1): all of K unless the tile is split.
+    const int kt0 = (SG > 1) ? part * kper : 0;
+    const int kt1 = (SG > 1) ? min(nkt, kt0 + kper) : nkt;
 
     if constexpr (USE_LDS) {
         // ---- cooperative slab loads: global -> registers -> LDS ----------
@@ -258,15 +273,15 @@ __device__ __forceinline__ void gemm_body(int M, int N, int K, float alpha,
             }
         };
 
-        gload(0);
+        gload(kt0);
         sstore(0);
         __syncthreads();
 
         const int arow0 = (wm * WTM + lr) * LDA_S + kg0;
         const int bcol0 = wn * WTN + lr;
-        for (int kt = 0; kt < nkt; ++kt) {
-            const int st = kt & 1;
-            if (kt + 1 < nkt) gload(kt + 1);
+        for (int kt = kt0; kt < kt1; ++kt) {
+            const int st = (kt - kt0) & 1;
+            if (kt + 1 < kt1) gload(kt + 1);
             const float* sA = sA0 + st * STAGE_FLOATS;
             const float* sB = sB0 + st * STAGE_FLOATS;
 #pragma unroll
@@ -290,7 +305,7 @@ __device__ __forceinline__ void gemm_body(int M, int N, int K, float alpha,
                             acc[i][j] = mfma(bv[j], vget<AV>(av[i], t), acc[i][j]);
                 }
             }
-            if (kt + 1 < nkt) sstore(st ^ 1);
+            if (kt + 1 < kt1) sstore(st ^ 1);
             __syncthreads();
         }
     } else {
@@ -329,14 +344,14 @@ __device__ __forceinline__ void gemm_body(int M, int N, int K, float alpha,
             }
         };
 
-        gload(0, 0);
-        for (int kt = 0; kt < nkt; kt += 2) {
+        gload(kt0, 0);
+        for (int kt = kt0; kt < kt1; kt += 2) {
             // Two slabs per trip so that the register buffers are indexed by
             // constants after unrolling.
 #pragma unroll
             for (int b = 0; b < 2; ++b) {
-                if (kt + b < nkt) {
-                    if (kt + b + 1 < nkt) gload(kt + b + 1, b ^ 1);
+                if (kt + b < kt1) {
+                    if (kt + b + 1 < kt1) gload(kt + b + 1, b ^ 1);
 #pragma unroll
                     for (int s = 0; s < S; ++s) {
 #pragma unroll
@@ -367,7 +382,7 @@ __device__ __forceinline__ void gemm_body(int M, int N, int K, float alpha,
                         dst[((i * RN + j) * ACC + e) * 64 + lane] = acc[i][j][e];
         }
         __syncthreads();
-        if (grp > 0) return;
+        if (grp == 0) {
 #pragma unroll
         for (int g = 1; g < SK; ++g) {
             const float* src = smem + ((g - 1) * (WM * WN) + wq) * PER_WAVE;
@@ -379,9 +394,22 @@ __device__ __forceinline__ void gemm_body(int M, int N, int K, float alpha,
                     for (int e = 0; e < ACC; ++e)
                         acc[i][j][e] += src[((i * RN + j) * ACC + e) * 64 + lane];
         }
+        }
     }
 
+    if (grp > 0) return;
+
     // ---- epilogue: C = alpha*acc + beta*C ----------------------------------
+    // With the K range split over work-groups the raw partial goes to this
+    // split's M x N slice of the workspace instead (alpha 1, beta 0).
+    if constexpr (SG > 1) {
+        if (splits > 1) {
+            C = ws + (size_t)part * (size_t)M * (size_t)N;
+            ldc = N;
+            alpha = 1.0f;
+            beta = 0.0f;
+        }
+    }
     // Lane holds row m0+wm*WTM+i*MI+lr and, per group of 4 accumulators, the
     // columns n0+wn*WTN+j*MI + (MI==32 ? 8*g : 0) + 4*lh + {0,1,2,3}.
     const bool cvec = ((reinterpret_cast<uintptr_t>(C) & 15) == 0) && ((ldc & 3) == 0);
@@ -424,16 +452,18 @@ __device__ __forceinline__ void gemm_body(int M, int N, int K, float alpha,
 
 extern "C" __global__ void __launch_bounds__(NT)
 FF_NAME(int M, int N, int K, float alpha, const float* __restrict__ A, long lda,
-        const float* __restrict__ B, long ldb, float beta, float* __restrict__ C, long ldc)
+        const float* __restrict__ B, long ldb, float beta, float* __restrict__ C, long ldc,
+        float* __restrict__ ws, int splits, int kper)
 {
     __shared__ __attribute__((aligned(16))) float smem[LDS_FLOATS];
-    gemm_body<VW>(M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, smem);
+    gemm_body<VW>(M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, ws, splits, kper, smem);
 }
 
 extern "C" __global__ void __launch_bounds__(NT)
 FF_CAT(FF_NAME, _v1)(int M, int N, int K, float alpha, const float* __restrict__ A, long lda,
-                     const float* __restrict__ B, long ldb, float beta, float* __restrict__ C, long ldc)
+                     const float* __restrict__ B, long ldb, float beta, float* __restrict__ C, long ldc,
+                     float* __restrict__ ws, int splits, int kper)
 {
     __shared__ __attribute__((aligned(16))) float smem[LDS_FLOATS];
-    gemm_body<1>(M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, smem);
+    gemm_body<1>(M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, ws, splits, kper, smem);
 }

@@ -8,7 +8,9 @@ Steps (Sec. IV, Sec. V-C, Sec. V-E), all arithmetic in libfewfit:
   Eq. 1 over the training shapes (exhaustive where feasible, greedy + swap
   otherwise);
 * the dispatch table for the set file: the in-set winner of each training
-  shape; unseen shapes go to the nearest training shape;
+  shape and every member's log-slowdown there; an unseen shape goes to the
+  member with the smallest summed log-slowdown over its nearest training
+  shapes (``ptune_dispatch``);
 * evaluation (Sec. V-E figures of merit): fraction of the per-shape best
   (1 / slowdown-over-best, geometric mean) on the held-out shapes as
   realised by the dispatch rule, and over all 27 shapes with a perfect
@@ -70,21 +72,33 @@ def tflops(shape, ms):
     return 2.0 * M * N * K / ms / 1e9
 
 
-def evaluate(t, shapes, train_idx, kappa):
+def member_costs(t, kappa, train_idx):
+    """ntrain x k matrix of ln(t[member][shape] / best[shape])."""
+    best, _, _, _, _ = abi.ptune_postprocess(t)
+    c = np.full((len(train_idx), len(kappa)), np.inf)
+    for i, s in enumerate(train_idx):
+        for j, v in enumerate(kappa):
+            if np.isfinite(t[v, s]):
+                c[i, j] = math.log(t[v, s] / best[s])
+    return c
+
+
+def evaluate(t, shapes, train_idx, kappa, extra=()):
     """Figures of merit of one set on the grid."""
     best, _, _, _, _ = abi.ptune_postprocess(t)
     train = [shapes[j] for j in train_idx]
     winners = abi.ptune_assign(t, kappa, train_idx)
+    costs = member_costs(t, kappa, train_idx)
     held_idx = [j for j in range(len(shapes)) if j not in set(train_idx)]
     realised = {}
     for j, s in enumerate(shapes):
-        i = abi.ptune_nearest(train, *s)
-        realised[j] = winners[i]
+        realised[j] = abi.ptune_dispatch(train, kappa, costs, *s)
     frac = lambda idx, pick: geomean(best[j] / t[pick(j), j] for j in idx)  # noqa: E731
     in_set = lambda j: min(kappa, key=lambda v: (t[v, j], v))  # noqa: E731
     return {
         "kappa": list(kappa),
         "winners": winners,
+        "costs": costs.tolist(),
         "frac_heldout_realised": frac(held_idx, lambda j: realised[j]),
         "frac_heldout_inset": frac(held_idx, in_set),
         "frac_train": frac(train_idx, in_set),
@@ -141,7 +155,8 @@ def run(table=TABLE, write_sets=False, splits=5, log=print):
             f"geomean {ev['geomean_tflops_realised']:.2f} TFLOP/s ({evals} subsets, {dt:.2f} s)")
         if write_sets:
             members = [(v, variants[v]) for v in kappa]
-            rules = [(*shapes[j], w) for j, w in zip(train_idx, ev["winners"])]
+            rules = [(*shapes[j], w, ev["costs"][i])
+                     for i, (j, w) in enumerate(zip(train_idx, ev["winners"]))]
             tuned.write_set_file(
                 tuned.set_path(k), members, rules,
                 comments=(f"PortabilityTune k={k} on the 14 checkerboard training shapes of the "
@@ -166,7 +181,7 @@ def run(table=TABLE, write_sets=False, splits=5, log=print):
         for k in KS:
             ev = report["sets"][str(k)]
             trs = [shapes[j] for j in train_idx]
-            picks = [ev["winners"][abi.ptune_nearest(trs, *s)] for s in extra_shapes]
+            picks = [abi.ptune_dispatch(trs, ev["kappa"], ev["costs"], *s) for s in extra_shapes]
             ex[f"k{k}"] = [float(be[j] / te[p, j]) for j, p in enumerate(picks)]
         report["default_example_shapes"] = {"shapes": extra_shapes, "frac_of_best": ex}
     # Square sweep (beta 0 and 0.5): per-shape best and whether beta moves it.

@@ -11,7 +11,8 @@ set and a seeded sample stratified by work-group tile shape.
 Axes (names match the kernel's FF_* macros):
   MWG, NWG  work-group tile; KWG slab depth; MI MFMA block edge (32: 32x32x2,
   16: 16x16x4); WM x WN wave grid; SK intra-work-group split of K; VW
-  global-load vector width; LDS staging on/off; GM tile-order group height.
+  global-load vector width; LDS staging on/off; GM tile-order group height;
+  SG largest number of work-groups splitting one tile's K range.
 """
 from __future__ import annotations
 
@@ -41,6 +42,7 @@ class Variant:
     vw: int
     lds: int
     gm: int = 8
+    sg: int = 1
 
     @property
     def mk(self):
@@ -77,17 +79,21 @@ class Variant:
     def name(self):
         n = (f"sgemm_m{self.mwg}n{self.nwg}k{self.kwg}_i{self.mi}_w{self.wm}x{self.wn}"
              f"_s{self.sk}_v{self.vw}_l{self.lds}")
-        return n if self.gm == 8 else n + f"_g{self.gm}"
+        if self.gm != 8:
+            n += f"_g{self.gm}"
+        if self.sg != 1:
+            n += f"_p{self.sg}"
+        return n
 
     def defines(self):
         return {"FF_MWG": self.mwg, "FF_NWG": self.nwg, "FF_KWG": self.kwg, "FF_MI": self.mi,
                 "FF_WM": self.wm, "FF_WN": self.wn, "FF_SK": self.sk, "FF_VW": self.vw,
-                "FF_LDS": self.lds, "FF_GM": self.gm, "FF_NAME": self.name}
+                "FF_LDS": self.lds, "FF_GM": self.gm, "FF_SG": self.sg, "FF_NAME": self.name}
 
     def descriptor(self, vid):
-        """Manifest / set-file descriptor: id name MWG NWG KWG MI WM WN SK VW LDS GM."""
+        """Manifest / set-file descriptor: id name MWG NWG KWG MI WM WN SK VW LDS GM SG."""
         return (f"{vid} {self.name} {self.mwg} {self.nwg} {self.kwg} {self.mi} {self.wm} {self.wn} "
-                f"{self.sk} {self.vw} {self.lds} {self.gm}")
+                f"{self.sk} {self.vw} {self.lds} {self.gm} {self.sg}")
 
     def as_dict(self):
         return asdict(self)
@@ -96,6 +102,8 @@ class Variant:
 def legal(v: Variant) -> bool:
     """Constraints of the kernel template plus resource budgets."""
     if v.mi not in (16, 32) or v.vw not in (1, 2, 4) or v.lds not in (0, 1):
+        return False
+    if v.sg not in SPLITS:
         return False
     if v.mwg % (v.wm * v.mi) or v.nwg % (v.wn * v.mi):
         return False
@@ -115,14 +123,16 @@ def legal(v: Variant) -> bool:
 
 
 TILES = (16, 32, 64, 128, 256)
+SPLITS = (1, 2, 4, 8, 16)
 
 
 def enumerate_space():
     """All legal configurations, in a fixed order."""
     out = []
-    for mi, mwg, nwg, kwg, wm, wn, sk, vw, lds in itertools.product(
-            (32, 16), TILES, TILES, (8, 16, 32), (1, 2, 4), (1, 2, 4), (1, 2, 4), (1, 2, 4), (1, 0)):
-        v = Variant(mwg, nwg, kwg, mi, wm, wn, sk, vw, lds)
+    for mi, mwg, nwg, kwg, wm, wn, sk, vw, lds, sg in itertools.product(
+            (32, 16), TILES, TILES, (8, 16, 32), (1, 2, 4), (1, 2, 4), (1, 2, 4), (1, 2, 4), (1, 0),
+            SPLITS):
+        v = Variant(mwg, nwg, kwg, mi, wm, wn, sk, vw, lds, 8, sg)
         if legal(v):
             out.append(v)
     return out
@@ -155,10 +165,26 @@ HAND = [
     Variant(32, 32, 16, 32, 1, 1, 1, 4, 0),
     Variant(64, 64, 16, 32, 2, 2, 1, 4, 0),
     Variant(128, 128, 16, 16, 2, 2, 1, 4, 1),
+    # K split over work-groups, for shapes with few tiles and long K.
+    Variant(64, 64, 32, 32, 2, 2, 2, 4, 1, sg=2),
+    Variant(64, 64, 32, 32, 2, 2, 2, 4, 1, sg=4),
+    Variant(64, 64, 32, 32, 2, 2, 2, 4, 1, sg=8),
+    Variant(64, 64, 16, 32, 2, 2, 1, 4, 1, sg=4),
+    Variant(32, 32, 32, 32, 1, 1, 4, 4, 1, sg=4),
+    Variant(32, 32, 32, 32, 1, 1, 4, 4, 1, sg=8),
+    Variant(32, 32, 32, 32, 1, 1, 4, 4, 1, sg=16),
+    Variant(16, 16, 32, 16, 1, 1, 2, 4, 0, sg=4),
+    Variant(16, 16, 32, 16, 1, 1, 2, 4, 0, sg=16),
+    Variant(128, 128, 16, 32, 2, 2, 1, 4, 1, sg=2),
+    Variant(128, 128, 16, 32, 2, 2, 1, 4, 1, sg=4),
+    Variant(256, 128, 16, 32, 4, 2, 1, 4, 1, sg=2),
+    Variant(128, 64, 16, 32, 2, 2, 1, 4, 1, sg=4),
+    Variant(64, 32, 32, 16, 2, 1, 2, 4, 1, sg=4),
+    Variant(64, 32, 32, 16, 2, 1, 2, 4, 1, sg=8),
 ]
 
 
-def family(n=200, seed=0):
+def family(n=300, seed=0):
     """The compiled family: DEFAULT, HAND, then a seeded sample stratified by
     (MWG, NWG) tile shape, up to ``n`` variants.  Deterministic for a seed."""
     space = enumerate_space()

@@ -8,9 +8,13 @@ variants for a set of inputs) together with the online dispatch table
     fewfit-set 1
     arch gfx950
     codedir ../variants
-    variant <id> <name> MWG NWG KWG MI WM WN SK VW LDS GM     (k lines)
-    rule <M> <N> <K> <id>                                  (training shapes)
+    variant <id> <name> MWG NWG KWG MI WM WN SK VW LDS GM SG    (k lines)
+    rule <M> <N> <K> <id> <c_1> ... <c_k>                    (training shapes)
     end
+
+A rule names the training shape's winner and every member's log-slowdown
+there (ln(t / best), "inf" where the member failed); the runtime uses these
+to pick a member for shapes between training shapes.
 """
 from __future__ import annotations
 
@@ -34,16 +38,21 @@ def default_set_path() -> str:
     return p if os.path.exists(p) else FIXED_SET
 
 
+def _fmt_cost(c):
+    return "inf" if c == float("inf") else f"{c:.17g}"
+
+
 def write_set_file(path, members, rules, arch="gfx950", codedir="../variants", comments=()):
-    """members: [(id, space.Variant)]; rules: [(M, N, K, id)]."""
-    ids = {vid for vid, _ in members}
+    """members: [(id, space.Variant)]; rules: [(M, N, K, winner_id, [cost per member])]."""
+    ids = [vid for vid, _ in members]
     for r in rules:
-        if r[3] not in ids:
-            raise ValueError(f"rule {r} names a variant outside the set")
+        if r[3] not in ids or len(r[4]) != len(ids):
+            raise ValueError(f"rule {r[:4]} does not match the set")
     lines = [f"# {c}" for c in comments]
     lines += ["fewfit-set 1", f"arch {arch}", f"codedir {codedir}"]
     lines += [f"variant {v.descriptor(vid)}" for vid, v in members]
-    lines += [f"rule {M} {N} {K} {vid}" for (M, N, K, vid) in rules]
+    lines += [f"rule {M} {N} {K} {vid} " + " ".join(_fmt_cost(c) for c in cost)
+              for (M, N, K, vid, cost) in rules]
     lines.append("end")
     os.makedirs(os.path.dirname(path), exist_ok=True)
     tmp = path + ".tmp"
@@ -54,5 +63,5 @@ def write_set_file(path, members, rules, arch="gfx950", codedir="../variants", c
 
 def write_fixed_set():
     """The one-variant set of the fixed 64x64 / K-step 16 kernel (id 0)."""
-    write_set_file(FIXED_SET, [(0, space.DEFAULT)], [(256, 256, 256, 0)],
+    write_set_file(FIXED_SET, [(0, space.DEFAULT)], [(256, 256, 256, 0, [0.0])],
                    comments=("single fixed variant: 64x64 tile, K-step 16",))

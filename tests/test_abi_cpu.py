@@ -84,13 +84,16 @@ GOOD_VARIANT = space.DEFAULT.descriptor(0)
 @pytest.mark.parametrize("body,code", [
     ("", abi.FF_ERR_PARSE),
     ("fewfit-set 2\n", abi.FF_ERR_PARSE),
-    ("fewfit-set 1\narch gfx950\ncodedir .\nvariant 0 bad\nrule 1 1 1 0\nend\n", abi.FF_ERR_PARSE),
-    (f"fewfit-set 1\narch gfx950\ncodedir .\nvariant {GOOD_VARIANT}\nrule 1 1 1 5\nend\n", abi.FF_ERR_PARSE),
-    (f"fewfit-set 1\narch gfx950\ncodedir .\nvariant {GOOD_VARIANT}\nrule 1 1 1 0\n", abi.FF_ERR_PARSE),
+    ("fewfit-set 1\narch gfx950\ncodedir .\nvariant 0 bad\nrule 1 1 1 0 0\nend\n", abi.FF_ERR_PARSE),
+    (f"fewfit-set 1\narch gfx950\ncodedir .\nvariant {GOOD_VARIANT}\nrule 1 1 1 5 0\nend\n", abi.FF_ERR_PARSE),
+    (f"fewfit-set 1\narch gfx950\ncodedir .\nvariant {GOOD_VARIANT}\nrule 1 1 1 0 0\n", abi.FF_ERR_PARSE),
     (f"fewfit-set 1\narch gfx950\ncodedir .\nvariant {GOOD_VARIANT}\nend\n", abi.FF_ERR_PARSE),
     (f"fewfit-set 1\narch gfx950\ncodedir .\nvariant {GOOD_VARIANT}\nvariant {GOOD_VARIANT}\n"
-     "rule 1 1 1 0\nend\n", abi.FF_ERR_PARSE),
-    (f"fewfit-set 1\narch gfx950\ncodedir .\nvariant {GOOD_VARIANT}\nrule 1 1 1 0 9\nend\n", abi.FF_ERR_PARSE),
+     "rule 1 1 1 0 0 0\nend\n", abi.FF_ERR_PARSE),
+    (f"fewfit-set 1\narch gfx950\ncodedir .\nvariant {GOOD_VARIANT}\nrule 1 1 1 0 0 9\nend\n", abi.FF_ERR_PARSE),
+    (f"fewfit-set 1\narch gfx950\ncodedir .\nvariant {GOOD_VARIANT}\nrule 1 1 1 0\nend\n", abi.FF_ERR_PARSE),
+    (f"fewfit-set 1\narch gfx950\ncodedir .\nvariant {GOOD_VARIANT}\nrule 1 1 1 0 -1\nend\n", abi.FF_ERR_PARSE),
+    (f"fewfit-set 1\narch gfx950\ncodedir .\nvariant {GOOD_VARIANT}\nrule 1 1 1 0 x\nend\n", abi.FF_ERR_PARSE),
     (f"fewfit-set 1\nfoo 1\nend\n", abi.FF_ERR_PARSE),
 ])
 def test_set_file_parse_errors(L, tmp_path, body, code):
@@ -173,6 +176,28 @@ def test_assign_matches_oracle():
     t = _rand_table(9, 9, 6, fail_frac=0.2)
     kap = (1, 4, 7)
     assert abi.ptune_assign(t, kap, [0, 2, 5]) == pr.assign_winners(t.tolist(), kap, [0, 2, 5])
+
+
+@pytest.mark.parametrize("seed", range(5))
+def test_dispatch_matches_oracle(seed):
+    from paper_2507_15277_amd import datagen
+    shapes = datagen.grid27()
+    if seed == 0:
+        train, _ = datagen.checkerboard_split()
+    else:
+        train, _ = datagen.random_split(seed, 14)
+    rng = np.random.default_rng([4, seed])
+    k = 4
+    members = sorted(rng.choice(50, k, replace=False).tolist())
+    cost = rng.exponential(0.3, (len(train), k))
+    cost[rng.random(cost.shape) < 0.1] = INF
+    for i in range(len(train)):
+        cost[i, rng.integers(k)] = 0.0      # each training shape has a winner
+    queries = shapes + [(512, 4096, 4096), (4096, 4096, 512), (1, 1, 1), (100, 3000, 77), (0, 5, 5)]
+    for q in queries:
+        assert abi.ptune_dispatch(train, members, cost, *q) == pr.dispatch(train, members, cost.tolist(), *q), q
+    for i, s in enumerate(train):
+        assert abi.ptune_nearest(train, *s) == i
 
 
 def test_select_argument_errors():

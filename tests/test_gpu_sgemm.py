@@ -201,3 +201,48 @@ def test_screen_kernels_agree_with_oracle(loaded):
     dC[3, 4] += 1.0                        # a planted wrong element is caught
     nbad, ratio = abi.screen_compare(M, N, dC, N, ref, tol)
     assert nbad == 1 and ratio > 1.0
+
+
+def _split_variants(loaded):
+    out = []
+    for vid, name in loaded:
+        desc = abi.variant_info(vid).split()
+        if int(desc[12]) > 1:
+            out.append((vid, name))
+    return out
+
+
+def test_k_split_variants_long_k(loaded):
+    # Long K over few tiles: every K-split variant splits here.  Two calls in
+    # a row must both be right (the arrival counters reset themselves) and
+    # bitwise equal (partials are summed in a fixed order).
+    M, N, K = 96, 80, 2000
+    A, B, C0 = datagen.gemm_operands(27, M, N, K, beta=0.75)
+    splits = _split_variants(loaded)
+    assert splits
+    fails = []
+    for vid, name in splits:
+        C1, g1 = run_gemm(vid, A, B, C0, 1.0, 0.75)
+        C2, g2 = run_gemm(vid, A, B, C0, 1.0, 0.75)
+        try:
+            _check(C1, A, B, C0, 1.0, 0.75, name)
+            assert g1 and g2, f"{name}: wrote outside C"
+            assert np.array_equal(C1, C2), f"{name}: not deterministic"
+        except AssertionError as e:
+            fails.append(str(e))
+    assert not fails, "\n".join(fails[:10])
+
+
+def test_k_split_integers_and_nan_c(loaded):
+    # Exact integers through the split path; beta = 0 with NaN C.
+    M, N, K = 70, 130, 1500
+    A = datagen.integers((28, 0), M, K, -4, 4)
+    B = datagen.integers((28, 1), K, N, -4, 4)
+    Cref, _, _ = oracle.ref_gemm(A, B)
+    nanC = np.full((M, N), np.nan, np.float32)
+    fails = []
+    for vid, name in _split_variants(loaded):
+        C, guard = run_gemm(vid, A, B, nanC, 1.0, 0.0)
+        if not (np.array_equal(C.astype(np.float64), Cref) and guard):
+            fails.append(name)
+    assert not fails, fails[:10]

@@ -176,17 +176,15 @@ def test_checkerboard_split():
     assert all(s.count(1024) == 1 for s in held if s != (1024, 1024, 1024))
 
 
-def test_dispatch_rule_hand_cases():
+def test_nearest_shape_hand_cases():
     train, held = datagen.checkerboard_split()
-    winners = list(range(100, 100 + len(train)))
-    # Every training shape maps to itself.
+    # Every training shape is nearest to itself.
     for i, s in enumerate(train):
         assert pr.nearest_training_shape(train, *s) == i
-        assert pr.dispatch(train, winners, *s) == winners[i]
     # (256,256,1024): distance 2 to (256,256,256) and to (256,256,4096);
-    # the tie goes to the lower index, (256,256,256).
+    # the first of them is (256,256,256).
     assert train[pr.nearest_training_shape(train, 256, 256, 1024)] == (256, 256, 256)
-    # 1024^3: distance 2 to each of the six two-1024 shapes; lowest index is
+    # 1024^3: distance 2 to each of the six two-1024 shapes; the first is
     # (256,1024,1024).
     assert train[pr.nearest_training_shape(train, 1024, 1024, 1024)] == (256, 1024, 1024)
     # (4096,4096,1024): distance 2 to (1024,4096,1024), (4096,1024,1024),
@@ -197,6 +195,45 @@ def test_dispatch_rule_hand_cases():
     assert train[pr.nearest_training_shape(train, 512, 4096, 4096)] == (256, 4096, 4096)
     # Degenerate sizes are clamped to 1.
     assert train[pr.nearest_training_shape(train, 0, 1, 1)] == (256, 256, 256)
+
+
+def test_dispatch_vote_hand_cases():
+    train, _ = datagen.checkerboard_split()
+    members = [7, 3, 9]
+    # Member 3 is the winner (cost 0) on the six two-1024 shapes except
+    # (256,1024,1024), where member 7 wins; member 9 wins the corners.
+    cost = []
+    for s in train:
+        if s == (256, 1024, 1024):
+            cost.append([0.0, 0.5, 2.0])
+        elif s.count(1024) == 2:
+            cost.append([0.4, 0.0, 2.0])
+        else:
+            cost.append([1.0, 1.0, 0.0])
+    # A training shape gets its own winner.
+    assert pr.dispatch(train, members, cost, 256, 1024, 1024) == 7
+    assert pr.dispatch(train, members, cost, 1024, 1024, 256) == 3
+    assert pr.dispatch(train, members, cost, 4096, 4096, 4096) == 9
+    # 1024^3: the six two-1024 shapes vote; totals 7: 0+5*0.4 = 2.0,
+    # 3: 0.5+0 = 0.5, 9: 12 -> member 3 (the nearest-first rule alone would
+    # have taken 7, the winner of (256,1024,1024)).
+    assert pr.dispatch(train, members, cost, 1024, 1024, 1024) == 3
+    # (256,256,1024): four shapes at distance 2 vote: the corners
+    # (256,256,256) and (256,256,4096) [1, 1, 0] each, (256,1024,1024)
+    # [0, 0.5, 2] and (1024,256,1024) [0.4, 0, 2]; totals 2.4, 2.5, 4.0 ->
+    # member 7.
+    assert pr.dispatch(train, members, cost, 256, 256, 1024) == 7
+    # (256,256,2048): distance 1 to (256,256,4096) only -> its winner, 9.
+    assert pr.dispatch(train, members, cost, 256, 256, 2048) == 9
+    # Equal totals go to the member listed first: two members identical.
+    cost2 = [[0.3, 0.3, 1.0] for _ in train]
+    assert pr.dispatch(train, members, cost2, 1024, 1024, 1024) == 7
+    # A member that failed on one of the nearest shapes cannot win there
+    # unless every member did.
+    cost3 = [[INF if s == (256, 1024, 1024) else 0.0, 0.1, 0.2] for s in train]
+    assert pr.dispatch(train, members, cost3, 1024, 1024, 1024) == 3
+    cost4 = [[INF, INF, INF] if s == (256, 1024, 1024) else [0.5, 0.1, 0.2] for s in train]
+    assert pr.dispatch(train, members, cost4, 1024, 1024, 1024) == 7
 
 
 def test_assign_winners():
