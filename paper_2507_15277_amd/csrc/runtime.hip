@@ -226,28 +226,42 @@ bool aligned_for(const void* p, int vw) { return (reinterpret_cast<uintptr_t>(p)
 
 // C = alpha * sum_{q < splits} P[q] + beta * C, P[q] the q-th M x N slice of
 // partial products; the splits are added in index order (deterministic).
-// Each thread handles four consecutive columns of one row.
+// Each thread handles four consecutive columns of one row, with 16-byte
+// accesses when N and ldc are multiples of 4 and C is 16-byte aligned.
+template <bool VEC>
 __global__ void __launch_bounds__(256)
 ff_splitk_reduce(int64_t M, int64_t N, int splits, const float* __restrict__ P, float alpha, float beta,
                  float* __restrict__ C, int64_t ldc)
 {
+    typedef float f4 __attribute__((ext_vector_type(4)));
     const int64_t nq = (N + 3) / 4;
     const int64_t total = M * nq;
     const int64_t slice = M * N;
     for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
          idx += (int64_t)gridDim.x * blockDim.x) {
         const int64_t i = idx / nq, j0 = (idx - i * nq) * 4;
-        const int w = (int)std::min<int64_t>(4, N - j0);
-        float s[4] = {0.0f, 0.0f, 0.0f, 0.0f};
-        for (int q = 0; q < splits; ++q) {
-            const float* p = P + q * slice + i * N + j0;
-            for (int c = 0; c < w; ++c) s[c] += p[c];
-        }
-        float* crow = C + i * ldc + j0;
-        for (int c = 0; c < w; ++c) {
-            float o = alpha * s[c];
-            if (beta != 0.0f) o += beta * crow[c];
-            crow[c] = o;
+        if constexpr (VEC) {
+            const f4* p = reinterpret_cast<const f4*>(P + i * N + j0);
+            const int64_t step = slice / 4;
+            f4 s = p[0];
+            for (int q = 1; q < splits; ++q) s += p[q * step];
+            f4* c = reinterpret_cast<f4*>(C + i * ldc + j0);
+            f4 o = alpha * s;
+            if (beta != 0.0f) o += beta * *c;
+            *c = o;
+        } else {
+            const int w = (int)(N - j0 < 4 ? N - j0 : 4);
+            float s[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+            for (int q = 0; q < splits; ++q) {
+                const float* p = P + q * slice + i * N + j0;
+                for (int c = 0; c < w; ++c) s[c] += p[c];
+            }
+            float* crow = C + i * ldc + j0;
+            for (int c = 0; c < w; ++c) {
+                float o = alpha * s[c];
+                if (beta != 0.0f) o += beta * crow[c];
+                crow[c] = o;
+            }
         }
     }
 }
@@ -292,8 +306,13 @@ int launch_variant(const Variant& v, int64_t M, int64_t N, int64_t K, float alph
     if (splits > 1) {
         const int64_t work = M * ((N + 3) / 4);
         const int64_t blocks = std::min<int64_t>((work + 255) / 256, 8192);
-        hipLaunchKernelGGL(ff_splitk_reduce, dim3((unsigned)blocks), dim3(256), 0, s, M, N, splits,
-                           (const float*)ws, alpha, beta, C, ldc);
+        const bool vec4 = (N % 4 == 0) && (ldc % 4 == 0) && aligned_for(C, 4);
+        if (vec4)
+            hipLaunchKernelGGL(ff_splitk_reduce<true>, dim3((unsigned)blocks), dim3(256), 0, s, M, N, splits,
+                               (const float*)ws, alpha, beta, C, ldc);
+        else
+            hipLaunchKernelGGL(ff_splitk_reduce<false>, dim3((unsigned)blocks), dim3(256), 0, s, M, N, splits,
+                               (const float*)ws, alpha, beta, C, ldc);
         e = hipGetLastError();
         if (e != hipSuccess) return hip_fail(e, "launch split-K reduction");
     }

@@ -28,6 +28,7 @@ MAX_ACC = 128            # accumulator floats per lane
 MAX_DIRECT_OPERANDS = 64  # double-buffered operand registers, direct loads
 MAX_LDS_BYTES = 80 * 1024  # keeps >= 2 work-groups per CU possible (160 KB LDS)
 MAX_THREADS = 512
+MAX_STAGING = 64          # floats per thread held in flight between global loads and LDS
 
 
 @dataclass(frozen=True)
@@ -116,13 +117,17 @@ def legal(v: Variant) -> bool:
     if not v.lds and 2 * v.steps * (v.rm + v.rn) > MAX_DIRECT_OPERANDS:
         return False
     if v.lds:
-        # Every thread should have at least one vector of each slab to stage.
+        # Every thread should have at least one vector of each slab to stage,
+        # and the staged slab must fit in registers next to the accumulators.
         if v.mwg * v.kwg < v.threads * v.vw or v.kwg * v.nwg < v.threads * v.vw:
+            return False
+        if (v.mwg * v.kwg + v.kwg * v.nwg) > MAX_STAGING * v.threads:
             return False
     return True
 
 
 TILES = (16, 32, 64, 128, 256)
+KSTEPS = (8, 16, 32, 64, 128)
 SPLITS = (1, 2, 4, 8, 16)
 
 
@@ -130,7 +135,7 @@ def enumerate_space():
     """All legal configurations, in a fixed order."""
     out = []
     for mi, mwg, nwg, kwg, wm, wn, sk, vw, lds, sg in itertools.product(
-            (32, 16), TILES, TILES, (8, 16, 32), (1, 2, 4), (1, 2, 4), (1, 2, 4), (1, 2, 4), (1, 0),
+            (32, 16), TILES, TILES, KSTEPS, (1, 2, 4), (1, 2, 4), (1, 2, 4), (1, 2, 4), (1, 0),
             SPLITS):
         v = Variant(mwg, nwg, kwg, mi, wm, wn, sk, vw, lds, 8, sg)
         if legal(v):
@@ -181,10 +186,20 @@ HAND = [
     Variant(128, 64, 16, 32, 2, 2, 1, 4, 1, sg=4),
     Variant(64, 32, 32, 16, 2, 1, 2, 4, 1, sg=4),
     Variant(64, 32, 32, 16, 2, 1, 2, 4, 1, sg=8),
+    # Deep K steps for small tiles: fewer global-load round trips.
+    Variant(16, 16, 64, 16, 1, 1, 4, 4, 0),
+    Variant(16, 16, 128, 16, 1, 1, 4, 4, 0),
+    Variant(16, 32, 64, 16, 1, 1, 4, 2, 0),
+    Variant(16, 32, 128, 16, 1, 1, 4, 4, 0),
+    Variant(32, 32, 64, 16, 1, 1, 4, 4, 0),
+    Variant(32, 32, 128, 32, 1, 1, 4, 4, 0),
+    Variant(32, 32, 64, 32, 1, 1, 4, 4, 1),
+    Variant(16, 16, 128, 16, 1, 1, 4, 4, 0, sg=4),
+    Variant(32, 32, 128, 32, 1, 1, 4, 4, 0, sg=4),
 ]
 
 
-def family(n=300, seed=0):
+def family(n=320, seed=0):
     """The compiled family: DEFAULT, HAND, then a seeded sample stratified by
     (MWG, NWG) tile shape, up to ``n`` variants.  Deterministic for a seed."""
     space = enumerate_space()
