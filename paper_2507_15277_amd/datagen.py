@@ -40,6 +40,17 @@ def uniform(seed, rows, cols, ld=None):
     return base[:, :cols]
 
 
+def lognormal(seed, rows, cols, sigma=2.0, emin=-8, emax=8):
+    """FP32 matrix with |x| = exp(sigma * z), z ~ N(0, 1), clamped to
+    [2^emin, 2^emax], and independent random signs (the precision-form
+    workload: magnitudes spread over 16 binades)."""
+    rng = np.random.default_rng(list(seed))
+    z = rng.standard_normal(rows * cols)
+    mag = np.clip(np.exp(sigma * z), 2.0 ** emin, 2.0 ** emax)
+    sign = np.where(rng.random(rows * cols) < 0.5, -1.0, 1.0)
+    return (sign * mag).astype(np.float32).reshape(rows, cols)
+
+
 def integers(seed, rows, cols, lo=-8, hi=8):
     """FP32 matrix of integers drawn uniformly from [lo, hi]."""
     rng = np.random.default_rng(list(seed))

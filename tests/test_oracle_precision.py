@@ -1,0 +1,102 @@
+"""Pins of the split-precision oracle: rounding against library routines,
+exactness of the splits, closed forms, and the truncation bounds."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from oracle import precision_ref as pr
+from paper_2507_15277_amd import datagen
+
+
+def test_bf16_rounding_matches_torch():
+    # torch's float32 -> bfloat16 conversion rounds to nearest, ties to even.
+    rng = np.random.default_rng(1)
+    x = (rng.standard_normal(20000) * np.exp(rng.uniform(-20, 20, 20000))).astype(np.float32)
+    # Exact ties: lower 16 bits 0x8000, with even and odd upper halves.
+    ties = (rng.integers(0x3F000000 >> 16, 0x47000000 >> 16, 2000, dtype=np.uint32) << 16) | 0x8000
+    x = np.concatenate([x, ties.view(np.float32), -ties.view(np.float32)])
+    want = torch.from_numpy(x).to(torch.bfloat16).to(torch.float32).numpy()
+    assert np.array_equal(pr.bf16_rne(x), want)
+
+
+def test_fp16_pieces_match_numpy():
+    A = datagen.lognormal((5, 0), 40, 30)
+    p, e = pr.split_fp16(A)
+    amax = float(np.max(np.abs(A)))
+    assert 2.0 ** 14 <= amax * 2.0 ** e < 2.0 ** 15
+    assert np.array_equal(p, (A * np.float32(2.0 ** e)).astype(np.float16).astype(np.float32))
+    assert pr.fp16_exponent(0.0) == 0
+    assert pr.fp16_exponent(1.0) == 14 and pr.fp16_exponent(0.75) == 15
+
+
+@pytest.mark.parametrize("terms", [2, 3])
+def test_bf16_split_is_exact(terms):
+    x = datagen.lognormal((6, terms), 1, 5000)[0]
+    pieces = pr.split_bf16(x, terms)
+    for p in pieces:                      # every piece is a bfloat16 value
+        assert np.all((p.view(np.uint32) & 0xFFFF) == 0)
+    total = sum(p.astype(np.float64) for p in pieces)
+    resid = x.astype(np.float64) - total
+    # Each split step leaves at most 2^-8 of the previous residual.
+    assert np.all(np.abs(resid) <= 2.0 ** (-8 * terms) * np.abs(x))
+    # Closed form: 1 + 2^-10 -> hi = 1, lo = 2^-10.
+    hi, lo = pr.split_bf16(np.array([1.0 + 2.0 ** -10], np.float32), 2)
+    assert hi[0] == 1.0 and lo[0] == 2.0 ** -10
+
+
+def test_bf16_forms_exact_on_bf16_inputs():
+    # Entries that are already bfloat16 values: lo = 0, so the split forms
+    # reproduce the exact product.
+    A = datagen.integers((7, 0), 20, 33, -100, 100)
+    B = datagen.integers((7, 1), 33, 17, -100, 100)
+    _, S, _ = oracle.ref_gemm(A, B)
+    for form in ("bf16x3", "bf16x6"):
+        C, _ = pr.split_form_gemm(A, B, form)
+        assert np.array_equal(C, S)
+
+
+def test_closed_form_one_plus_eps():
+    # A = 1 + 2^-10 (bf16 hi 1, lo 2^-10), B = 1 + 2^-12, K = 1:
+    # bf16x3 keeps hi*hi + hi*lo + lo*hi = 1 + 2^-12 + 2^-10, drops 2^-22.
+    A = np.array([[1.0 + 2.0 ** -10]], np.float32)
+    B = np.array([[1.0 + 2.0 ** -12]], np.float32)
+    C, T = pr.split_form_gemm(A, B, "bf16x3")
+    assert C[0, 0] == 1.0 + 2.0 ** -12 + 2.0 ** -10
+    C6, _ = pr.split_form_gemm(A, B, "bf16x6")
+    assert C6[0, 0] == (1.0 + 2.0 ** -10) * (1.0 + 2.0 ** -12)
+
+
+@pytest.mark.parametrize("form", ["bf16x3", "bf16x6", "fp16s"])
+def test_truncation_bound_holds_and_is_not_vacuous(form):
+    M, N, K = 24, 20, 300
+    A = datagen.lognormal((8, 0), M, K)
+    B = datagen.lognormal((8, 1), K, N)
+    _, S, T = oracle.ref_gemm(A, B)
+    C, _ = pr.split_form_gemm(A, B, form)
+    err = np.abs(C - S)
+    assert np.all(err <= pr.truncation_bound(form) * T)
+    # The form really drops something: the largest error is within a factor
+    # 1000 of the bound (a split that kept everything would be exact).
+    assert np.max(err / T) > pr.truncation_bound(form) / 1000
+
+
+def test_alpha_beta_in_split_form():
+    M, N, K = 9, 7, 11
+    A = datagen.lognormal((9, 0), M, K)
+    B = datagen.lognormal((9, 1), K, N)
+    C0 = datagen.uniform((9, 2), M, N)
+    C, T = pr.split_form_gemm(A, B, "bf16x3", alpha=-0.5, beta=2.0, C0=C0)
+    C1, T1 = pr.split_form_gemm(A, B, "bf16x3")
+    assert np.allclose(C, -0.5 * C1 + 2.0 * C0.astype(np.float64), rtol=0, atol=1e-12)
+    assert np.allclose(T, 0.5 * T1)
+
+
+def test_lognormal_generator_range():
+    x = datagen.lognormal((10, 0), 200, 200)
+    a = np.abs(x)
+    assert a.min() >= 2.0 ** -8 and a.max() <= 2.0 ** 8
+    assert 0.4 < np.mean(x > 0) < 0.6
+    # sigma = 2: about 0.56% of the magnitudes fall outside 2^[-8,8].
+    frac = np.mean((a == np.float32(2.0 ** -8)) | (a == np.float32(2.0 ** 8)))
+    assert 0.002 < frac < 0.01
