@@ -57,6 +57,13 @@ extern "C" {
 #define FF_ERR_TOO_LARGE (-106)/* M, N or K above INT32_MAX */
 #define FF_ERR_ARG (-107)      /* other invalid argument (tuning ABI) */
 
+/* Precision forms: how the FP32 product is formed (accumulation and the
+ * alpha/beta epilogue are FP32 in every form). */
+#define FF_FORM_FP32 0    /* FP32 MFMA */
+#define FF_FORM_BF16X3 1  /* split-bf16, 3 products: hi*hi + hi*lo + lo*hi */
+#define FF_FORM_BF16X6 2  /* split-bf16 in 3 pieces, 6 products */
+#define FF_FORM_FP16S 3   /* per-matrix power-of-two scaled fp16, 1 product */
+
 /* ---------------------------------------------------------------------
  * Hot path
  * ------------------------------------------------------------------- */
@@ -96,13 +103,32 @@ int sgemm(int64_t M, int64_t N, int64_t K, float alpha,
 /*
  * Load a variant set file (the output of portability tuning, Sec. IV-B):
  * the k member variants, their parameters, the GPU architecture they were
- * built for, and the dispatch table of training shapes.  Only the k code
+ * built for, its precision form (a "form" line; FP32 when absent), and the
+ * dispatch table of training shapes.  Only the k code
  * objects of the set are loaded (Sec. III-B-3: pre-selection keeps the
- * number of shipped variants small).  Replaces any previously loaded set.
+ * number of shipped variants small).  Replaces any previously loaded set
+ * of the same form.
  * Not safe to call concurrently with sgemm() on another thread.
  * Returns k on success; FF_ERR_IO, FF_ERR_PARSE, FF_ERR_ARCH, FF_ERR_HIP.
  */
 int variant_set_load(const char *path);
+
+/*
+ * sgemm() in precision form `form` (FF_FORM_*), dispatched through the set
+ * loaded for that form.  The 16-bit forms split each FP32 operand into
+ * bfloat16 or scaled float16 pieces inside the kernel and accumulate the
+ * piece products in FP32 (not a paper method: an MI355X form of the same
+ * operation).  Per-element error, as a multiple of |alpha|(|A||B|): about
+ * 3.1*2^-16 (bf16x3), 4.2*2^-24 (bf16x6), 2.1*2^-11 (fp16s, for operands
+ * within 2^25 of each matrix's largest magnitude), plus FP32 accumulation.
+ * The fp16s form first reduces max|A| and max|B| on the device into the
+ * per-device workspace (calls on one device must not overlap in time) and
+ * needs finite inputs.  Other semantics as sgemm(); FF_ERR_ARG for an
+ * unknown form.
+ */
+int sgemm_form(int form, int64_t M, int64_t N, int64_t K, float alpha,
+               const float *A, int64_t lda, const float *B, int64_t ldb,
+               float beta, float *C, int64_t ldc, void *stream);
 
 /*
  * Variant id that sgemm() would run for (M, N, K) under the loaded set.
@@ -116,6 +142,9 @@ int variant_set_load(const char *path);
  * argument error for negative sizes.
  */
 int variant_select(int64_t M, int64_t N, int64_t K);
+
+/* variant_select() for the set loaded for precision form `form`. */
+int variant_select_form(int form, int64_t M, int64_t N, int64_t K);
 
 /* Text of the calling thread's most recent error ("" if none). */
 const char *fewfit_last_error(void);
@@ -136,7 +165,8 @@ int variant_count(void);
 
 /*
  * Write variant `id`'s descriptor into buf (NUL-terminated, truncated to
- * len): "<id> <name> <MWG> <NWG> <KWG> <MI> <WM> <WN> <SK> <VW> <LDS> <GM> <SG>".
+ * len): "<id> <name> <MWG> <NWG> <KWG> <MI> <WM> <WN> <SK> <VW> <LDS> <GM> <SG>
+ * <PREC>", PREC the precision form (FF_FORM_*).
  * Returns the full length, or FF_ERR_VARIANT.
  */
 int variant_info(int id, char *buf, size_t len);
@@ -167,7 +197,10 @@ int sgemm_time(int id, int64_t M, int64_t N, int64_t K, float alpha,
  *               (+ 2*2^-24*(|alpha*sum_k A B| + |beta*C0|) if alpha != 1 or beta != 0)
  * into caller-owned device arrays ref and tol (M*N doubles each, dense
  * row-major).  screen_compare() counts the elements of C (row stride ldc)
- * with |C - ref| > tol or non-finite C, and the largest |C - ref| / tol.
+ * with |C - ref| > tol_scale*tol or non-finite C, and writes the largest
+ * |C - ref| / (tol_scale*tol) and, if err2/ref2 are not NULL, the sums of
+ * (C - ref)^2 and ref^2 (normwise relative error = sqrt(err2/ref2)).
+ * tol_scale > 1 widens the bound for the 16-bit precision forms.
  * Both synchronise the stream.  Returns 0, FF_ERR_ARG or FF_ERR_HIP.
  */
 int screen_reference(int64_t M, int64_t N, int64_t K, float alpha,
@@ -175,8 +208,9 @@ int screen_reference(int64_t M, int64_t N, int64_t K, float alpha,
                      float beta, const float *C0, int64_t ldc0,
                      double *ref, double *tol, void *stream);
 int screen_compare(int64_t M, int64_t N, const float *C, int64_t ldc,
-                   const double *ref, const double *tol,
-                   int64_t *nbad, double *max_ratio, void *stream);
+                   const double *ref, const double *tol, double tol_scale,
+                   int64_t *nbad, double *max_ratio, double *err2, double *ref2,
+                   void *stream);
 
 /* ---------------------------------------------------------------------
  * Portability tuning on an execution-time table (host only, Sec. IV, V-C)

@@ -22,8 +22,11 @@ FF_ERR_M, FF_ERR_N, FF_ERR_K = -1, -2, -3
 FF_ERR_A, FF_ERR_LDA, FF_ERR_B, FF_ERR_LDB, FF_ERR_C, FF_ERR_LDC = -5, -6, -7, -8, -10, -11
 FF_ERR_NO_SET, FF_ERR_VARIANT, FF_ERR_PARSE = -100, -101, -102
 FF_ERR_ARCH, FF_ERR_HIP, FF_ERR_IO, FF_ERR_TOO_LARGE, FF_ERR_ARG = -103, -104, -105, -106, -107
+FF_FORM_FP32, FF_FORM_BF16X3, FF_FORM_BF16X6, FF_FORM_FP16S = 0, 1, 2, 3
+FORM_NAMES = ("fp32", "bf16x3", "bf16x6", "fp16s")
 
-EXPORTS = ("sgemm", "variant_set_load", "variant_select", "fewfit_last_error",
+EXPORTS = ("sgemm", "sgemm_form", "variant_set_load", "variant_select", "variant_select_form",
+           "fewfit_last_error",
            "variant_manifest_load", "variant_count", "variant_info", "sgemm_variant",
            "sgemm_time", "screen_reference", "screen_compare", "ptune_postprocess",
            "ptune_cost", "ptune_select", "ptune_assign", "ptune_nearest", "ptune_dispatch")
@@ -48,6 +51,8 @@ def lib():
         i64, f32, f64, vp, i32 = ctypes.c_int64, ctypes.c_float, ctypes.c_double, ctypes.c_void_p, ctypes.c_int
         gemm_args = [i64, i64, i64, f32, vp, i64, vp, i64, f32, vp, i64, vp]
         L.sgemm.argtypes = gemm_args
+        L.sgemm_form.argtypes = [i32] + gemm_args
+        L.variant_select_form.argtypes = [i32, i64, i64, i64]
         L.sgemm_variant.argtypes = [i32] + gemm_args
         L.sgemm_time.argtypes = [i32] + gemm_args + [i32, i32, i32, vp]
         L.variant_set_load.argtypes = [ctypes.c_char_p]
@@ -58,7 +63,7 @@ def lib():
         L.fewfit_last_error.argtypes = []
         L.fewfit_last_error.restype = ctypes.c_char_p
         L.screen_reference.argtypes = [i64, i64, i64, f32, vp, i64, vp, i64, f32, vp, i64, vp, vp, vp]
-        L.screen_compare.argtypes = [i64, i64, vp, i64, vp, vp, vp, vp, vp]
+        L.screen_compare.argtypes = [i64, i64, vp, i64, vp, vp, f64, vp, vp, vp, vp, vp]
         L.ptune_postprocess.argtypes = [i32, i32, vp, vp, vp, vp, vp, vp]
         L.ptune_cost.argtypes = [i32, i32, vp, i32, vp, i32, vp, vp]
         L.ptune_select.argtypes = [i32, i32, vp, i32, vp, i32, i32, vp, vp, vp]
@@ -106,6 +111,15 @@ def sgemm(M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, stream=None):
                               _stream(stream)))
 
 
+def sgemm_form(form, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, stream=None):
+    return _check(lib().sgemm_form(form, M, N, K, alpha, _ptr(A), lda, _ptr(B), ldb, beta, _ptr(C), ldc,
+                                   _stream(stream)))
+
+
+def variant_select_form(form, M, N, K):
+    return _check(lib().variant_select_form(form, M, N, K))
+
+
 def variant_set_load(path):
     return _check(lib().variant_set_load(os.fsencode(path)))
 
@@ -148,11 +162,18 @@ def screen_reference(M, N, K, alpha, A, lda, B, ldb, beta, C0, ldc0, ref, tol, s
                                          _ptr(C0), ldc0, _ptr(ref), _ptr(tol), _stream(stream)))
 
 
-def screen_compare(M, N, C, ldc, ref, tol, stream=None):
+def screen_compare(M, N, C, ldc, ref, tol, stream=None, tol_scale=1.0, norms=False):
+    """(bad count, max error/bound ratio[, normwise relative error])."""
     nbad = ctypes.c_int64(0)
     ratio = ctypes.c_double(0.0)
-    _check(lib().screen_compare(M, N, _ptr(C), ldc, _ptr(ref), _ptr(tol), ctypes.byref(nbad),
-                                ctypes.byref(ratio), _stream(stream)))
+    e2 = ctypes.c_double(0.0)
+    r2 = ctypes.c_double(0.0)
+    _check(lib().screen_compare(M, N, _ptr(C), ldc, _ptr(ref), _ptr(tol), float(tol_scale),
+                                ctypes.byref(nbad), ctypes.byref(ratio), ctypes.byref(e2),
+                                ctypes.byref(r2), _stream(stream)))
+    if norms:
+        rel = (e2.value / r2.value) ** 0.5 if r2.value > 0 else 0.0
+        return nbad.value, ratio.value, rel
     return nbad.value, ratio.value
 
 

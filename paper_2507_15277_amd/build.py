@@ -43,7 +43,7 @@ def _compile_variant(v: space.Variant, outdir: str):
     out = os.path.join(outdir, v.name + ".co")
     tmp = out + ".tmp"
     cmd = [HIPCC, *DEVICE_FLAGS, "--cuda-device-only", "--no-gpu-bundle-output", "-c",
-           os.path.join(CSRC, "sgemm_variant.hip"), "-o", tmp]
+           os.path.join(CSRC, v.source), "-o", tmp]
     cmd += [f"-D{k}={val}" for k, val in v.defines().items()]
     t0 = time.perf_counter()
     _run(cmd, False)
@@ -54,7 +54,7 @@ def _compile_variant(v: space.Variant, outdir: str):
 
 def build_variants(variants=None, outdir=VARIANT_DIR, jobs=None, verbose=False):
     """Compile every variant in parallel; write manifest.txt and build_stats.txt."""
-    variants = space.family() if variants is None else variants
+    variants = space.full_family() if variants is None else variants
     os.makedirs(outdir, exist_ok=True)
     jobs = jobs or min(16, os.cpu_count() or 4)
     results = {}
@@ -66,7 +66,7 @@ def build_variants(variants=None, outdir=VARIANT_DIR, jobs=None, verbose=False):
             if verbose:
                 print(f"  built {v.name} ({dt:.1f} s, {size} B)", flush=True)
     with open(os.path.join(outdir, "manifest.txt"), "w") as f:
-        f.write("# id name MWG NWG KWG MI WM WN SK VW LDS GM\n")
+        f.write("# id name MWG NWG KWG MI WM WN SK VW LDS GM SG PREC\n")
         for vid, v in enumerate(variants):
             f.write(v.descriptor(vid) + "\n")
     with open(os.path.join(outdir, "build_stats.txt"), "w") as f:

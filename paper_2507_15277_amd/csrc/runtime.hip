@@ -55,22 +55,24 @@ struct Variant {
     int id = -1;
     std::string name;
     int mwg = 0, nwg = 0, kwg = 0, mi = 0, wm = 0, wn = 0, sk = 0, vw = 0, lds = 0, gm = 0, sg = 0;
+    int prec = 0;  // 0 FP32 MFMA; 1 bf16x3, 2 bf16x6, 3 scaled fp16 (16-bit MFMA, FP32 accumulation)
     hipModule_t mod = nullptr;
     hipFunction_t fvec = nullptr;  // VW-wide loads
     hipFunction_t fsca = nullptr;  // scalar loads
     int threads() const { return 64 * wm * wn * sk; }
 };
 
-// "<id> <name> MWG NWG KWG MI WM WN SK VW LDS GM SG"
+// "<id> <name> MWG NWG KWG MI WM WN SK VW LDS GM SG PREC"
 bool parse_descriptor(std::istringstream& is, Variant& v)
 {
     if (!(is >> v.id >> v.name >> v.mwg >> v.nwg >> v.kwg >> v.mi >> v.wm >> v.wn >> v.sk >> v.vw >> v.lds >> v.gm >>
-          v.sg))
+          v.sg >> v.prec))
         return false;
     if (v.id < 0 || v.mwg <= 0 || v.nwg <= 0 || v.kwg <= 0 || (v.mi != 16 && v.mi != 32) || v.wm <= 0 ||
         v.wn <= 0 || v.sk <= 0 || (v.vw != 1 && v.vw != 2 && v.vw != 4) || (v.lds != 0 && v.lds != 1) ||
-        v.gm <= 0 || v.sg < 1 || v.sg > 64 || v.threads() > 1024)
+        v.gm <= 0 || v.sg < 1 || v.sg > 64 || v.prec < 0 || v.prec > 3 || v.threads() > 1024)
         return false;
+    if (v.prec > 0 && (v.sk != 1 || v.sg != 1 || v.lds != 1)) return false;
     for (char c : v.name)
         if (!(isalnum((unsigned char)c) || c == '_')) return false;
     return true;
@@ -84,9 +86,10 @@ struct VarSet {
     std::vector<double> cost;                    // ntrain x k log-slowdowns of the members
 };
 
+constexpr int kForms = 4;
 std::mutex g_mu;
 std::map<int, std::shared_ptr<Variant>> g_variants;
-std::shared_ptr<const VarSet> g_set;
+std::shared_ptr<const VarSet> g_set[kForms];  // one loaded set per precision form
 
 // Workspace of the K-split variants: one M x N slice of partial products per
 // split, per device.  Allocated once, when the first K-split variant is
@@ -95,8 +98,10 @@ constexpr size_t kWsBytes = size_t(128) << 20;
 constexpr int kMaxDevices = 16;
 struct Workspace {
     float* ws = nullptr;
+    float* scale = nullptr;  // FP16 form: block maxima of |A| and |B|, then {2^eA, 2^eB, 2^-(eA+eB)}
 };
 Workspace g_ws[kMaxDevices];
+constexpr int kMaxBlocks = 1024;  // per matrix, for the |A|, |B| maxima
 
 int ensure_workspace()
 {
@@ -107,9 +112,11 @@ int ensure_workspace()
     Workspace& w = g_ws[dev];
     if (w.ws != nullptr) return FF_OK;
     e = hipMalloc(&w.ws, kWsBytes);
+    if (e == hipSuccess) e = hipMalloc(&w.scale, (2 * kMaxBlocks + 4) * sizeof(float));
     if (e != hipSuccess) {
+        if (w.ws) hipFree(w.ws);
         w = Workspace{};
-        return hip_fail(e, "allocate split-K workspace");
+        return hip_fail(e, "allocate workspace");
     }
     return FF_OK;
 }
@@ -150,7 +157,7 @@ int register_variant(const Variant& d, const std::string& dir)
     auto v = std::make_shared<Variant>(d);
     int rc = load_code_object(*v, dir + "/" + d.name + ".co");
     if (rc != FF_OK) return rc;
-    if (d.sg > 1) {
+    if (d.sg > 1 || d.prec == 3) {
         rc = ensure_workspace();
         if (rc != FF_OK) return rc;
     }
@@ -266,6 +273,53 @@ ff_splitk_reduce(int64_t M, int64_t N, int splits, const float* __restrict__ P, 
     }
 }
 
+// Scaled FP16 form, step 1: block maxima of |A| (blocks [0, nb)) and |B|
+// (blocks [nb, 2 nb)).
+__global__ void __launch_bounds__(256)
+ff_absmax_blocks(int64_t M, int64_t K, const float* __restrict__ A, int64_t lda, int64_t N,
+                 const float* __restrict__ B, int64_t ldb, int nb, float* __restrict__ out)
+{
+    __shared__ float red[256];
+    const bool isA = (int)blockIdx.x < nb;
+    const int blk = isA ? blockIdx.x : blockIdx.x - nb;
+    const int64_t rows = isA ? M : K, cols = isA ? K : N, ld = isA ? lda : ldb;
+    const float* X = isA ? A : B;
+    const int64_t total = rows * cols;
+    float m = 0.0f;
+    for (int64_t idx = (int64_t)blk * blockDim.x + threadIdx.x; idx < total; idx += (int64_t)nb * blockDim.x) {
+        const int64_t i = idx / cols, j = idx - i * cols;
+        m = fmaxf(m, fabsf(X[i * ld + j]));
+    }
+    red[threadIdx.x] = m;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] = fmaxf(red[threadIdx.x], red[threadIdx.x + w]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[blockIdx.x] = red[0];
+}
+
+// Step 2: exponents e with max * 2^e in [2^14, 2^15) (0 for an all-zero
+// matrix); writes {2^eA, 2^eB, 2^-(eA+eB)} after the block maxima.
+__global__ void __launch_bounds__(64) ff_fp16_prescale(int nb, float* __restrict__ buf)
+{
+    if (threadIdx.x != 0) return;
+    float ma = 0.0f, mb = 0.0f;
+    for (int i = 0; i < nb; ++i) {
+        ma = fmaxf(ma, buf[i]);
+        mb = fmaxf(mb, buf[nb + i]);
+    }
+    int ea = 0, eb = 0;
+    if (ma > 0.0f) { int E; frexpf(ma, &E); ea = 15 - E; }
+    if (mb > 0.0f) { int E; frexpf(mb, &E); eb = 15 - E; }
+    ea = max(-100, min(100, ea));
+    eb = max(-100, min(100, eb));
+    float* o = buf + 2 * kMaxBlocks;
+    o[0] = ldexpf(1.0f, ea);
+    o[1] = ldexpf(1.0f, eb);
+    o[2] = ldexpf(1.0f, -(ea + eb));
+}
+
 int launch_variant(const Variant& v, int64_t M, int64_t N, int64_t K, float alpha, const float* A,
                    int64_t lda, const float* B, int64_t ldb, float beta, float* C, int64_t ldc, hipStream_t s)
 {
@@ -275,15 +329,33 @@ int launch_variant(const Variant& v, int64_t M, int64_t N, int64_t K, float alph
     // The vector-load kernel needs whole, aligned vectors along K (A rows)
     // and N (B rows); otherwise the scalar-load kernel of the same variant.
     const int w = v.vw;
-    const bool vec = w > 1 && K % w == 0 && N % w == 0 && lda % w == 0 && ldb % w == 0 && aligned_for(A, w) &&
-                     aligned_for(B, w);
+    // Split-precision variants load B by columns (scalar) and A in 16-byte
+    // vectors; FP32 variants load both in VW-wide vectors.
+    const bool vec = v.prec > 0
+                         ? (K % 4 == 0 && lda % 4 == 0 && aligned_for(A, 4))
+                         : (w > 1 && K % w == 0 && N % w == 0 && lda % w == 0 && ldb % w == 0 &&
+                            aligned_for(A, w) && aligned_for(B, w));
     hipFunction_t f = vec ? v.fvec : v.fsca;
+    const float* prescale = nullptr;
+    if (v.prec == 3) {
+        int dev = 0;
+        if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices || g_ws[dev].scale == nullptr)
+            return fail(FF_ERR_HIP, "fp16 form: no scale buffer on this device");
+        float* buf = g_ws[dev].scale;
+        const int64_t most = std::max(M * K, K * N);
+        const int nbk = (int)std::min<int64_t>(kMaxBlocks, (most + 255) / 256);
+        hipLaunchKernelGGL(ff_absmax_blocks, dim3(2 * nbk), dim3(256), 0, s, M, K, A, lda, N, B, ldb, nbk, buf);
+        hipLaunchKernelGGL(ff_fp16_prescale, dim3(1), dim3(64), 0, s, nbk, buf);
+        hipError_t e0 = hipGetLastError();
+        if (e0 != hipSuccess) return hip_fail(e0, "launch fp16 prescale");
+        prescale = buf + 2 * kMaxBlocks;
+    }
     // K split over work-groups: as many as the variant allows, no more than
     // there are slabs, every split non-empty, and within the workspace.
     const int64_t nkt = (K + v.kwg - 1) / v.kwg;
     int splits = 1;
     float* ws = nullptr;
-    if (v.sg > 1 && nkt > 1) {
+    if (v.sg > 1 && nkt > 1 && v.prec == 0) {
         int dev = 0;
         if (hipGetDevice(&dev) == hipSuccess && dev >= 0 && dev < kMaxDevices && g_ws[dev].ws != nullptr) {
             int64_t sp = std::min<int64_t>(v.sg, nkt);
@@ -298,8 +370,10 @@ int launch_variant(const Variant& v, int64_t M, int64_t N, int64_t K, float alph
     int kper = (int)((nkt + splits - 1) / splits);
     int Mi = (int)M, Ni = (int)N, Ki = (int)K;
     long la = (long)lda, lb = (long)ldb, lc = (long)ldc;
+    // FP32 variants take 14 arguments; split-precision variants add the
+    // FP16 prescale pointer.
     void* args[] = {&Mi, &Ni, &Ki, &alpha, (void*)&A, &la, (void*)&B, &lb, &beta, (void*)&C, &lc,
-                    (void*)&ws, &splits, &kper};
+                    (void*)&ws, &splits, &kper, (void*)&prescale};
     hipError_t e = hipModuleLaunchKernel(f, (unsigned)(nb * splits), 1, 1, (unsigned)v.threads(), 1, 1, 0, s, args,
                                          nullptr);
     if (e != hipSuccess) return hip_fail(e, ("launch " + v.name).c_str());
@@ -321,8 +395,8 @@ int launch_variant(const Variant& v, int64_t M, int64_t N, int64_t K, float alph
 
 // Shared body of sgemm() and sgemm_variant(); `v` may be null for the
 // dispatch path, in which case the set picks it.
-int gemm_common(const Variant* v, int64_t M, int64_t N, int64_t K, float alpha, const float* A, int64_t lda,
-                const float* B, int64_t ldb, float beta, float* C, int64_t ldc, void* stream)
+int gemm_common(const Variant* v, int form, int64_t M, int64_t N, int64_t K, float alpha, const float* A,
+                int64_t lda, const float* B, int64_t ldb, float beta, float* C, int64_t ldc, void* stream)
 {
     int rc = validate(M, N, K, alpha, A, lda, B, ldb, beta, C, ldc);
     if (rc != FF_OK) return rc;
@@ -334,7 +408,7 @@ int gemm_common(const Variant* v, int64_t M, int64_t N, int64_t K, float alpha, 
     }
     std::shared_ptr<Variant> hold;
     if (v == nullptr) {
-        int id = variant_select(M, N, K);
+        int id = variant_select_form(form, M, N, K);
         if (id < 0) return id;
         std::lock_guard<std::mutex> lk(g_mu);
         auto it = g_variants.find(id);
@@ -388,41 +462,52 @@ __global__ void ff_screen_ref(int64_t M, int64_t N, int64_t K, double alpha, con
 
 constexpr int kCmpThreads = 256, kCmpBlocks = 1024;
 
+// Per block: count of |C - ref| > scale*tol or non-finite C, the largest
+// |C - ref| / (scale*tol), and the sums of (C - ref)^2 and ref^2 (for the
+// normwise relative error).
 __global__ void __launch_bounds__(kCmpThreads)
-ff_screen_cmp(int64_t M, int64_t N, const float* C, int64_t ldc, const double* ref, const double* tol,
-              long long* bad_out, double* ratio_out)
+ff_screen_cmp(int64_t M, int64_t N, const float* C, int64_t ldc, const double* ref, const double* tol, double scale,
+              long long* bad_out, double* ratio_out, double* err2_out, double* ref2_out)
 {
     __shared__ long long sb[kCmpThreads];
-    __shared__ double sr[kCmpThreads];
+    __shared__ double sr[kCmpThreads], se[kCmpThreads], sf[kCmpThreads];
     long long bad = 0;
-    double mr = 0.0;
+    double mr = 0.0, e2 = 0.0, r2 = 0.0;
     const int64_t total = M * N;
     for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
          idx += (int64_t)gridDim.x * blockDim.x) {
         const int64_t i = idx / N, j = idx - i * N;
         const double c = C[i * ldc + j];
         const double d = fabs(c - ref[idx]);
-        const double tl = tol[idx];
+        const double tl = scale * tol[idx];
         double ratio;
         if (!isfinite(c)) ratio = INFINITY;
         else if (tl > 0.0) ratio = d / tl;
         else ratio = (d == 0.0) ? 0.0 : INFINITY;
         if (!(d <= tl) || !isfinite(c)) ++bad;
         mr = fmax(mr, ratio);
+        e2 += d * d;
+        r2 += ref[idx] * ref[idx];
     }
     sb[threadIdx.x] = bad;
     sr[threadIdx.x] = mr;
+    se[threadIdx.x] = e2;
+    sf[threadIdx.x] = r2;
     __syncthreads();
     for (int w = kCmpThreads / 2; w > 0; w >>= 1) {
         if ((int)threadIdx.x < w) {
             sb[threadIdx.x] += sb[threadIdx.x + w];
             sr[threadIdx.x] = fmax(sr[threadIdx.x], sr[threadIdx.x + w]);
+            se[threadIdx.x] += se[threadIdx.x + w];
+            sf[threadIdx.x] += sf[threadIdx.x + w];
         }
         __syncthreads();
     }
     if (threadIdx.x == 0) {
         bad_out[blockIdx.x] = sb[0];
         ratio_out[blockIdx.x] = sr[0];
+        err2_out[blockIdx.x] = se[0];
+        ref2_out[blockIdx.x] = sf[0];
     }
 }
 
@@ -469,8 +554,8 @@ FF_EXPORT int variant_info(int id, char* buf, size_t len)
     auto v = find_variant(id);
     if (!v) return fail(FF_ERR_VARIANT, "variant %d not registered", id);
     char tmp[512];
-    int n = snprintf(tmp, sizeof tmp, "%d %s %d %d %d %d %d %d %d %d %d %d %d", v->id, v->name.c_str(), v->mwg,
-                     v->nwg, v->kwg, v->mi, v->wm, v->wn, v->sk, v->vw, v->lds, v->gm, v->sg);
+    int n = snprintf(tmp, sizeof tmp, "%d %s %d %d %d %d %d %d %d %d %d %d %d %d", v->id, v->name.c_str(), v->mwg,
+                     v->nwg, v->kwg, v->mi, v->wm, v->wn, v->sk, v->vw, v->lds, v->gm, v->sg, v->prec);
     if (buf && len > 0) {
         size_t c = std::min(len - 1, (size_t)n);
         memcpy(buf, tmp, c);
@@ -483,6 +568,8 @@ FF_EXPORT int variant_info(int id, char* buf, size_t len)
 //   fewfit-set 1
 //   arch <gfx name>
 //   codedir <dir>          code objects, relative to the set file's directory
+//   form <name>            optional: fp32 (default), bf16x3, bf16x6 or fp16s;
+//                          every member must be of that form
 //   variant <descriptor>   k lines, descriptor as in the manifest
 //   rule <M> <N> <K> <id> <c_1> ... <c_k>
 //                          one line per training shape (after the variant
@@ -497,6 +584,7 @@ FF_EXPORT int variant_set_load(const char* path)
     auto set = std::make_shared<VarSet>();
     std::vector<Variant> members;
     std::string arch, codedir, line;
+    int form = 0;
     bool header = false, ended = false;
     int lineno = 0;
     while (std::getline(f, line)) {
@@ -519,6 +607,14 @@ FF_EXPORT int variant_set_load(const char* path)
             if (!(is >> arch)) return fail(FF_ERR_PARSE, "%s:%d: arch needs a value", path, lineno);
         } else if (key == "codedir") {
             if (!(is >> codedir)) return fail(FF_ERR_PARSE, "%s:%d: codedir needs a value", path, lineno);
+        } else if (key == "form") {
+            std::string f;
+            static const char* names[kForms] = {"fp32", "bf16x3", "bf16x6", "fp16s"};
+            if (!(is >> f)) return fail(FF_ERR_PARSE, "%s:%d: form needs a value", path, lineno);
+            form = -1;
+            for (int i = 0; i < kForms; ++i)
+                if (f == names[i]) form = i;
+            if (form < 0) return fail(FF_ERR_PARSE, "%s:%d: unknown form '%s'", path, lineno, f.c_str());
         } else if (key == "variant") {
             Variant v;
             if (!parse_descriptor(is, v)) return fail(FF_ERR_PARSE, "%s:%d: bad variant descriptor", path, lineno);
@@ -562,6 +658,8 @@ FF_EXPORT int variant_set_load(const char* path)
     if (!ended) return fail(FF_ERR_PARSE, "%s: missing 'end' (truncated file?)", path);
     if (arch.empty() || codedir.empty() || members.empty() || set->shapes.empty())
         return fail(FF_ERR_PARSE, "%s: needs arch, codedir, at least one variant and one rule", path);
+    for (const Variant& v : members)
+        if (v.prec != form) return fail(FF_ERR_PARSE, "%s: variant %d is not of the set's form", path, v.id);
 
     std::string dev;
     int rc = device_arch(dev);
@@ -574,31 +672,41 @@ FF_EXPORT int variant_set_load(const char* path)
         rc = register_variant(v, dir);
         if (rc != FF_OK) return rc;
     }
-    g_set = set;
+    g_set[form] = set;
     return (int)set->ids.size();
 }
 
-FF_EXPORT int variant_select(int64_t M, int64_t N, int64_t K)
+FF_EXPORT int variant_select_form(int form, int64_t M, int64_t N, int64_t K)
 {
+    if (form < 0 || form >= kForms) return fail(FF_ERR_ARG, "variant_select_form: unknown form %d", form);
     if (M < 0) return fail(FF_ERR_M, "variant_select: M < 0");
     if (N < 0) return fail(FF_ERR_N, "variant_select: N < 0");
     if (K < 0) return fail(FF_ERR_K, "variant_select: K < 0");
     std::shared_ptr<const VarSet> set;
     {
         std::lock_guard<std::mutex> lk(g_mu);
-        set = g_set;
+        set = g_set[form];
     }
-    if (!set) return fail(FF_ERR_NO_SET, "no variant set loaded");
+    if (!set) return fail(FF_ERR_NO_SET, "no variant set loaded for form %d", form);
     const int id = ptune_dispatch((int)set->shapes.size(), set->flat.data(), (int)set->ids.size(), set->ids.data(),
                                   set->cost.data(), M, N, K);
     if (id < 0) return fail(FF_ERR_NO_SET, "variant set has no training shapes");
     return id;
 }
 
+FF_EXPORT int variant_select(int64_t M, int64_t N, int64_t K) { return variant_select_form(0, M, N, K); }
+
 FF_EXPORT int sgemm(int64_t M, int64_t N, int64_t K, float alpha, const float* A, int64_t lda, const float* B,
                     int64_t ldb, float beta, float* C, int64_t ldc, void* stream)
 {
-    return gemm_common(nullptr, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, stream);
+    return gemm_common(nullptr, 0, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, stream);
+}
+
+FF_EXPORT int sgemm_form(int form, int64_t M, int64_t N, int64_t K, float alpha, const float* A, int64_t lda,
+                         const float* B, int64_t ldb, float beta, float* C, int64_t ldc, void* stream)
+{
+    if (form < 0 || form >= kForms) return fail(FF_ERR_ARG, "sgemm_form: unknown form %d", form);
+    return gemm_common(nullptr, form, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, stream);
 }
 
 FF_EXPORT int sgemm_variant(int id, int64_t M, int64_t N, int64_t K, float alpha, const float* A, int64_t lda,
@@ -608,7 +716,7 @@ FF_EXPORT int sgemm_variant(int id, int64_t M, int64_t N, int64_t K, float alpha
     if (rc != FF_OK) return rc;
     auto v = find_variant(id);
     if (!v) return fail(FF_ERR_VARIANT, "variant %d not registered", id);
-    return gemm_common(v.get(), M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, stream);
+    return gemm_common(v.get(), 0, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, stream);
 }
 
 FF_EXPORT int sgemm_time(int id, int64_t M, int64_t N, int64_t K, float alpha, const float* A, int64_t lda,
@@ -623,7 +731,7 @@ FF_EXPORT int sgemm_time(int id, int64_t M, int64_t N, int64_t K, float alpha, c
     if (!v) return fail(FF_ERR_VARIANT, "variant %d not registered", id);
     hipStream_t s = static_cast<hipStream_t>(stream);
     for (int i = 0; i < warmup; ++i) {
-        rc = gemm_common(v.get(), M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, stream);
+        rc = gemm_common(v.get(), 0, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, stream);
         if (rc != FF_OK) return rc;
     }
     hipEvent_t e0, e1;
@@ -639,7 +747,7 @@ FF_EXPORT int sgemm_time(int id, int64_t M, int64_t N, int64_t K, float alpha, c
         e = hipEventRecord(e0, s);
         if (e != hipSuccess) { rc = hip_fail(e, "hipEventRecord"); break; }
         for (int r = 0; r < reps && rc == FF_OK; ++r)
-            rc = gemm_common(v.get(), M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, stream);
+            rc = gemm_common(v.get(), 0, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, stream);
         if (rc != FF_OK) break;
         e = hipEventRecord(e1, s);
         if (e == hipSuccess) e = hipEventSynchronize(e1);
@@ -674,41 +782,49 @@ FF_EXPORT int screen_reference(int64_t M, int64_t N, int64_t K, float alpha, con
 }
 
 FF_EXPORT int screen_compare(int64_t M, int64_t N, const float* C, int64_t ldc, const double* ref,
-                             const double* tol, int64_t* nbad, double* max_ratio, void* stream)
+                             const double* tol, double tol_scale, int64_t* nbad, double* max_ratio, double* err2,
+                             double* ref2, void* stream)
 {
     if (M < 0 || N < 0 || ldc < std::max<int64_t>(1, N) || nbad == nullptr || max_ratio == nullptr ||
-        (M * N > 0 && (C == nullptr || ref == nullptr || tol == nullptr)))
+        !(tol_scale > 0.0) || (M * N > 0 && (C == nullptr || ref == nullptr || tol == nullptr)))
         return fail(FF_ERR_ARG, "screen_compare: invalid arguments");
     *nbad = 0;
     *max_ratio = 0.0;
+    if (err2) *err2 = 0.0;
+    if (ref2) *ref2 = 0.0;
     if (M == 0 || N == 0) return FF_OK;
     static long long* d_bad = nullptr;
-    static double* d_ratio = nullptr;
+    static double* d_dbl = nullptr;  // ratio, err2, ref2 per block
     static std::mutex mu;
     std::lock_guard<std::mutex> lk(mu);
     hipError_t e = hipSuccess;
     if (d_bad == nullptr) {
         e = hipMalloc(&d_bad, kCmpBlocks * sizeof(long long));
-        if (e == hipSuccess) e = hipMalloc(&d_ratio, kCmpBlocks * sizeof(double));
+        if (e == hipSuccess) e = hipMalloc(&d_dbl, 3 * kCmpBlocks * sizeof(double));
         if (e != hipSuccess) return hip_fail(e, "screen_compare alloc");
     }
     hipStream_t s = static_cast<hipStream_t>(stream);
-    hipLaunchKernelGGL(ff_screen_cmp, dim3(kCmpBlocks), dim3(kCmpThreads), 0, s, M, N, C, ldc, ref, tol, d_bad,
-                       d_ratio);
+    hipLaunchKernelGGL(ff_screen_cmp, dim3(kCmpBlocks), dim3(kCmpThreads), 0, s, M, N, C, ldc, ref, tol, tol_scale,
+                       d_bad, d_dbl, d_dbl + kCmpBlocks, d_dbl + 2 * kCmpBlocks);
     std::vector<long long> hb(kCmpBlocks);
-    std::vector<double> hr(kCmpBlocks);
+    std::vector<double> hd(3 * kCmpBlocks);
     e = hipGetLastError();
     if (e == hipSuccess) e = hipMemcpyAsync(hb.data(), d_bad, kCmpBlocks * sizeof(long long), hipMemcpyDeviceToHost, s);
-    if (e == hipSuccess) e = hipMemcpyAsync(hr.data(), d_ratio, kCmpBlocks * sizeof(double), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(hd.data(), d_dbl, 3 * kCmpBlocks * sizeof(double), hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) return hip_fail(e, "screen_compare");
     long long b = 0;
-    double r = 0.0;
+    double r = 0.0, e2 = 0.0, r2 = 0.0;
     for (int i = 0; i < kCmpBlocks; ++i) {
         b += hb[i];
-        r = std::max(r, hr[i]);
+        r = std::max(r, hd[i]);
+        e2 += hd[kCmpBlocks + i];
+        r2 += hd[2 * kCmpBlocks + i];
     }
     *nbad = b;
     *max_ratio = r;
+    if (err2) *err2 = e2;
+    if (ref2) *ref2 = r2;
     return FF_OK;
 }

@@ -1,0 +1,365 @@
+// Single-precision GEMM through 16-bit MFMA with FP32 accumulation (gfx950).
+//
+//   C = alpha * A * B + beta * C      A: M x K, B: K x N, C: M x N, row-major FP32
+//
+// The operands are FP32; each is split on the fly into T 16-bit terms and
+// the product is formed from the term products that matter, accumulated in
+// FP32 by v_mfma_f32_32x32x16_{bf16,f16} / v_mfma_f32_16x16x32_{bf16,f16}:
+//
+//   FF_PREC 1 (bf16x3): x = hi + lo + O(2^-16 x), hi = bf16(x), lo = bf16(x - hi);
+//                       A*B ~ lo_A hi_B + hi_A lo_B + hi_A hi_B
+//   FF_PREC 2 (bf16x6): x = hi + mid + lo + O(2^-24 x), mid = bf16(x - hi),
+//                       lo = bf16(x - hi - mid); the six products of total
+//                       order <= 2 (lo hi, hi lo, mid mid, mid hi, hi mid, hi hi)
+//   FF_PREC 3 (fp16s):  x * 2^e rounded to FP16, with e per matrix such that
+//                       max |x| * 2^e lies in [2^14, 2^15); one product,
+//                       unscaled exactly by 2^-(eA+eB) in FP32
+//
+// Residuals x - hi and x - hi - mid are exact in FP32, and every term
+// product is exact in the FP32 accumulator's input, so the only roundings
+// are the splits themselves and the FP32 accumulation.  Term products are
+// issued smallest first.  The alpha/beta epilogue stays in FP32.
+//
+// Compile-time parameters: FF_MWG, FF_NWG (work-group tile), FF_KWG (slab
+// depth, a multiple of the MFMA k: 16 for MI 32, 32 for MI 16), FF_MI
+// (MFMA block edge 32 or 16), FF_WM x FF_WN (wave grid), FF_PREC, FF_GM
+// (tile-order group height), FF_NAME (kernel symbol; FF_NAME##_v1 is the
+// scalar-load kernel of the same configuration).
+//
+// Data flow: each slab of A (M rows, 8 consecutive k per item) and of B (8
+// consecutive k of one column per item; consecutive threads take
+// consecutive columns, so each load instruction is coalesced) is loaded in
+// FP32, split, and stored in LDS as [term][row][k] for A and [term][n][k]
+// for B, so that both MFMA operands are one 16-byte LDS read per lane: lane
+// l supplies 8 consecutive k of row / column (l % MI) at k offset 8*(l/MI).
+// As in the FP32 kernel the MFMA's first operand comes from B and its second
+// from A, so each lane's accumulators hold one row of C and runs of four
+// consecutive columns.  Double-buffered LDS, one barrier per slab, the next
+// slab's global loads in flight during the MFMAs.
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#ifndef FF_MWG
+#define FF_MWG 128
+#define FF_NWG 128
+#define FF_KWG 32
+#define FF_MI 32
+#define FF_WM 2
+#define FF_WN 2
+#define FF_PREC 1
+#define FF_GM 8
+#define FF_NAME sgemmx_bf16x3_m128n128k32_i32_w2x2
+#endif
+
+#define FF_CAT2(a, b) a##b
+#define FF_CAT(a, b) FF_CAT2(a, b)
+
+namespace {
+
+constexpr int MWG = FF_MWG, NWG = FF_NWG, KWG = FF_KWG, MI = FF_MI;
+constexpr int WM = FF_WM, WN = FF_WN, PREC = FF_PREC, GM = FF_GM;
+constexpr int TERMS = PREC == 1 ? 2 : (PREC == 2 ? 3 : 1);
+constexpr int KB = 8 * (64 / MI);        // MFMA k depth: 16 (MI 32) or 32 (MI 16)
+constexpr int WTM = MWG / WM, WTN = NWG / WN;
+constexpr int RM = WTM / MI, RN = WTN / MI;
+constexpr int NT = 64 * WM * WN;
+constexpr int S = KWG / KB;              // MFMA k steps per slab
+constexpr int ACC = MI * MI / 64;
+// LDS rows of 16-bit values padded by 8: the row stride in dwords,
+// (KWG + 8) / 2, is an odd multiple of 4 for KWG in {16, 32, 64}, so 16-byte
+// reads of 8 consecutive rows fall in disjoint banks.
+constexpr int LDK = KWG + 8;
+constexpr int A_TERM = MWG * LDK, B_TERM = NWG * LDK;   // 16-bit elements
+constexpr int STAGE = TERMS * (A_TERM + B_TERM);
+constexpr int LDS_ELEMS = 2 * STAGE;
+
+static_assert(PREC >= 1 && PREC <= 3, "precision form");
+static_assert(MI == 32 || MI == 16, "MFMA block edge");
+static_assert(MWG % (WM * MI) == 0 && NWG % (WN * MI) == 0, "tile must split into MFMA blocks");
+static_assert(KWG % KB == 0, "slab depth must be a multiple of the MFMA k");
+static_assert(NT <= 1024, "work-group size");
+
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
+typedef short i16x8 __attribute__((ext_vector_type(8)));
+
+template <int E> struct AccT;
+template <> struct AccT<16> { typedef f32x16 T; };
+template <> struct AccT<4> { typedef f32x4 T; };
+typedef typename AccT<ACC>::T acc_t;
+
+// One MFMA on 8 16-bit values per lane, kept as raw 16-bit patterns.
+__device__ __forceinline__ f32x16 mfma16(i16x8 x, i16x8 y, f32x16 c)
+{
+    if constexpr (PREC == 3)
+        return __builtin_amdgcn_mfma_f32_32x32x16_f16(__builtin_bit_cast(f16x8, x), __builtin_bit_cast(f16x8, y),
+                                                      c, 0, 0, 0);
+    else
+        return __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, x),
+                                                       __builtin_bit_cast(bf16x8, y), c, 0, 0, 0);
+}
+__device__ __forceinline__ f32x4 mfma16(i16x8 x, i16x8 y, f32x4 c)
+{
+    if constexpr (PREC == 3)
+        return __builtin_amdgcn_mfma_f32_16x16x32_f16(__builtin_bit_cast(f16x8, x), __builtin_bit_cast(f16x8, y),
+                                                      c, 0, 0, 0);
+    else
+        return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, x),
+                                                       __builtin_bit_cast(bf16x8, y), c, 0, 0, 0);
+}
+
+// Split 8 FP32 values into TERMS vectors of 8 16-bit patterns.  `scale` is
+// the power-of-two prescale of the FP16 form (1 otherwise).
+__device__ __forceinline__ void split8(const float (&x)[8], float scale, i16x8 (&out)[TERMS])
+{
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+        if constexpr (PREC == 3) {
+            const _Float16 h = (_Float16)(x[e] * scale);
+            out[0][e] = __builtin_bit_cast(short, h);
+        } else {
+            float r = x[e];
+#pragma unroll
+            for (int t = 0; t < TERMS; ++t) {
+                const __bf16 b = (__bf16)r;
+                out[t][e] = __builtin_bit_cast(short, b);
+                r -= (float)b;          // exact: the residual fits in FP32
+            }
+        }
+    }
+}
+
+__device__ __forceinline__ void tile_of(int bid, int nbm, int nbn, int& tm, int& tn)
+{
+    const int nb = nbm * nbn;
+    const int q = nb >> 3, r = nb & 7;
+    const int x = bid & 7, i = bid >> 3;
+    const int lin = (x < r) ? x * (q + 1) + i : r * (q + 1) + (x - r) * q + i;
+    const int width = GM * nbn;
+    const int grp = lin / width;
+    const int first = grp * GM;
+    const int gsz = min(nbm - first, GM);
+    const int w = lin - grp * width;
+    tm = first + w % gsz;
+    tn = w / gsz;
+}
+
+// Term products (A term, B term), smallest first.
+struct Pair { int a, b; };
+__device__ constexpr Pair kPairs3[3] = {{1, 0}, {0, 1}, {0, 0}};
+__device__ constexpr Pair kPairs6[6] = {{2, 0}, {0, 2}, {1, 1}, {1, 0}, {0, 1}, {0, 0}};
+__device__ constexpr Pair kPairs1[1] = {{0, 0}};
+constexpr int NPAIRS = PREC == 1 ? 3 : (PREC == 2 ? 6 : 1);
+
+template <bool VEC>
+__device__ __forceinline__ void body(int M, int N, int K, float alpha, const float* __restrict__ A, long lda,
+                                     const float* __restrict__ B, long ldb, float beta, float* __restrict__ C,
+                                     long ldc, const float* __restrict__ prescale, short* smem)
+{
+    const int nbm = (M + MWG - 1) / MWG, nbn = (N + NWG - 1) / NWG;
+    int tm, tn;
+    tile_of(blockIdx.x, nbm, nbn, tm, tn);
+    const int m0 = tm * MWG, n0 = tn * NWG;
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    const int wm = wid / WN, wn = wid % WN;
+    const int lr = lane % MI, lh = lane / MI;
+
+    float sa = 1.0f, sb = 1.0f, unscale = 1.0f;
+    if constexpr (PREC == 3) {
+        sa = prescale[0];
+        sb = prescale[1];
+        unscale = prescale[2];
+    }
+
+    acc_t acc[RM][RN];
+#pragma unroll
+    for (int i = 0; i < RM; ++i)
+#pragma unroll
+        for (int j = 0; j < RN; ++j) acc[i][j] = acc_t{};
+
+    // Load items: 8 consecutive k of one A row, or of one B column.
+    constexpr int KC = KWG / 8;
+    constexpr int NA = MWG * KC, NB = NWG * KC;
+    constexpr int LA = (NA + NT - 1) / NT, LB = (NB + NT - 1) / NT;
+    float ra[LA][8], rb[LB][8];
+    const int nkt = (K + KWG - 1) / KWG;
+
+    // Loads read clamped addresses and keep raw values; validity is
+    // recomputed and applied when the slab is split into LDS, so the loads of
+    // the next slab stay in flight during the MFMAs.
+    auto gload = [&](int kt) {
+        const int kb = kt * KWG;
+#pragma unroll
+        for (int i = 0; i < LA; ++i) {
+            const int item = tid + i * NT;
+            if (NA % NT == 0 || item < NA) {
+                const int row = item / KC, kk = (item % KC) * 8;
+                const int m = m0 + row, k = kb + kk;
+                const bool rok = m < M;
+                const float* p = A + (long)(rok ? m : 0) * lda + k;
+                if constexpr (VEC) {
+                    // K % 4 == 0 and 16-byte aligned rows: two whole vectors.
+                    const f32x4 v0 = *reinterpret_cast<const f32x4*>(rok && k < K ? p : A);
+                    const f32x4 v1 = *reinterpret_cast<const f32x4*>(rok && k + 4 < K ? p + 4 : A);
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) {
+                        ra[i][e] = v0[e];
+                        ra[i][4 + e] = v1[e];
+                    }
+                } else {
+#pragma unroll
+                    for (int e = 0; e < 8; ++e) ra[i][e] = *(rok && k + e < K ? p + e : A);
+                }
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < LB; ++i) {
+            const int item = tid + i * NT;
+            if (NB % NT == 0 || item < NB) {
+                const int col = item % NWG, kk = (item / NWG) * 8;
+                const int n = n0 + col, k = kb + kk;
+                const bool cok = n < N;
+#pragma unroll
+                for (int e = 0; e < 8; ++e) rb[i][e] = *(cok && k + e < K ? B + (long)(k + e) * ldb + n : B);
+            }
+        }
+    };
+    auto sstore = [&](int st, int kt) {
+        const int kb = kt * KWG;
+        short* sA = smem + st * STAGE;
+        short* sB = sA + TERMS * A_TERM;
+#pragma unroll
+        for (int i = 0; i < LA; ++i) {
+            const int item = tid + i * NT;
+            if (NA % NT == 0 || item < NA) {
+                const int row = item / KC, kk = (item % KC) * 8;
+                const bool rok = m0 + row < M;
+                float x[8];
+#pragma unroll
+                for (int e = 0; e < 8; ++e) x[e] = (rok && kb + kk + e < K) ? ra[i][e] : 0.0f;
+                i16x8 t[TERMS];
+                split8(x, sa, t);
+#pragma unroll
+                for (int q = 0; q < TERMS; ++q)
+                    *reinterpret_cast<i16x8*>(sA + q * A_TERM + row * LDK + kk) = t[q];
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < LB; ++i) {
+            const int item = tid + i * NT;
+            if (NB % NT == 0 || item < NB) {
+                const int col = item % NWG, kk = (item / NWG) * 8;
+                const bool cok = n0 + col < N;
+                float x[8];
+#pragma unroll
+                for (int e = 0; e < 8; ++e) x[e] = (cok && kb + kk + e < K) ? rb[i][e] : 0.0f;
+                i16x8 t[TERMS];
+                split8(x, sb, t);
+#pragma unroll
+                for (int q = 0; q < TERMS; ++q)
+                    *reinterpret_cast<i16x8*>(sB + q * B_TERM + col * LDK + kk) = t[q];
+            }
+        }
+    };
+
+    gload(0);
+    sstore(0, 0);
+    __syncthreads();
+    const int arow = (wm * WTM + lr) * LDK + lh * 8;
+    const int bcol = (wn * WTN + lr) * LDK + lh * 8;
+    for (int kt = 0; kt < nkt; ++kt) {
+        const int st = kt & 1;
+        if (kt + 1 < nkt) gload(kt + 1);
+        const short* sA = smem + st * STAGE;
+        const short* sB = sA + TERMS * A_TERM;
+#pragma unroll
+        for (int s = 0; s < S; ++s) {
+            i16x8 av[TERMS][RM], bv[TERMS][RN];
+#pragma unroll
+            for (int q = 0; q < TERMS; ++q) {
+#pragma unroll
+                for (int i = 0; i < RM; ++i)
+                    av[q][i] = *reinterpret_cast<const i16x8*>(sA + q * A_TERM + arow + i * MI * LDK + s * KB);
+#pragma unroll
+                for (int j = 0; j < RN; ++j)
+                    bv[q][j] = *reinterpret_cast<const i16x8*>(sB + q * B_TERM + bcol + j * MI * LDK + s * KB);
+            }
+#pragma unroll
+            for (int p = 0; p < NPAIRS; ++p) {
+                const Pair pr = PREC == 1 ? kPairs3[p] : (PREC == 2 ? kPairs6[p] : kPairs1[p]);
+#pragma unroll
+                for (int i = 0; i < RM; ++i)
+#pragma unroll
+                    for (int j = 0; j < RN; ++j) acc[i][j] = mfma16(bv[pr.b][j], av[pr.a][i], acc[i][j]);
+            }
+        }
+        if (kt + 1 < nkt) sstore(st ^ 1, kt + 1);
+        __syncthreads();
+    }
+
+    // Epilogue as in the FP32 kernel; the FP16 form first removes its
+    // prescale (a power of two, exact).
+    const bool cvec = ((reinterpret_cast<uintptr_t>(C) & 15) == 0) && ((ldc & 3) == 0);
+    const bool use_beta = (beta != 0.0f);
+#pragma unroll
+    for (int i = 0; i < RM; ++i) {
+        const int m = m0 + wm * WTM + i * MI + lr;
+        if (m >= M) continue;
+        float* crow = C + (long)m * ldc;
+#pragma unroll
+        for (int j = 0; j < RN; ++j) {
+#pragma unroll
+            for (int g = 0; g < ACC / 4; ++g) {
+                const int n = n0 + wn * WTN + j * MI + (MI == 32 ? 8 * g : 0) + 4 * lh;
+                f32x4 v;
+#pragma unroll
+                for (int c = 0; c < 4; ++c) v[c] = acc[i][j][4 * g + c] * unscale;
+                if (cvec && n + 4 <= N) {
+                    f32x4 o = alpha * v;
+                    if (use_beta) o += beta * *reinterpret_cast<const f32x4*>(crow + n);
+                    *reinterpret_cast<f32x4*>(crow + n) = o;
+                } else {
+#pragma unroll
+                    for (int c = 0; c < 4; ++c) {
+                        if (n + c < N) {
+                            float o = alpha * v[c];
+                            if (use_beta) o += beta * crow[n + c];
+                            crow[n + c] = o;
+                        }
+                    }
+                }
+            }
+        }
+    }
+}
+
+}  // namespace
+
+// Same argument list as the FP32 variants; `ws`, `splits` and `kper` are
+// unused here, `prescale` (FP16 form only) points to {2^eA, 2^eB, 2^-(eA+eB)}.
+extern "C" __global__ void __launch_bounds__(NT)
+FF_NAME(int M, int N, int K, float alpha, const float* __restrict__ A, long lda, const float* __restrict__ B,
+        long ldb, float beta, float* __restrict__ C, long ldc, float* __restrict__ ws, int splits, int kper,
+        const float* __restrict__ prescale)
+{
+    (void)ws;
+    (void)splits;
+    (void)kper;
+    __shared__ __attribute__((aligned(16))) short smem[LDS_ELEMS];
+    body<true>(M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, prescale, smem);
+}
+
+extern "C" __global__ void __launch_bounds__(NT)
+FF_CAT(FF_NAME, _v1)(int M, int N, int K, float alpha, const float* __restrict__ A, long lda,
+                     const float* __restrict__ B, long ldb, float beta, float* __restrict__ C, long ldc,
+                     float* __restrict__ ws, int splits, int kper, const float* __restrict__ prescale)
+{
+    (void)ws;
+    (void)splits;
+    (void)kper;
+    __shared__ __attribute__((aligned(16))) short smem[LDS_ELEMS];
+    body<false>(M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, prescale, smem);
+}

@@ -29,7 +29,7 @@ import time
 import numpy as np
 
 from . import abi, datagen, space, tuned
-from .tune import load_rows, kernel_hash
+from .tune import load_rows, kernel_hash, current_hashes
 
 PKG = os.path.dirname(os.path.abspath(__file__))
 DATA_DIR = os.path.join(PKG, "data")
@@ -49,16 +49,18 @@ def read_variants(directory=tuned.VARIANT_DIR):
     return out
 
 
-def matrix(rows, shapes, beta=0.0, nv=None):
-    """Time matrix t[v][s] (ms); +inf where a variant failed or is missing."""
+def matrix(rows, shapes, beta=0.0, nv=None, data="uniform", field="ms"):
+    """Matrix x[v][s] of a row field (default the time in ms) for one input
+    distribution; +inf where a variant failed or is missing."""
     nv = nv if nv is not None else 1 + max(r["variant"] for r in rows)
     idx = {tuple(s): j for j, s in enumerate(shapes)}
     t = np.full((nv, len(shapes)), np.inf)
     for r in rows:
         j = idx.get((r["M"], r["N"], r["K"]))
-        if j is None or r["beta"] != beta or r.get("status") != "ok":
+        if (j is None or r["beta"] != beta or r.get("status") != "ok"
+                or r.get("data", "uniform") != data or r.get(field) is None):
             continue
-        t[r["variant"], j] = r["ms"]
+        t[r["variant"], j] = r[field]
     return t
 
 
@@ -113,8 +115,75 @@ def evaluate(t, shapes, train_idx, kappa, extra=()):
     }
 
 
+def precision_report(rows, variants, write_sets=False, log=print):
+    """Split-precision forms on the lognormal grid: per shape and form the
+    fastest variant, its speedup over the fastest FP32 variant on the same
+    inputs, and its errors against the FP64 reference; a k=4 set per form."""
+    shapes = datagen.grid27()
+    nv = len(variants)
+    t = matrix(rows, shapes, 0.0, nv, data="lognormal")
+    if not np.isfinite(t).any():
+        return None
+    en = matrix(rows, shapes, 0.0, nv, data="lognormal", field="err_norm")
+    ec = matrix(rows, shapes, 0.0, nv, data="lognormal", field="err_comp")
+    prec = np.array([variants[v].prec for v in range(nv)])
+    train, _ = datagen.checkerboard_split(shapes)
+    train_idx = [shapes.index(s) for s in train]
+    out = {"forms": {}, "per_shape": []}
+    best = {}
+    for p in range(4):
+        tp = np.where((prec == p)[:, None], t, np.inf)
+        if not np.isfinite(tp).any(axis=0).all():
+            continue
+        bid = [int(np.argmin(tp[:, j])) for j in range(len(shapes))]
+        best[p] = bid
+        form = abi.FORM_NAMES[p]
+        errs = [float(en[bid[j], j]) for j in range(len(shapes))]
+        comps = [float(ec[bid[j], j]) for j in range(len(shapes))]
+        # The most accurate variant of the form as well (errors differ by
+        # accumulation order).
+        worst_all = float(np.max(np.where(np.isfinite(tp), en, 0.0)))
+        rec = {"geomean_tflops_best": geomean(tflops(s, tp[bid[j], j]) for j, s in enumerate(shapes)),
+               "max_err_norm_of_fastest": max(errs), "median_err_norm_of_fastest": float(np.median(errs)),
+               "max_err_comp_of_fastest": max(comps), "max_err_norm_any_variant": worst_all}
+        if p > 0:
+            kappa, cost, _ = abi.ptune_select(tp, 4, shapes=train_idx, method=-1)
+            ev = evaluate(tp, shapes, train_idx, kappa)
+            rec.update(k4_kappa=list(kappa), k4_names=[variants[v].name for v in kappa],
+                       k4_train_frac=1.0 / cost, k4_heldout_realised=ev["frac_heldout_realised"],
+                       k4_geomean_tflops=ev["geomean_tflops_realised"])
+            if write_sets:
+                members = [(v, variants[v]) for v in kappa]
+                rules = [(*shapes[j], w, ev["costs"][i])
+                         for i, (j, w) in enumerate(zip(train_idx, ev["winners"]))]
+                tuned.write_set_file(
+                    tuned.set_path(4, form), members, rules, form=form,
+                    comments=(f"PortabilityTune k=4 for the {form} form on the 14 checkerboard training "
+                              f"shapes, lognormal operands",))
+        out["forms"][form] = rec
+        log(f"[precision] {form}: geomean {rec['geomean_tflops_best']:.2f} TFLOP/s (per-shape best), "
+            f"normwise error of the fastest: median {rec['median_err_norm_of_fastest']:.2e} "
+            f"max {rec['max_err_norm_of_fastest']:.2e}")
+    for j, s in enumerate(shapes):
+        rec = {"M": s[0], "N": s[1], "K": s[2]}
+        for p, bid in best.items():
+            form = abi.FORM_NAMES[p]
+            rec[form] = {"variant": bid[j], "tflops": tflops(s, t[bid[j], j]),
+                         "err_norm": float(en[bid[j], j]), "err_comp": float(ec[bid[j], j])}
+            if p > 0 and 0 in best:
+                rec[form]["speedup_vs_fp32"] = float(t[best[0][j], j] / t[bid[j], j])
+        out["per_shape"].append(rec)
+    if 0 in best:
+        for p in best:
+            if p > 0:
+                form = abi.FORM_NAMES[p]
+                out["forms"][form]["geomean_speedup_vs_fp32"] = geomean(
+                    r[form]["speedup_vs_fp32"] for r in out["per_shape"])
+    return out
+
+
 def run(table=TABLE, write_sets=False, splits=5, log=print):
-    rows = load_rows(table, kernel_hash())
+    rows = load_rows(table, current_hashes())
     if not rows:
         raise RuntimeError(f"no rows for the current kernel source in {table}")
     variants = read_variants()
@@ -201,6 +270,7 @@ def run(table=TABLE, write_sets=False, splits=5, log=print):
                            "slowdown_q75": float(np.percentile(col, 75)),
                            "n_ok": int(np.isfinite(ts[:, j]).sum())})
     report["square_sweep"] = sq_out
+    report["precision"] = precision_report(rows, variants, write_sets, log)
     report["screen"] = {
         "ok": sum(1 for r in rows if r.get("status") == "ok"),
         "wrong": sum(1 for r in rows if r.get("status") == "wrong"),

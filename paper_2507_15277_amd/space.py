@@ -44,10 +44,21 @@ class Variant:
     lds: int
     gm: int = 8
     sg: int = 1
+    prec: int = 0   # 0 FP32 MFMA; 1 bf16x3, 2 bf16x6, 3 scaled fp16 (csrc/sgemm_split.hip)
 
     @property
     def mk(self):
+        if self.prec:
+            return 16 if self.mi == 32 else 32
         return 2 if self.mi == 32 else 4
+
+    @property
+    def terms(self):
+        return {0: 1, 1: 2, 2: 3, 3: 1}[self.prec]
+
+    @property
+    def source(self):
+        return "sgemm_split.hip" if self.prec else "sgemm_variant.hip"
 
     @property
     def threads(self):
@@ -72,12 +83,17 @@ class Variant:
 
     @property
     def lds_bytes(self):
+        if self.prec:
+            return 2 * 2 * self.terms * (self.mwg + self.nwg) * (self.kwg + 8)
         stage = self.mwg * (self.kwg + 4) + self.kwg * (self.nwg + 4)
         red = (self.sk - 1) * self.mwg * self.nwg
         return 4 * (max(2 * stage, red) if self.lds else max(red, 1))
 
     @property
     def name(self):
+        if self.prec:
+            form = PREC_NAMES[self.prec]
+            return f"sgemmx_{form}_m{self.mwg}n{self.nwg}k{self.kwg}_i{self.mi}_w{self.wm}x{self.wn}"
         n = (f"sgemm_m{self.mwg}n{self.nwg}k{self.kwg}_i{self.mi}_w{self.wm}x{self.wn}"
              f"_s{self.sk}_v{self.vw}_l{self.lds}")
         if self.gm != 8:
@@ -87,21 +103,45 @@ class Variant:
         return n
 
     def defines(self):
+        if self.prec:
+            return {"FF_MWG": self.mwg, "FF_NWG": self.nwg, "FF_KWG": self.kwg, "FF_MI": self.mi,
+                    "FF_WM": self.wm, "FF_WN": self.wn, "FF_PREC": self.prec, "FF_GM": self.gm,
+                    "FF_NAME": self.name}
         return {"FF_MWG": self.mwg, "FF_NWG": self.nwg, "FF_KWG": self.kwg, "FF_MI": self.mi,
                 "FF_WM": self.wm, "FF_WN": self.wn, "FF_SK": self.sk, "FF_VW": self.vw,
                 "FF_LDS": self.lds, "FF_GM": self.gm, "FF_SG": self.sg, "FF_NAME": self.name}
 
     def descriptor(self, vid):
-        """Manifest / set-file descriptor: id name MWG NWG KWG MI WM WN SK VW LDS GM SG."""
+        """Manifest / set-file descriptor: id name MWG NWG KWG MI WM WN SK VW LDS GM SG PREC."""
         return (f"{vid} {self.name} {self.mwg} {self.nwg} {self.kwg} {self.mi} {self.wm} {self.wn} "
-                f"{self.sk} {self.vw} {self.lds} {self.gm} {self.sg}")
+                f"{self.sk} {self.vw} {self.lds} {self.gm} {self.sg} {self.prec}")
 
     def as_dict(self):
         return asdict(self)
 
 
+PREC_NAMES = {0: "fp32", 1: "bf16x3", 2: "bf16x6", 3: "fp16s"}
+MAX_SPLIT_LDS_BYTES = 160 * 1024
+
+
+def legal_split(v: Variant) -> bool:
+    """Constraints of the split-precision kernel (csrc/sgemm_split.hip)."""
+    if v.mi not in (16, 32) or v.sk != 1 or v.sg != 1 or v.lds != 1 or v.vw != 4:
+        return False
+    if v.mwg % (v.wm * v.mi) or v.nwg % (v.wn * v.mi) or v.kwg % v.mk:
+        return False
+    if v.threads > MAX_THREADS or v.acc_regs > MAX_ACC or v.lds_bytes > MAX_SPLIT_LDS_BYTES:
+        return False
+    # Staged FP32 slab values per thread (8 per load item).
+    if (v.mwg + v.nwg) * v.kwg > MAX_STAGING * v.threads:
+        return False
+    return True
+
+
 def legal(v: Variant) -> bool:
     """Constraints of the kernel template plus resource budgets."""
+    if v.prec:
+        return legal_split(v)
     if v.mi not in (16, 32) or v.vw not in (1, 2, 4) or v.lds not in (0, 1):
         return False
     if v.sg not in SPLITS:
@@ -225,3 +265,37 @@ def family(n=320, seed=0):
             seen.add(v)
         idx += 1
     return chosen[:n]
+
+
+# Split-precision family: the same handful of work-group shapes for each form.
+SPLIT_SHAPES = [
+    # (MWG, NWG, KWG, MI, WM, WN)
+    (128, 128, 32, 32, 2, 2),
+    (128, 128, 16, 32, 2, 2),
+    (256, 128, 16, 32, 4, 2),
+    (128, 256, 16, 32, 2, 4),
+    (64, 64, 32, 32, 2, 2),
+    (64, 64, 64, 32, 2, 2),
+    (64, 128, 32, 32, 2, 2),
+    (128, 64, 32, 32, 2, 2),
+    (32, 32, 64, 32, 1, 1),
+    (32, 32, 32, 16, 2, 2),
+    (64, 64, 32, 16, 2, 2),
+    (128, 128, 32, 16, 4, 4),
+]
+
+
+def split_family(precs=(1, 2, 3)):
+    out = []
+    for prec in precs:
+        for (mwg, nwg, kwg, mi, wm, wn) in SPLIT_SHAPES:
+            v = Variant(mwg, nwg, kwg, mi, wm, wn, 1, 4, 1, 8, 1, prec)
+            if legal(v):
+                out.append(v)
+    return out
+
+
+def full_family():
+    """Everything that is compiled: the FP32 family, then the split forms
+    (appended, so FP32 variant ids do not depend on the split family)."""
+    return family() + split_family()

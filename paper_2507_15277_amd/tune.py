@@ -15,7 +15,12 @@ Each result is one JSON line appended to the table file, so an interrupted
 run resumes where it stopped (keys already present are skipped).  Rows
 carry a hash of the kernel source; rows from another source are ignored.
 
-Usage: python -m paper_2507_15277_amd.tune --out table.jsonl [--sets grid,extra,square]
+The "precision" set times every variant, FP32 and split-precision forms,
+on the 27 grid shapes with lognormal operands, and records each result's
+normwise relative error and largest componentwise error against the FP64
+screening reference.
+
+Usage: python -m paper_2507_15277_amd.tune --out table.jsonl [--sets grid,extra,square,precision]
 """
 from __future__ import annotations
 
@@ -32,36 +37,72 @@ from . import abi, datagen
 PKG = os.path.dirname(os.path.abspath(__file__))
 VARIANT_DIR = os.path.join(PKG, "variants")
 KERNEL_SRC = os.path.join(PKG, "csrc", "sgemm_variant.hip")
+SPLIT_SRC = os.path.join(PKG, "csrc", "sgemm_split.hip")
 
 # Seed tags of the workloads (first element of every seed tuple).
-CFG_SQUARE, CFG_GRID = 2, 3
+CFG_SQUARE, CFG_GRID, CFG_PRECISION = 2, 3, 5
+
+# Per-product truncation error of each 16-bit form, as a multiple of |a||b|,
+# and its number of term products.  Round-to-nearest bf16 keeps 8 bits
+# (|x - hi| <= 2^-8 |x|), fp16 keeps 11; the dropped terms of bf16x3 are
+# hi*d + d*hi + lo*lo + smaller (3.03 * 2^-16), those of bf16x6 mid*lo +
+# lo*mid + hi*d + d*hi + smaller (4.03 * 2^-24), and fp16s rounds both
+# operands once (2 * 2^-11).
+FORM_TRUNCATION = {1: 3.1 * 2.0 ** -16, 2: 4.2 * 2.0 ** -24, 3: 2.1 * 2.0 ** -11}
+FORM_PRODUCTS = {0: 1, 1: 3, 2: 6, 3: 1}
 
 
-def kernel_hash() -> str:
-    with open(KERNEL_SRC, "rb") as f:
+def _sha(path):
+    with open(path, "rb") as f:
         return hashlib.sha1(f.read()).hexdigest()[:12]
 
 
-def read_manifest(directory=VARIANT_DIR):
+def kernel_hash() -> str:
+    """Build hash of the FP32 variant kernel source."""
+    return _sha(KERNEL_SRC)
+
+
+def split_hash() -> str:
+    """Build hash of the split-precision kernel source."""
+    return _sha(SPLIT_SRC)
+
+
+def current_hashes():
+    return {kernel_hash(), split_hash()}
+
+
+def screen_scale(prec, K):
+    """Factor applied to the FP32 bound 4*K*2^-24*|A||B| for a form: its
+    truncation error plus FP32 accumulation of all its term products."""
+    if prec == 0 or K == 0:
+        return 1.0
+    u = 2.0 ** -24
+    return FORM_TRUNCATION[prec] / (4.0 * K * u) + 1.05 * FORM_PRODUCTS[prec]
+
+
+def read_manifest(directory=VARIANT_DIR, with_prec=False):
     out = []
     with open(os.path.join(directory, "manifest.txt")) as f:
         for line in f:
             if line.strip() and not line.startswith("#"):
                 p = line.split()
-                out.append((int(p[0]), p[1]))
+                out.append((int(p[0]), p[1], int(p[14])) if with_prec else (int(p[0]), p[1]))
     return out
 
 
 def workload(sets):
-    """[(cfg, M, N, K, beta)] for the requested shape sets."""
+    """[(cfg, M, N, K, beta, data)] for the requested shape sets; data is
+    "uniform" (entries on [-1, 1)) or "lognormal" (the precision workload)."""
     jobs = []
     if "grid" in sets:
-        jobs += [(CFG_GRID, M, N, K, 0.0) for (M, N, K) in datagen.grid27()]
+        jobs += [(CFG_GRID, M, N, K, 0.0, "uniform") for (M, N, K) in datagen.grid27()]
     if "extra" in sets:
-        jobs += [(CFG_GRID, M, N, K, 0.0) for (M, N, K) in datagen.SKEWED_EXTRA]
+        jobs += [(CFG_GRID, M, N, K, 0.0, "uniform") for (M, N, K) in datagen.SKEWED_EXTRA]
     if "square" in sets:
         for beta in (0.0, 0.5):
-            jobs += [(CFG_SQUARE, M, N, K, beta) for (M, N, K) in datagen.square_shapes()]
+            jobs += [(CFG_SQUARE, M, N, K, beta, "uniform") for (M, N, K) in datagen.square_shapes()]
+    if "precision" in sets:
+        jobs += [(CFG_PRECISION, M, N, K, 0.0, "lognormal") for (M, N, K) in datagen.grid27()]
     # A shape shared by two sets is timed once (the first set's inputs).
     seen, out = set(), []
     for j in jobs:
@@ -72,11 +113,22 @@ def workload(sets):
 
 
 def key(row):
-    return (row["M"], row["N"], row["K"], row["beta"], row["variant"])
+    return (row["M"], row["N"], row["K"], row["beta"], row.get("data", "uniform"), row["variant"])
+
+
+def operands(cfg, M, N, K, beta, data):
+    if data == "lognormal":
+        A = datagen.lognormal((cfg, M, N, K, datagen.OP_A), M, K)
+        B = datagen.lognormal((cfg, M, N, K, datagen.OP_B), K, N)
+        C0 = datagen.uniform((cfg, M, N, K, datagen.OP_C), M, N) if beta != 0.0 else None
+        return A, B, C0
+    return datagen.gemm_operands(cfg, M, N, K, beta=beta)
 
 
 def load_rows(path, khash=None):
-    """Complete rows of a table file (a truncated last line is skipped)."""
+    """Complete rows of a table file (a truncated last line is skipped).
+    ``khash``: a build hash or a set of them; rows of other builds are
+    dropped."""
     rows = []
     if not os.path.exists(path):
         return rows
@@ -89,7 +141,7 @@ def load_rows(path, khash=None):
                 r = json.loads(line)
             except json.JSONDecodeError:
                 continue
-            if khash is None or r.get("build") == khash:
+            if khash is None or r.get("build") in ({khash} if isinstance(khash, str) else khash):
                 rows.append(r)
     return rows
 
@@ -104,24 +156,26 @@ def tune(out, sets=("grid", "extra", "square"), variants=None, target_ms=2.0, tr
          warmup=2, log=print):
     import torch
 
-    khash = kernel_hash()
-    manifest = read_manifest()
+    hashes = {0: kernel_hash(), 1: split_hash()}
+    manifest = read_manifest(with_prec=True)
     n = abi.variant_manifest_load(VARIANT_DIR)
     if n != len(manifest):
         raise RuntimeError("manifest and loaded variant count differ")
     if variants is not None:
         manifest = [m for m in manifest if m[0] in set(variants)]
-    done = {key(r) for r in load_rows(out, khash)}
+    done = {key(r) for r in load_rows(out, current_hashes())}
     dev = torch.cuda.get_device_properties(0)
     device = f"{dev.name} {dev.gcnArchName.split(':')[0]}"
     f = open(out, "a")
     t_start = time.time()
-    for (cfg, M, N, K, beta) in workload(sets):
-        todo = [(vid, name) for vid, name in manifest if (M, N, K, beta, vid) not in done]
+    for (cfg, M, N, K, beta, data) in workload(sets):
+        # The split-precision forms are timed on the precision workload only.
+        todo = [(vid, name, prec) for vid, name, prec in manifest
+                if (M, N, K, beta, data, vid) not in done and (prec == 0 or data == "lognormal")]
         if not todo:
             continue
         t0 = time.time()
-        A, B, C0 = datagen.gemm_operands(cfg, M, N, K, beta=beta)
+        A, B, C0 = operands(cfg, M, N, K, beta, data)
         dA = torch.from_numpy(A).cuda()
         dB = torch.from_numpy(B).cuda()
         dC0 = torch.from_numpy(C0).cuda() if C0 is not None else None
@@ -129,24 +183,29 @@ def tune(out, sets=("grid", "extra", "square"), variants=None, target_ms=2.0, tr
         ref = torch.empty(M * N, dtype=torch.float64, device="cuda")
         tol = torch.empty(M * N, dtype=torch.float64, device="cuda")
         abi.screen_reference(M, N, K, 1.0, dA, K, dB, N, beta, dC0, N, ref, tol)
-        best = math.inf
+        best = {}
         flops = 2.0 * M * N * K
         n_ok = 0
-        for vid, name in todo:
+        for vid, name, prec in todo:
             if beta == 0.0:
                 dC.fill_(float("nan"))
             else:
                 dC.copy_(dC0)
-            row = {"device": device, "M": M, "N": N, "K": K, "beta": beta, "variant": vid,
-                   "name": name, "build": khash}
+            row = {"device": device, "M": M, "N": N, "K": K, "beta": beta, "data": data, "variant": vid,
+                   "name": name, "prec": prec, "build": hashes[min(prec, 1)]}
+            scale = screen_scale(prec, K)
             try:
                 abi.sgemm_variant(vid, M, N, K, 1.0, dA, K, dB, N, beta, dC, N)
-                nbad, ratio = abi.screen_compare(M, N, dC, N, ref, tol)
+                nbad, ratio, rel = abi.screen_compare(M, N, dC, N, ref, tol, tol_scale=scale, norms=True)
             except abi.FewfitError as e:
                 row.update(status="launch_fail", error=str(e))
                 f.write(json.dumps(row) + "\n")
                 continue
             row["err_ratio"] = ratio if math.isfinite(ratio) else None
+            row["err_norm"] = rel
+            if beta == 0.0 and math.isfinite(ratio):
+                # tol = 4*K*u*|A||B| exactly when alpha = 1 and beta = 0.
+                row["err_comp"] = ratio * scale * 4.0 * K * 2.0 ** -24
             if nbad:
                 row.update(status="wrong", nbad=nbad)
                 f.write(json.dumps(row) + "\n")
@@ -156,7 +215,7 @@ def tune(out, sets=("grid", "extra", "square"), variants=None, target_ms=2.0, tr
             # One probe trial sizes the repetition count.
             probe = abi.sgemm_time(vid, M, N, K, 1.0, dA, K, dB, N, beta, dC, N,
                                    warmup=1, reps=1, trials=1)[0]
-            if probe > 20.0 * best:
+            if probe > 20.0 * best.get(prec, math.inf):
                 ms_list = [probe]       # far off the best: not worth more time
                 reps, ntr = 1, 1
             else:
@@ -165,7 +224,7 @@ def tune(out, sets=("grid", "extra", "square"), variants=None, target_ms=2.0, tr
                 ms_list = abi.sgemm_time(vid, M, N, K, 1.0, dA, K, dB, N, beta, dC, N,
                                          warmup=warmup, reps=reps, trials=ntr)
             med = _median(ms_list)
-            best = min(best, med)
+            best[prec] = min(best.get(prec, math.inf), med)
             n_ok += 1
             row.update(status="ok", ms=med, ms_mean=sum(ms_list) / len(ms_list),
                        ms_min=min(ms_list), ms_max=max(ms_list), reps=reps, trials=ntr,
@@ -174,9 +233,9 @@ def tune(out, sets=("grid", "extra", "square"), variants=None, target_ms=2.0, tr
         f.flush()
         del dA, dB, dC0, dC, ref, tol
         torch.cuda.empty_cache()
-        log(f"[tune] {M}x{N}x{K} beta={beta}: {n_ok}/{len(todo)} ok, best "
-            f"{flops / best / 1e9 if best < math.inf else 0:.2f} TFLOP/s, {time.time() - t0:.1f} s "
-            f"(total {time.time() - t_start:.0f} s)")
+        bests = " ".join(f"{abi.FORM_NAMES[p]} {flops / b / 1e9:.2f}" for p, b in sorted(best.items()))
+        log(f"[tune] {M}x{N}x{K} beta={beta} {data}: {n_ok}/{len(todo)} ok, best TFLOP/s {bests}, "
+            f"{time.time() - t0:.1f} s (total {time.time() - t_start:.0f} s)")
         sys.stdout.flush()
     f.close()
 

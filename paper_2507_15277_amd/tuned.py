@@ -28,8 +28,10 @@ VARIANT_DIR = os.path.join(PKG, "variants")
 FIXED_SET = os.path.join(SETS_DIR, "fixed_k1.txt")
 
 
-def set_path(k: int) -> str:
-    return os.path.join(SETS_DIR, f"set_k{k}.txt")
+def set_path(k: int, form: str = "fp32") -> str:
+    if form == "fp32":
+        return os.path.join(SETS_DIR, f"set_k{k}.txt")
+    return os.path.join(SETS_DIR, f"set_{form}_k{k}.txt")
 
 
 def default_set_path() -> str:
@@ -42,7 +44,7 @@ def _fmt_cost(c):
     return "inf" if c == float("inf") else f"{c:.17g}"
 
 
-def write_set_file(path, members, rules, arch="gfx950", codedir="../variants", comments=()):
+def write_set_file(path, members, rules, arch="gfx950", codedir="../variants", comments=(), form="fp32"):
     """members: [(id, space.Variant)]; rules: [(M, N, K, winner_id, [cost per member])]."""
     ids = [vid for vid, _ in members]
     for r in rules:
@@ -50,6 +52,8 @@ def write_set_file(path, members, rules, arch="gfx950", codedir="../variants", c
             raise ValueError(f"rule {r[:4]} does not match the set")
     lines = [f"# {c}" for c in comments]
     lines += ["fewfit-set 1", f"arch {arch}", f"codedir {codedir}"]
+    if form != "fp32":
+        lines.append(f"form {form}")
     lines += [f"variant {v.descriptor(vid)}" for vid, v in members]
     lines += [f"rule {M} {N} {K} {vid} " + " ".join(_fmt_cost(c) for c in cost)
               for (M, N, K, vid, cost) in rules]

@@ -71,6 +71,14 @@ def test_null_operands_allowed_when_not_read(L):
     assert L.sgemm(4, 4, 0, 1.0, None, 1, None, 4, 1.0, 8, 4, None) == 0
 
 
+def test_form_arguments(L):
+    assert L.sgemm_form(7, 4, 4, 4, 1.0, 8, 4, 8, 4, 0.0, 8, 4, None) == abi.FF_ERR_ARG
+    assert L.sgemm_form(-1, 4, 4, 4, 1.0, 8, 4, 8, 4, 0.0, 8, 4, None) == abi.FF_ERR_ARG
+    assert L.variant_select_form(4, 1, 1, 1) == abi.FF_ERR_ARG
+    assert L.variant_select_form(2, 1, 1, 1) == abi.FF_ERR_NO_SET
+    assert L.sgemm_form(1, -1, 4, 4, 1.0, 8, 4, 8, 4, 0.0, 8, 4, None) == abi.FF_ERR_M
+
+
 def test_no_set_loaded(L):
     assert L.variant_select(256, 256, 256) == abi.FF_ERR_NO_SET
     assert L.sgemm(4, 4, 4, 1.0, 8, 4, 8, 4, 0.0, 8, 4, None) == abi.FF_ERR_NO_SET
@@ -95,6 +103,14 @@ GOOD_VARIANT = space.DEFAULT.descriptor(0)
     (f"fewfit-set 1\narch gfx950\ncodedir .\nvariant {GOOD_VARIANT}\nrule 1 1 1 0 -1\nend\n", abi.FF_ERR_PARSE),
     (f"fewfit-set 1\narch gfx950\ncodedir .\nvariant {GOOD_VARIANT}\nrule 1 1 1 0 x\nend\n", abi.FF_ERR_PARSE),
     (f"fewfit-set 1\nfoo 1\nend\n", abi.FF_ERR_PARSE),
+    # a split-precision descriptor must not carry split-K groups
+    ("fewfit-set 1\narch gfx950\ncodedir .\nform bf16x3\nvariant 5 x 64 64 32 32 2 2 2 4 1 8 1 1\n"
+     "rule 1 1 1 5 0\nend\n", abi.FF_ERR_PARSE),
+    # members must match the set's form
+    (f"fewfit-set 1\narch gfx950\ncodedir .\nform bf16x6\nvariant {GOOD_VARIANT}\nrule 1 1 1 0 0\nend\n",
+     abi.FF_ERR_PARSE),
+    (f"fewfit-set 1\narch gfx950\ncodedir .\nform fp64\nvariant {GOOD_VARIANT}\nrule 1 1 1 0 0\nend\n",
+     abi.FF_ERR_PARSE),
 ])
 def test_set_file_parse_errors(L, tmp_path, body, code):
     p = tmp_path / "set.txt"

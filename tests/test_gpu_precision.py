@@ -1,0 +1,115 @@
+"""GPU parity of the split-precision forms (bf16x3, bf16x6, scaled fp16).
+
+Each variant's result is compared with the oracle's exact value of the same
+form (the 16-bit pieces formed by definition, their kept products summed in
+FP64): the difference may only be FP32 accumulation of the term products,
+bounded like the FP32 GEMM's.  The error against the true product is
+checked against the form's truncation bound."""
+import os
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+import oracle
+from oracle import precision_ref as pr
+from paper_2507_15277_amd import abi, datagen, tuned
+from tests.gpu_util import run_gemm
+
+pytestmark = pytest.mark.gpu
+
+VARIANT_DIR = tuned.VARIANT_DIR
+FORMS = {1: "bf16x3", 2: "bf16x6", 3: "fp16s"}
+
+
+def _split_variants():
+    out = []
+    for line in open(os.path.join(VARIANT_DIR, "manifest.txt")):
+        if not line.startswith("#"):
+            f = line.split()
+            if int(f[14]) > 0:
+                out.append((int(f[0]), f[1], FORMS[int(f[14])]))
+    return out
+
+
+@pytest.fixture(scope="module")
+def split_loaded():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    abi.variant_manifest_load(VARIANT_DIR)
+    v = _split_variants()
+    assert {f for _, _, f in v} == set(FORMS.values())
+    return v
+
+
+def _check_form(C, A, B, form, alpha=1.0, beta=0.0, C0=None, label=""):
+    K = A.shape[1]
+    Cs, Ts = pr.split_form_gemm(A, B, form, alpha, beta, C0)
+    tol = pr.accumulation_tolerance(K, form, alpha, beta, Ts, Cs, C0)
+    err = np.abs(C.astype(np.float64) - Cs)
+    bad = ~(err <= tol)
+    assert not bad.any(), (f"{label}: {int(bad.sum())} elements off the {form} value; max err/tol "
+                           f"{np.max(err / np.maximum(tol, 1e-300)):.3g}")
+
+
+@pytest.mark.parametrize("shape,lds", [((133, 97, 75), (3, 5, 2)), ((200, 328, 136), (0, 0, 0)),
+                                       ((1, 1, 1), (0, 0, 0)), ((70, 300, 520), (4, 0, 4))])
+def test_split_forms_match_oracle(split_loaded, shape, lds):
+    M, N, K = shape
+    lda, ldb, ldc = K + lds[0], N + lds[1], N + lds[2]
+    A = datagen.lognormal((40, M, N, K, 0), M, K)
+    B = datagen.lognormal((40, M, N, K, 1), K, N)
+    C0 = datagen.uniform((40, M, N, K, 2), M, N)
+    fails = []
+    for vid, name, form in split_loaded:
+        C, guard = run_gemm(vid, A, B, C0, 1.5, -0.5, lda, ldb, ldc)
+        try:
+            _check_form(C, A, B, form, 1.5, -0.5, C0, name)
+            assert guard, f"{name}: wrote outside C"
+        except AssertionError as e:
+            fails.append(str(e))
+    assert not fails, "\n".join(fails[:10])
+
+
+def test_split_forms_error_against_true_product(split_loaded):
+    # alpha = 1, beta = 0: the error against the exact product is the form's
+    # truncation plus FP32 accumulation.
+    M, N, K = 96, 160, 640
+    A = datagen.lognormal((41, 0), M, K)
+    B = datagen.lognormal((41, 1), K, N)
+    _, S, T = oracle.ref_gemm(A, B)
+    for vid, name, form in split_loaded:
+        C, _ = run_gemm(vid, A, B, np.full((M, N), np.nan, np.float32), 1.0, 0.0)
+        n = len(pr.PAIRS[form])
+        bound = (pr.truncation_bound(form) + 4.2 * n * K * 2.0 ** -24) * T
+        assert np.all(np.abs(C - S) <= bound), name
+
+
+def test_bf16_forms_exact_on_bf16_values(split_loaded):
+    # Small integers are bf16 and fp16 values: every form is exact when the
+    # partial sums stay below 2^24 (fp16s: |x| <= 100 scales by 2^8 at most,
+    # products up to 2^30 scaled back exactly).
+    M, N, K = 64, 96, 200
+    A = datagen.integers((42, 0), M, K, -100, 100)
+    B = datagen.integers((42, 1), K, N, -100, 100)
+    _, S, _ = oracle.ref_gemm(A, B)
+    for vid, name, form in split_loaded:
+        if form == "fp16s":
+            continue
+        C, _ = run_gemm(vid, A, B, None, 1.0, 0.0)
+        assert np.array_equal(C.astype(np.float64), S), name
+
+
+def test_fp16_scale_follows_the_data(split_loaded):
+    # Scaling the inputs by powers of two changes the prescale but not the
+    # result beyond the same power of two.
+    M, N, K = 48, 64, 96
+    A = datagen.lognormal((43, 0), M, K)
+    B = datagen.lognormal((43, 1), K, N)
+    for vid, name, form in split_loaded:
+        if form != "fp16s":
+            continue
+        C1, _ = run_gemm(vid, A, B, None, 1.0, 0.0)
+        C2, _ = run_gemm(vid, A * np.float32(2.0 ** 20), B * np.float32(2.0 ** -30), None, 1.0, 0.0)
+        assert np.array_equal(C1 * np.float32(2.0 ** -10), C2), name

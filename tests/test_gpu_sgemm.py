@@ -23,21 +23,25 @@ PKG = os.path.dirname(abi.LIB_PATH)
 VARIANT_DIR = os.path.join(PKG, "variants")
 
 
-def _manifest():
+def _manifest(prec=0):
+    """(id, name) of the manifest's variants of one precision form."""
     out = []
     for line in open(os.path.join(VARIANT_DIR, "manifest.txt")):
         if not line.startswith("#"):
-            out.append((int(line.split()[0]), line.split()[1]))
+            f = line.split()
+            if int(f[14]) == prec:
+                out.append((int(f[0]), f[1]))
     return out
 
 
 @pytest.fixture(scope="module")
 def loaded():
+    """The FP32 variants (the split-precision forms have their own tests)."""
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
     n = abi.variant_manifest_load(VARIANT_DIR)
-    assert n == len(_manifest())
-    return _manifest()
+    assert n == sum(len(_manifest(p)) for p in range(4))
+    return _manifest(0)
 
 
 def _check(C, A, B, C0, alpha, beta, label=""):
