@@ -254,6 +254,46 @@ int ptune_select(int nv, int ns, const double *t, int nsel, const int *shapes,
                  int k, int method, int *kappa_out, double *cost_out, int64_t *evals_out);
 
 /*
+ * Fleet objective (Sec. IV-D-2, Eq. 2) on one device: the fleet's task rate
+ * is quantity(d) / sum_i y'(i) quantity(i), so maximising it minimises the
+ * weighted total time sum_j weights[j] * min_{v in kappa} t[v][shapes[j]]
+ * of one task.  Same search as ptune_select (dominance pruning keeps it
+ * exact: a dominated variant never lowers the sum); writes the set and the
+ * total.  weights has nsel positive entries (shapes must not be NULL).
+ */
+int ptune_select_total(int nv, int ns, const double *t, int nsel, const int *shapes,
+                       const double *weights, int k, int method, int *kappa_out,
+                       double *total_out, int64_t *evals_out);
+
+/*
+ * k-means selection (Sec. IV-C-2): every selected shape is a point in
+ * nv-dimensional space, its relative performance best/t per variant (0
+ * where failed); Lloyd's algorithm from the k initial centroids
+ * init[0..k) (positions among the selected shapes; the caller draws them):
+ * assign points to the nearest centroid (lowest index on ties), move
+ * centroids to their points' mean (an empty cluster keeps its centroid),
+ * until no assignment changes or max_iter.  Each final centroid contributes
+ * its best variant (largest component, lowest id on ties; a variant already
+ * taken is replaced by the centroid's next best).  Writes the sorted set
+ * (returns its size <= k), the cluster of each point and the iterations.
+ */
+int ptune_kmeans(int nv, int ns, const double *t, int nsel, const int *shapes, int k,
+                 const int *init, int max_iter, int *kappa_out, int *assign_out, int *iters_out);
+
+/*
+ * Decision-tree selection (Sec. IV-C-3): a regression tree from the shapes'
+ * features (nfeat per selected shape, row-major) to their relative
+ * performance vectors, grown best first to k leaves (each step splits the
+ * leaf whose best axis split lowers the summed squared error most;
+ * thresholds halfway between consecutive distinct values; ties to the lower
+ * leaf, feature and threshold).  Each leaf's mean vector contributes its best
+ * variant as in ptune_kmeans.  Writes the sorted set (returns its size) and
+ * each shape's leaf.
+ */
+int ptune_tree(int nv, int ns, const double *t, int nsel, const int *shapes, int nfeat,
+               const double *features, int k, int *kappa_out, int *leaf_out);
+
+/*
  * For each of the nsel shapes, the member of kappa with the lowest time
  * (ties to the lower id; -1 if none is finite): the dispatch table that a
  * set file records for its training shapes.

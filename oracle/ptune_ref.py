@@ -201,3 +201,138 @@ def dispatch(train_shapes, members, cost, M, N, K):
         i0 = near[0]
         best_j = min(range(len(members)), key=lambda j: (cost[i0][j], j))
     return members[best_j]
+
+
+# --- Sec. IV-D-2 with one device: weighted total time --------------------------
+
+def total_time(times, kappa, shapes, weights):
+    """sum_i weight(i) * min_{v in kappa} t[v][i]: the time of one fleet task
+    on one device, the reciprocal of Eq. 2's rate up to quantity(d)."""
+    tot = 0.0
+    for s, w in zip(shapes, weights):
+        m = min(times[v][s] for v in kappa)
+        if not _finite(m):
+            return INF
+        tot += w * m
+    return tot
+
+
+def portability_tune_total(times, k, shapes, weights):
+    """argmin over k-subsets of total_time (first subset in lexicographic
+    order on ties)."""
+    nv = len(times)
+    k = min(k, nv)
+    best_set, best_cost = None, INF
+    for kappa in itertools.combinations(range(nv), k):
+        c = total_time(times, kappa, shapes, weights)
+        if c < best_cost:
+            best_set, best_cost = kappa, c
+    return (best_set if best_set is not None else tuple(range(k))), best_cost
+
+
+# --- Sec. IV-C-2: k-means on performance vectors -------------------------------
+
+def performance_vectors(times, shapes):
+    """One point per environment (shape): its |K|-dim vector of relative
+    performance best/t (0 where a variant failed).  The paper leaves the
+    normalisation open; relative performance puts every shape on the same
+    scale, as Eq. 1 does."""
+    best, _, _, _, _ = postprocess(times)
+    nv = len(times)
+    pts = []
+    for s in shapes:
+        pts.append([best[s] / times[v][s] if _finite(times[v][s]) else 0.0 for v in range(nv)])
+    return pts
+
+
+def _pick_distinct(vectors, k, nv):
+    """Best variant (largest component, lowest index on ties) of each
+    representative vector; a variant already taken is replaced by the
+    vector's next best.  Returns the sorted set."""
+    chosen = []
+    for vec in vectors:
+        order = sorted(range(nv), key=lambda v: (-vec[v], v))
+        for v in order:
+            if v not in chosen:
+                chosen.append(v)
+                break
+    return tuple(sorted(chosen[:k]))
+
+
+def kmeans_select(times, k, shapes, init, max_iter=100):
+    """Lloyd's algorithm from the given initial centroids (indices into
+    `shapes`): assign each point to its nearest centroid (squared Euclidean
+    distance, lowest centroid on ties), move each centroid to the mean of its
+    points (an empty cluster keeps its centroid), until no assignment
+    changes.  Returns (kappa, assignment, iterations)."""
+    pts = performance_vectors(times, shapes)
+    nv = len(times)
+    cents = [list(pts[i]) for i in init]
+    assign = [-1] * len(pts)
+    it = 0
+    for it in range(1, max_iter + 1):
+        new = []
+        for p in pts:
+            d = [sum((p[v] - c[v]) ** 2 for v in range(nv)) for c in cents]
+            new.append(min(range(len(cents)), key=lambda j: (d[j], j)))
+        changed = new != assign
+        assign = new
+        for j in range(len(cents)):
+            mem = [pts[i] for i in range(len(pts)) if assign[i] == j]
+            if mem:
+                cents[j] = [sum(m[v] for m in mem) / len(mem) for v in range(nv)]
+        if not changed:
+            break
+    return _pick_distinct(cents, k, nv), assign, it
+
+
+# --- Sec. IV-C-3: decision tree with |kappa| leaves ----------------------------
+
+def tree_select(times, k, shapes, features):
+    """Regression tree from environment features to performance vectors,
+    grown best first to k leaves: repeatedly split the leaf whose best split
+    lowers the summed squared error of the vectors most (thresholds halfway
+    between consecutive distinct feature values; ties to the lower leaf,
+    feature, threshold); each leaf's representative is the mean vector of
+    its environments and contributes its best variant.
+    Returns (kappa, leaf index of each environment)."""
+    pts = performance_vectors(times, shapes)
+    nv = len(times)
+
+    def sse(idx):
+        if not idx:
+            return 0.0
+        mean = [sum(pts[i][v] for i in idx) / len(idx) for v in range(nv)]
+        return sum((pts[i][v] - mean[v]) ** 2 for i in idx for v in range(nv))
+
+    def best_split(idx):
+        base = sse(idx)
+        best = None
+        for f in range(len(features[0])):
+            vals = sorted(set(features[i][f] for i in idx))
+            for a, b in zip(vals, vals[1:]):
+                thr = 0.5 * (a + b)
+                left = [i for i in idx if features[i][f] <= thr]
+                right = [i for i in idx if features[i][f] > thr]
+                gain = base - sse(left) - sse(right)
+                if best is None or gain > best[0] + 1e-12:
+                    best = (gain, f, thr, left, right)
+        return best
+
+    leaves = [list(range(len(pts)))]
+    while len(leaves) < k:
+        cands = []
+        for li, idx in enumerate(leaves):
+            bs = best_split(idx)
+            if bs is not None:
+                cands.append((bs[0], li, bs))
+        if not cands:
+            break
+        gain, li, bs = max(cands, key=lambda c: (c[0], -c[1]))
+        leaves[li:li + 1] = [bs[3], bs[4]]
+    reps = [[sum(pts[i][v] for i in idx) / len(idx) for v in range(nv)] for idx in leaves]
+    leaf_of = [0] * len(pts)
+    for li, idx in enumerate(leaves):
+        for i in idx:
+            leaf_of[i] = li
+    return _pick_distinct(reps, k, nv), leaf_of

@@ -29,7 +29,8 @@ EXPORTS = ("sgemm", "sgemm_form", "variant_set_load", "variant_select", "variant
            "fewfit_last_error",
            "variant_manifest_load", "variant_count", "variant_info", "sgemm_variant",
            "sgemm_time", "screen_reference", "screen_compare", "ptune_postprocess",
-           "ptune_cost", "ptune_select", "ptune_assign", "ptune_nearest", "ptune_dispatch")
+           "ptune_cost", "ptune_select", "ptune_assign", "ptune_nearest", "ptune_dispatch",
+           "ptune_select_total", "ptune_kmeans", "ptune_tree")
 
 
 class FewfitError(RuntimeError):
@@ -70,6 +71,9 @@ def lib():
         L.ptune_assign.argtypes = [i32, i32, vp, i32, vp, i32, vp, vp]
         L.ptune_nearest.argtypes = [i32, vp, i64, i64, i64]
         L.ptune_dispatch.argtypes = [i32, vp, i32, vp, vp, i64, i64, i64]
+        L.ptune_select_total.argtypes = [i32, i32, vp, i32, vp, vp, i32, i32, vp, vp, vp]
+        L.ptune_kmeans.argtypes = [i32, i32, vp, i32, vp, i32, vp, i32, vp, vp, vp]
+        L.ptune_tree.argtypes = [i32, i32, vp, i32, vp, i32, vp, i32, vp, vp]
         for name in EXPORTS:
             if name != "fewfit_last_error":
                 getattr(L, name).restype = i32
@@ -259,3 +263,46 @@ def ptune_dispatch(train_shapes, members, cost, M, N, K):
     c = np.ascontiguousarray(cost, dtype=np.float64).reshape(tr.shape[0], mem.size)
     return _check(lib().ptune_dispatch(tr.shape[0], tr.ctypes.data, mem.size, mem.ctypes.data,
                                        c.ctypes.data, M, N, K))
+
+
+def ptune_select_total(t, k, shapes, weights, method=-1):
+    import numpy as np
+    t = _table(t)
+    nv, ns = t.shape
+    s, nsel = _shapes(shapes)
+    w = np.ascontiguousarray(weights, dtype=np.float64)
+    kap = np.empty(k, np.int32)
+    tot = ctypes.c_double(0.0)
+    evals = ctypes.c_int64(0)
+    n = _check(lib().ptune_select_total(nv, ns, t.ctypes.data, nsel, s.ctypes.data, w.ctypes.data, k, method,
+                                        kap.ctypes.data, ctypes.byref(tot), ctypes.byref(evals)))
+    return tuple(int(x) for x in kap[:n]), tot.value, evals.value
+
+
+def ptune_kmeans(t, k, shapes, init, max_iter=100):
+    import numpy as np
+    t = _table(t)
+    nv, ns = t.shape
+    s, nsel = _shapes(shapes)
+    ini = np.ascontiguousarray(init, dtype=np.int32)
+    kap = np.empty(k, np.int32)
+    n_pts = ns if s is None else nsel
+    asg = np.empty(n_pts, np.int32)
+    it = ctypes.c_int(0)
+    n = _check(lib().ptune_kmeans(nv, ns, t.ctypes.data, nsel, None if s is None else s.ctypes.data, k,
+                                  ini.ctypes.data, max_iter, kap.ctypes.data, asg.ctypes.data, ctypes.byref(it)))
+    return tuple(int(x) for x in kap[:n]), [int(a) for a in asg], it.value
+
+
+def ptune_tree(t, k, shapes, features):
+    import numpy as np
+    t = _table(t)
+    nv, ns = t.shape
+    s, nsel = _shapes(shapes)
+    f = np.ascontiguousarray(features, dtype=np.float64)
+    kap = np.empty(k, np.int32)
+    n_pts = ns if s is None else nsel
+    leaf = np.empty(n_pts, np.int32)
+    n = _check(lib().ptune_tree(nv, ns, t.ctypes.data, nsel, None if s is None else s.ctypes.data, f.shape[1],
+                                f.ctypes.data, k, kap.ctypes.data, leaf.ctypes.data))
+    return tuple(int(x) for x in kap[:n]), [int(x) for x in leaf]

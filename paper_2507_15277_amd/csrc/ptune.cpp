@@ -79,6 +79,28 @@ LogTable make_log_table(int nv, int ns, const double* t, const std::vector<int>&
     return lt;
 }
 
+// Weighted-time table for the fleet objective: L[v][j] = w_j * t[v][s_j]
+// (+inf where failed); a set's cost is the plain sum of per-shape minima.
+LogTable make_time_table(int nv, int ns, const double* t, const std::vector<int>& sel, const double* w)
+{
+    LogTable lt;
+    lt.nv = nv;
+    lt.nsel = (int)sel.size();
+    lt.L.assign((size_t)nv * lt.nsel, kInf);
+    for (int j = 0; j < lt.nsel; ++j) {
+        bool any = false;
+        for (int v = 0; v < nv; ++v) {
+            const double x = t[(int64_t)v * ns + sel[j]];
+            if (finite_pos(x)) {
+                lt.L[(size_t)v * lt.nsel + j] = w[j] * x;
+                any = true;
+            }
+        }
+        if (!any) lt.ok = false;
+    }
+    return lt;
+}
+
 double set_logsum(const LogTable& lt, const int* kappa, int k)
 {
     double sum = 0.0;
@@ -282,18 +304,14 @@ FF_EXPORT int ptune_cost(int nv, int ns, const double* t, int k, const int* kapp
     return FF_OK;
 }
 
-FF_EXPORT int ptune_select(int nv, int ns, const double* t, int nsel, const int* shapes, int k, int method,
-                           int* kappa_out, double* cost_out, int64_t* evals_out)
+namespace {
+
+// Minimise the summed per-shape minimum of lt over sets of kk variants.
+std::vector<int> search(const LogTable& lt, int nv, int kk, int method, int64_t& evals)
 {
-    std::vector<int> sel;
-    if (nv <= 0 || ns <= 0 || t == nullptr || k < 1 || kappa_out == nullptr || method < -1 || method > 1 ||
-        !selection(ns, nsel, shapes, sel))
-        return FF_ERR_ARG;
-    const int kk = std::min(k, nv);
-    const LogTable lt = make_log_table(nv, ns, t, sel);
     std::vector<int> cand = undominated(lt);
-    int64_t evals = 0;
     std::vector<int> result;
+    evals = 0;
     if ((int)cand.size() <= kk) {
         // Every undominated variant fits; fill up with the lowest other ids.
         result = cand;
@@ -316,10 +334,237 @@ FF_EXPORT int ptune_select(int nv, int ns, const double* t, int nsel, const int*
         }
     }
     std::sort(result.begin(), result.end());
+    return result;
+}
+
+}  // namespace
+
+FF_EXPORT int ptune_select(int nv, int ns, const double* t, int nsel, const int* shapes, int k, int method,
+                           int* kappa_out, double* cost_out, int64_t* evals_out)
+{
+    std::vector<int> sel;
+    if (nv <= 0 || ns <= 0 || t == nullptr || k < 1 || kappa_out == nullptr || method < -1 || method > 1 ||
+        !selection(ns, nsel, shapes, sel))
+        return FF_ERR_ARG;
+    const int kk = std::min(k, nv);
+    const LogTable lt = make_log_table(nv, ns, t, sel);
+    int64_t evals = 0;
+    const std::vector<int> result = search(lt, nv, kk, method, evals);
     for (int i = 0; i < kk; ++i) kappa_out[i] = result[i];
     if (cost_out) *cost_out = lt.ok ? cost_of(lt, set_logsum(lt, result.data(), kk)) : kInf;
     if (evals_out) *evals_out = evals;
     return kk;
+}
+
+FF_EXPORT int ptune_select_total(int nv, int ns, const double* t, int nsel, const int* shapes,
+                                 const double* weights, int k, int method, int* kappa_out, double* total_out,
+                                 int64_t* evals_out)
+{
+    std::vector<int> sel;
+    if (nv <= 0 || ns <= 0 || t == nullptr || weights == nullptr || k < 1 || kappa_out == nullptr ||
+        method < -1 || method > 1 || !selection(ns, nsel, shapes, sel))
+        return FF_ERR_ARG;
+    for (size_t j = 0; j < sel.size(); ++j)
+        if (!(weights[j] > 0.0) || !std::isfinite(weights[j])) return FF_ERR_ARG;
+    const int kk = std::min(k, nv);
+    const LogTable lt = make_time_table(nv, ns, t, sel, weights);
+    int64_t evals = 0;
+    const std::vector<int> result = search(lt, nv, kk, method, evals);
+    for (int i = 0; i < kk; ++i) kappa_out[i] = result[i];
+    if (total_out) *total_out = lt.ok ? set_logsum(lt, result.data(), kk) : kInf;
+    if (evals_out) *evals_out = evals;
+    return kk;
+}
+
+namespace {
+
+// Relative performance vectors best_s / t[v][s] (0 where failed), one per
+// selected shape, best over all nv variants.
+std::vector<std::vector<double>> perf_vectors(int nv, int ns, const double* t, const std::vector<int>& sel)
+{
+    std::vector<double> best;
+    std::vector<int> bid;
+    column_best(nv, ns, t, best, bid);
+    std::vector<std::vector<double>> p(sel.size(), std::vector<double>(nv, 0.0));
+    for (size_t j = 0; j < sel.size(); ++j)
+        for (int v = 0; v < nv; ++v) {
+            const double x = t[(int64_t)v * ns + sel[j]];
+            if (finite_pos(x) && bid[sel[j]] >= 0) p[j][v] = best[sel[j]] / x;
+        }
+    return p;
+}
+
+// The best variant of each representative vector; a variant already taken
+// is replaced by that vector's next best.  Sorted, at most k.
+std::vector<int> pick_distinct(const std::vector<std::vector<double>>& reps, int k, int nv)
+{
+    std::vector<int> chosen;
+    for (const auto& vec : reps) {
+        std::vector<int> order(nv);
+        for (int v = 0; v < nv; ++v) order[v] = v;
+        std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return vec[a] > vec[b]; });
+        for (int v : order)
+            if (std::find(chosen.begin(), chosen.end(), v) == chosen.end()) {
+                chosen.push_back(v);
+                break;
+            }
+        if ((int)chosen.size() == k) break;
+    }
+    std::sort(chosen.begin(), chosen.end());
+    return chosen;
+}
+
+double sq_dist(const std::vector<double>& a, const std::vector<double>& b)
+{
+    double d = 0.0;
+    for (size_t i = 0; i < a.size(); ++i) d += (a[i] - b[i]) * (a[i] - b[i]);
+    return d;
+}
+
+}  // namespace
+
+FF_EXPORT int ptune_kmeans(int nv, int ns, const double* t, int nsel, const int* shapes, int k, const int* init,
+                           int max_iter, int* kappa_out, int* assign_out, int* iters_out)
+{
+    std::vector<int> sel;
+    if (nv <= 0 || ns <= 0 || t == nullptr || k < 1 || init == nullptr || kappa_out == nullptr || max_iter < 1 ||
+        !selection(ns, nsel, shapes, sel))
+        return FF_ERR_ARG;
+    const int np = (int)sel.size();
+    for (int j = 0; j < k; ++j)
+        if (init[j] < 0 || init[j] >= np) return FF_ERR_ARG;
+    const auto pts = perf_vectors(nv, ns, t, sel);
+    std::vector<std::vector<double>> cents;
+    for (int j = 0; j < k; ++j) cents.push_back(pts[init[j]]);
+    std::vector<int> assign(np, -1);
+    int it = 0;
+    for (it = 1; it <= max_iter; ++it) {
+        bool changed = false;
+        for (int i = 0; i < np; ++i) {
+            int bj = 0;
+            double bd = sq_dist(pts[i], cents[0]);
+            for (int j = 1; j < k; ++j) {
+                const double d = sq_dist(pts[i], cents[j]);
+                if (d < bd) {
+                    bd = d;
+                    bj = j;
+                }
+            }
+            if (bj != assign[i]) changed = true;
+            assign[i] = bj;
+        }
+        for (int j = 0; j < k; ++j) {
+            std::vector<double> mean(nv, 0.0);
+            int cnt = 0;
+            for (int i = 0; i < np; ++i)
+                if (assign[i] == j) {
+                    ++cnt;
+                    for (int v = 0; v < nv; ++v) mean[v] += pts[i][v];
+                }
+            if (cnt > 0) {
+                for (int v = 0; v < nv; ++v) mean[v] /= cnt;
+                cents[j] = mean;
+            }
+        }
+        if (!changed) break;
+    }
+    if (it > max_iter) it = max_iter;
+    const std::vector<int> kap = pick_distinct(cents, k, nv);
+    for (size_t i = 0; i < kap.size(); ++i) kappa_out[i] = kap[i];
+    if (assign_out)
+        for (int i = 0; i < np; ++i) assign_out[i] = assign[i];
+    if (iters_out) *iters_out = it;
+    return (int)kap.size();
+}
+
+namespace {
+
+double leaf_sse(const std::vector<std::vector<double>>& pts, const std::vector<int>& idx, int nv)
+{
+    if (idx.empty()) return 0.0;
+    std::vector<double> mean(nv, 0.0);
+    for (int i : idx)
+        for (int v = 0; v < nv; ++v) mean[v] += pts[i][v];
+    for (int v = 0; v < nv; ++v) mean[v] /= (double)idx.size();
+    double s = 0.0;
+    for (int i : idx)
+        for (int v = 0; v < nv; ++v) s += (pts[i][v] - mean[v]) * (pts[i][v] - mean[v]);
+    return s;
+}
+
+struct Split {
+    bool ok = false;
+    double gain = 0.0;
+    std::vector<int> left, right;
+};
+
+Split best_split(const std::vector<std::vector<double>>& pts, const std::vector<int>& idx, int nv, int nf,
+                 const double* feat)
+{
+    Split b;
+    const double base = leaf_sse(pts, idx, nv);
+    for (int f = 0; f < nf; ++f) {
+        std::vector<double> vals;
+        for (int i : idx) vals.push_back(feat[(size_t)i * nf + f]);
+        std::sort(vals.begin(), vals.end());
+        vals.erase(std::unique(vals.begin(), vals.end()), vals.end());
+        for (size_t a = 0; a + 1 < vals.size(); ++a) {
+            const double thr = 0.5 * (vals[a] + vals[a + 1]);
+            std::vector<int> l, r;
+            for (int i : idx) (feat[(size_t)i * nf + f] <= thr ? l : r).push_back(i);
+            const double gain = base - leaf_sse(pts, l, nv) - leaf_sse(pts, r, nv);
+            if (!b.ok || gain > b.gain + 1e-12) {
+                b.ok = true;
+                b.gain = gain;
+                b.left = l;
+                b.right = r;
+            }
+        }
+    }
+    return b;
+}
+
+}  // namespace
+
+FF_EXPORT int ptune_tree(int nv, int ns, const double* t, int nsel, const int* shapes, int nfeat,
+                         const double* features, int k, int* kappa_out, int* leaf_out)
+{
+    std::vector<int> sel;
+    if (nv <= 0 || ns <= 0 || t == nullptr || k < 1 || nfeat < 1 || features == nullptr || kappa_out == nullptr ||
+        !selection(ns, nsel, shapes, sel))
+        return FF_ERR_ARG;
+    const auto pts = perf_vectors(nv, ns, t, sel);
+    const int np = (int)pts.size();
+    std::vector<std::vector<int>> leaves(1);
+    for (int i = 0; i < np; ++i) leaves[0].push_back(i);
+    while ((int)leaves.size() < k) {
+        int bl = -1;
+        Split bs;
+        for (size_t li = 0; li < leaves.size(); ++li) {
+            Split s = best_split(pts, leaves[li], nv, nfeat, features);
+            if (s.ok && (bl < 0 || s.gain > bs.gain)) {
+                bl = (int)li;
+                bs = s;
+            }
+        }
+        if (bl < 0) break;
+        leaves[bl] = bs.left;
+        leaves.insert(leaves.begin() + bl + 1, bs.right);
+    }
+    std::vector<std::vector<double>> reps;
+    for (const auto& idx : leaves) {
+        std::vector<double> mean(nv, 0.0);
+        for (int i : idx)
+            for (int v = 0; v < nv; ++v) mean[v] += pts[i][v];
+        for (int v = 0; v < nv; ++v) mean[v] /= (double)idx.size();
+        reps.push_back(mean);
+    }
+    const std::vector<int> kap = pick_distinct(reps, k, nv);
+    for (size_t i = 0; i < kap.size(); ++i) kappa_out[i] = kap[i];
+    if (leaf_out)
+        for (size_t li = 0; li < leaves.size(); ++li)
+            for (int i : leaves[li]) leaf_out[i] = (int)li;
+    return (int)kap.size();
 }
 
 FF_EXPORT int ptune_assign(int nv, int ns, const double* t, int k, const int* kappa, int nsel, const int* shapes,

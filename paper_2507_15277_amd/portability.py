@@ -182,6 +182,75 @@ def precision_report(rows, variants, write_sets=False, log=print):
     return out
 
 
+def selector_comparison(t, shapes, train_idx, runs=30, log=print):
+    """PortabilityTune (exact search) against the paper's two pruning
+    implementations (Sec. IV-C-2, IV-C-3), on the training shapes, for each
+    k: fraction of per-shape best on the training shapes and realised on the
+    held-out shapes (all sets dispatched by the same rule), and selection
+    wall time.  k-means runs 30 times from seeded initial centroids (the
+    paper reports the mean and a 95% interval over 30 runs, Sec. V-E)."""
+    held_idx = [j for j in range(len(shapes)) if j not in set(train_idx)]
+    feats = [[math.log2(x) for x in shapes[j]] for j in train_idx]
+    out = {}
+    for k in KS:
+        rec = {}
+        t0 = time.perf_counter()
+        kap, cost, _ = abi.ptune_select(t, k, shapes=train_idx, method=-1)
+        dt = time.perf_counter() - t0
+        ev = evaluate(t, shapes, train_idx, kap)
+        rec["portability_tune"] = {"kappa": list(kap), "train_frac": 1.0 / cost,
+                                   "heldout_realised": ev["frac_heldout_realised"], "seconds": dt}
+        fr_tr, fr_ho, secs = [], [], []
+        for r in range(runs):
+            rng = np.random.default_rng([9, k, r])
+            init = sorted(rng.choice(len(train_idx), min(k, len(train_idx)), replace=False).tolist())
+            t0 = time.perf_counter()
+            kk, _, _ = abi.ptune_kmeans(t, len(init), train_idx, init)
+            secs.append(time.perf_counter() - t0)
+            fr_tr.append(1.0 / abi.ptune_cost(t, kk, train_idx))
+            fr_ho.append(evaluate(t, shapes, train_idx, kk)["frac_heldout_realised"])
+        ci = lambda x: 1.96 * float(np.std(x, ddof=1)) / math.sqrt(len(x))  # noqa: E731
+        rec["kmeans"] = {"train_frac_mean": float(np.mean(fr_tr)), "train_frac_ci95": ci(fr_tr),
+                         "train_frac_max": float(np.max(fr_tr)),
+                         "heldout_realised_mean": float(np.mean(fr_ho)), "heldout_realised_ci95": ci(fr_ho),
+                         "seconds_mean": float(np.mean(secs)), "runs": runs}
+        t0 = time.perf_counter()
+        kt, _ = abi.ptune_tree(t, k, train_idx, feats)
+        dt = time.perf_counter() - t0
+        rec["decision_tree"] = {"kappa": list(kt), "train_frac": 1.0 / abi.ptune_cost(t, kt, train_idx),
+                                "heldout_realised": evaluate(t, shapes, train_idx, kt)["frac_heldout_realised"],
+                                "seconds": dt}
+        out[str(k)] = rec
+        log(f"[selectors] k={k}: PortabilityTune {rec['portability_tune']['train_frac']:.4f}, "
+            f"k-means {rec['kmeans']['train_frac_mean']:.4f} +- {rec['kmeans']['train_frac_ci95']:.4f}, "
+            f"tree {rec['decision_tree']['train_frac']:.4f} (training shapes)")
+    return out
+
+
+def fleet_comparison(t, shapes, log=print):
+    """Eq. 2 with one device: a task runs every grid shape once (weight 1,
+    as the paper's fleet task runs every known input once).  Sets chosen for
+    the total time of a task against sets chosen by Eq. 1, both with a
+    perfect in-set pick, and against the per-shape best (the lower bound)."""
+    idx = list(range(len(shapes)))
+    w = np.ones(len(shapes))
+    best, _, _, _, _ = abi.ptune_postprocess(t)
+    floor = float(np.sum(best))
+    out = {"task_ms_per_shape_best": floor}
+    for k in KS:
+        kt, tot, _ = abi.ptune_select_total(t, k, idx, w, method=-1)
+        ke, _, _ = abi.ptune_select(t, k, method=-1)
+        tot_e = float(sum(min(t[v, j] for v in ke) for j in idx))
+        out[str(k)] = {"total_kappa": list(kt), "task_ms": tot, "rate_vs_best": floor / tot,
+                       "geomean_frac": 1.0 / abi.ptune_cost(t, kt),
+                       "eq1_kappa": list(ke), "eq1_task_ms": tot_e, "eq1_rate_vs_best": floor / tot_e,
+                       "eq1_geomean_frac": 1.0 / abi.ptune_cost(t, ke)}
+        log(f"[fleet] k={k}: task time {tot:.3f} ms (Eq. 2 set) vs {tot_e:.3f} ms (Eq. 1 set), "
+            f"best {floor:.3f} ms; geomean fraction {out[str(k)]['geomean_frac']:.3f} vs "
+            f"{out[str(k)]['eq1_geomean_frac']:.3f}")
+    return out
+
+
 def run(table=TABLE, write_sets=False, splits=5, log=print):
     rows = load_rows(table, current_hashes())
     if not rows:
@@ -270,6 +339,8 @@ def run(table=TABLE, write_sets=False, splits=5, log=print):
                            "slowdown_q75": float(np.percentile(col, 75)),
                            "n_ok": int(np.isfinite(ts[:, j]).sum())})
     report["square_sweep"] = sq_out
+    report["selectors"] = selector_comparison(t, shapes, train_idx, log=log)
+    report["fleet"] = fleet_comparison(t, shapes, log=log)
     report["precision"] = precision_report(rows, variants, write_sets, log)
     report["screen"] = {
         "ok": sum(1 for r in rows if r.get("status") == "ok"),

@@ -224,3 +224,48 @@ def test_select_argument_errors():
         abi.ptune_select(t, 2, shapes=[0, 9])
     with pytest.raises(abi.FewfitError):
         abi.ptune_cost(t, [5])
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_total_time_select_matches_bruteforce(seed):
+    nv, ns = 10, 6
+    t = _rand_table(300 + seed, nv, ns, fail_frac=0.1 if seed % 2 else 0.0)
+    rng = np.random.default_rng(seed)
+    w = rng.uniform(0.5, 4.0, ns)
+    shapes = list(range(ns))
+    for k in (1, 2, 3):
+        kap, tot, _ = abi.ptune_select_total(t, k, shapes, w, method=0)
+        ref_kap, ref_tot = pr.portability_tune_total(t.tolist(), k, shapes, w.tolist())
+        if ref_tot == INF:
+            assert tot == INF
+        else:
+            assert tot == pytest.approx(ref_tot, rel=1e-12)
+            assert pr.total_time(t.tolist(), kap, shapes, w.tolist()) == pytest.approx(ref_tot, rel=1e-12)
+
+
+@pytest.mark.parametrize("seed", range(8))
+def test_kmeans_matches_oracle(seed):
+    nv, ns = 12, 9
+    t = _rand_table(400 + seed, nv, ns, fail_frac=0.1 if seed % 2 else 0.0)
+    rng = np.random.default_rng([5, seed])
+    shapes = sorted(rng.choice(ns, 7, replace=False).tolist())
+    for k in (1, 2, 3, 4):
+        init = sorted(rng.choice(len(shapes), k, replace=False).tolist())
+        kap, assign, it = abi.ptune_kmeans(t, k, shapes, init)
+        rk, ra, rit = pr.kmeans_select(t.tolist(), k, shapes, init)
+        assert kap == rk and assign == ra and it == rit
+
+
+@pytest.mark.parametrize("seed", range(8))
+def test_tree_matches_oracle(seed):
+    from paper_2507_15277_amd import datagen
+    shapes27 = datagen.grid27()
+    nv = 10
+    t = _rand_table(500 + seed, nv, 27)
+    rng = np.random.default_rng([6, seed])
+    shapes = sorted(rng.choice(27, 12, replace=False).tolist())
+    feats = [[np.log2(x) for x in shapes27[s]] for s in shapes]
+    for k in (1, 2, 3, 5):
+        kap, leaf = abi.ptune_tree(t, k, shapes, feats)
+        rk, rl = pr.tree_select(t.tolist(), k, shapes, feats)
+        assert kap == rk and leaf == rl

@@ -240,3 +240,64 @@ def test_assign_winners():
     t = [[1.0, 5.0, 2.0], [2.0, 1.0, 2.0], [3.0, 3.0, 1.0]]
     assert pr.assign_winners(t, (0, 1), [0, 1, 2]) == [0, 1, 0]
     assert pr.assign_winners(t, (1, 2), [0, 2]) == [1, 2]
+
+
+# --- Eq. 2 on one device, k-means and decision-tree selectors -------------------
+
+def test_total_time_is_the_reciprocal_fleet_rate():
+    # One device: Eq. 2's rate is quantity(d) / sum_i y' quantity(i) with
+    # y' the set's best time, so the subset maximising the rate minimises
+    # the weighted total time.
+    t = _rand_table(11, 7, 5)
+    w = [3.0, 1.0, 2.0, 5.0, 1.0]
+    rates = {}
+    for kap in itertools.combinations(range(7), 2):
+        y = [[min(t[v][s] for v in kap) for s in range(5)]]
+        rates[kap] = pr.fleet_rate(y, [4], w)
+        assert rates[kap] == pytest.approx(4.0 / pr.total_time(t, kap, range(5), w))
+    best_rate = max(rates, key=lambda k: (rates[k], [-x for x in k]))
+    kap, tot = pr.portability_tune_total(t, 2, range(5), w)
+    assert kap == best_rate
+
+
+def test_total_time_hand_example():
+    # Shape 0 costs 100x more than shape 1: the total-time objective keeps
+    # the variant that is fastest on shape 0 even though it is 4x slower on
+    # shape 1, where Eq. 1 (geomean) prefers the balanced variant.
+    t = [[100.0, 4.0], [110.0, 1.0]]
+    assert pr.portability_tune_total(t, 1, [0, 1], [1.0, 1.0]) == ((0,), 104.0)
+    assert pr.portability_tune(t, 1)[0] == (1,)
+
+
+def test_kmeans_closed_forms():
+    t = _rand_table(12, 6, 5)
+    pts = pr.performance_vectors(t, range(5))
+    # k = 1: the single centroid is the mean vector; its best variant.
+    mean = np.mean(np.array(pts), axis=0)
+    kap, assign, _ = pr.kmeans_select(t, 1, list(range(5)), [0])
+    assert kap == (int(np.argmax(mean)),) and assign == [0] * 5
+    # k = #shapes, seeded on every shape: each shape its own cluster, so the
+    # set holds every per-shape winner (made distinct).
+    kap, assign, it = pr.kmeans_select(t, 5, list(range(5)), [0, 1, 2, 3, 4])
+    assert assign == [0, 1, 2, 3, 4] and it == 2
+    _, _, best_id, _, _ = pr.postprocess(t)
+    assert set(best_id) <= set(kap)
+
+
+def test_kmeans_two_groups():
+    # Shapes 0-2 want variant 0, shapes 3-5 variant 1; started from one shape
+    # of each group, Lloyd's algorithm separates them.
+    t = [[1.0, 1.0, 1.0, 3.0, 3.0, 3.0], [3.0, 3.0, 3.0, 1.0, 1.0, 1.0], [2.0] * 6]
+    kap, assign, _ = pr.kmeans_select(t, 2, list(range(6)), [0, 3])
+    assert kap == (0, 1) and assign == [0, 0, 0, 1, 1, 1]
+
+
+def test_tree_closed_forms():
+    t = [[1.0, 1.0, 1.0, 3.0, 3.0, 3.0], [3.0, 3.0, 3.0, 1.0, 1.0, 1.0], [2.0] * 6]
+    feats = [[8.0], [9.0], [10.0], [11.0], [12.0], [13.0]]
+    # One split at 10.5 separates the two groups exactly.
+    kap, leaf = pr.tree_select(t, 2, list(range(6)), feats)
+    assert kap == (0, 1) and leaf == [0, 0, 0, 1, 1, 1]
+    # k = 1: the root's mean vector (0.667, 0.667, 0.5): ties -> variant 0.
+    kap, leaf = pr.tree_select(t, 1, list(range(6)), feats)
+    assert kap == (0,) and leaf == [0] * 6
