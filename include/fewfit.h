@@ -213,6 +213,42 @@ int screen_compare(int64_t M, int64_t N, const float *C, int64_t ldc,
                    void *stream);
 
 /* ---------------------------------------------------------------------
+ * Batches of independent GEMMs in one grouped persistent launch
+ * ------------------------------------------------------------------- */
+
+/* One problem of a batch: C = alpha*A*B + beta*C with the batch's alpha,
+ * beta; device pointers; `tiles` is filled in by sgemm_grouped_plan(). */
+typedef struct ff_gemm_desc {
+    const float *A;
+    const float *B;
+    float *C;
+    int64_t lda, ldb, ldc;
+    int32_t M, N, K, tiles;
+} ff_gemm_desc;
+
+/*
+ * Host-side plan of a grouped launch of FP32 variant `id` over `count`
+ * problems (descs in host memory): checks every problem (sizes >= 1,
+ * lda >= K, ldb >= N, ldc >= N, non-null matrices), writes each problem's
+ * tile count and prefix[g] = tiles before problem g, and *vec_ok = 1 if
+ * every problem allows the variant's vector loads.  Returns the total tile
+ * count, FF_ERR_ARG, FF_ERR_VARIANT or FF_ERR_TOO_LARGE.  No HIP call.
+ */
+int sgemm_grouped_plan(int id, int count, ff_gemm_desc *descs, int32_t *prefix, int *vec_ok);
+
+/*
+ * One persistent launch of variant `id` over a planned batch: descs and
+ * prefix are the plan's arrays copied to device memory; the grid holds as
+ * many work-groups as fit on the device at once and each walks the batch's
+ * tile list with a fixed stride.  vec != 0 selects the vector-load kernel
+ * (only if the plan allowed it).  Allocates nothing and does not
+ * synchronise, so it can be captured in a HIP graph.  Returns 0,
+ * FF_ERR_ARG, FF_ERR_VARIANT or FF_ERR_HIP.
+ */
+int sgemm_grouped(int id, int count, const ff_gemm_desc *descs, const int32_t *prefix,
+                  int total, float alpha, float beta, int vec, void *stream);
+
+/* ---------------------------------------------------------------------
  * Portability tuning on an execution-time table (host only, Sec. IV, V-C)
  *
  * A table is a dense row-major nv x ns array of doubles: t[v*ns + s] is the

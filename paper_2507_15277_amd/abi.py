@@ -30,7 +30,7 @@ EXPORTS = ("sgemm", "sgemm_form", "variant_set_load", "variant_select", "variant
            "variant_manifest_load", "variant_count", "variant_info", "sgemm_variant",
            "sgemm_time", "screen_reference", "screen_compare", "ptune_postprocess",
            "ptune_cost", "ptune_select", "ptune_assign", "ptune_nearest", "ptune_dispatch",
-           "ptune_select_total", "ptune_kmeans", "ptune_tree")
+           "ptune_select_total", "ptune_kmeans", "ptune_tree", "sgemm_grouped_plan", "sgemm_grouped")
 
 
 class FewfitError(RuntimeError):
@@ -71,6 +71,8 @@ def lib():
         L.ptune_assign.argtypes = [i32, i32, vp, i32, vp, i32, vp, vp]
         L.ptune_nearest.argtypes = [i32, vp, i64, i64, i64]
         L.ptune_dispatch.argtypes = [i32, vp, i32, vp, vp, i64, i64, i64]
+        L.sgemm_grouped_plan.argtypes = [i32, i32, vp, vp, vp]
+        L.sgemm_grouped.argtypes = [i32, i32, vp, vp, i32, f32, f32, i32, vp]
         L.ptune_select_total.argtypes = [i32, i32, vp, i32, vp, vp, i32, i32, vp, vp, vp]
         L.ptune_kmeans.argtypes = [i32, i32, vp, i32, vp, i32, vp, i32, vp, vp, vp]
         L.ptune_tree.argtypes = [i32, i32, vp, i32, vp, i32, vp, i32, vp, vp]
@@ -179,6 +181,32 @@ def screen_compare(M, N, C, ldc, ref, tol, stream=None, tol_scale=1.0, norms=Fal
         rel = (e2.value / r2.value) ** 0.5 if r2.value > 0 else 0.0
         return nbad.value, ratio.value, rel
     return nbad.value, ratio.value
+
+
+# --- grouped launches ------------------------------------------------------------
+
+def gemm_desc_dtype():
+    """numpy layout of ff_gemm_desc (64 bytes)."""
+    import numpy as np
+    return np.dtype([("A", np.uint64), ("B", np.uint64), ("C", np.uint64), ("lda", np.int64),
+                     ("ldb", np.int64), ("ldc", np.int64), ("M", np.int32), ("N", np.int32),
+                     ("K", np.int32), ("tiles", np.int32)])
+
+
+def sgemm_grouped_plan(vid, descs):
+    """descs: numpy array of gemm_desc_dtype (modified in place: tiles).
+    Returns (total tiles, prefix int32 array, vector loads allowed)."""
+    import numpy as np
+    prefix = np.empty(len(descs), np.int32)
+    vec = ctypes.c_int(0)
+    total = _check(lib().sgemm_grouped_plan(vid, len(descs), descs.ctypes.data, prefix.ctypes.data,
+                                            ctypes.byref(vec)))
+    return total, prefix, bool(vec.value)
+
+
+def sgemm_grouped(vid, count, descs_dev, prefix_dev, total, alpha, beta, vec, stream=None):
+    return _check(lib().sgemm_grouped(vid, count, _ptr(descs_dev), _ptr(prefix_dev), total, alpha, beta,
+                                      1 if vec else 0, _stream(stream)))
 
 
 # --- portability tuning (host) -------------------------------------------------

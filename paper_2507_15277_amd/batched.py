@@ -1,0 +1,209 @@
+"""Batches of uneven GEMMs: grouped persistent launches, one per size bucket,
+captured in a HIP graph.
+
+The batch: ``count`` independent problems with M, N, K each log-uniform on
+[16, 1024] and rounded to the nearest multiple of 16.  Problems are split
+into size buckets by quantiles of log(M N K); for each bucket the autotuner
+times the grouped launch of every FP32 variant and keeps the fastest (the
+per-bucket variant).  One batch then costs one grouped launch per bucket,
+and the launches are captured once in a HIP graph and replayed.  The
+baseline issues one launch per problem with its bucket's variant.
+
+This is the batched use of the selection machinery: the buckets play the
+role of the paper's environments and the total time of the batch is the
+single-device form of the fleet objective (Eq. 2).
+
+    python -m paper_2507_15277_amd.batched [--count 2000] [--buckets 4] [--out report.json]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import time
+
+import numpy as np
+
+from . import abi, tuned
+from .tune import read_manifest
+
+ALIGN = 4          # floats; every operand starts 16-byte aligned
+
+
+def batch_shapes(count=2000, seed=0, lo=16, hi=1024, step=16):
+    """[(M, N, K)]: each log-uniform on [lo, hi], rounded to the nearest
+    multiple of `step` and clamped to [lo, hi]."""
+    rng = np.random.default_rng([4, seed])
+    x = np.exp(rng.uniform(math.log(lo), math.log(hi), (count, 3)))
+    x = np.clip(np.rint(x / step) * step, lo, hi).astype(np.int64)
+    return [tuple(int(v) for v in r) for r in x]
+
+
+def buckets_of(shapes, nb):
+    """Bucket index per problem: quantiles of log(M N K), nb buckets."""
+    w = np.log(np.array([m * n * k for m, n, k in shapes], dtype=np.float64))
+    edges = np.quantile(w, np.linspace(0, 1, nb + 1)[1:-1]) if nb > 1 else []
+    return np.searchsorted(edges, w, side="right").astype(int)
+
+
+class Batch:
+    """Device operands of a batch, packed in three pooled buffers."""
+
+    def __init__(self, shapes, host_ops=None, seed=0):
+        import torch
+
+        self.shapes = list(shapes)
+        offs = {"A": [0], "B": [0], "C": [0]}
+        for (M, N, K) in self.shapes:
+            for key, n in (("A", M * K), ("B", K * N), ("C", M * N)):
+                offs[key].append(offs[key][-1] + (n + ALIGN - 1) // ALIGN * ALIGN)
+        self.off = {k: v[:-1] for k, v in offs.items()}
+        if host_ops is None:
+            g = torch.Generator(device="cuda")
+            g.manual_seed(seed)
+            self.A = torch.rand(offs["A"][-1], device="cuda", generator=g) * 2 - 1
+            self.B = torch.rand(offs["B"][-1], device="cuda", generator=g) * 2 - 1
+        else:
+            a = np.zeros(offs["A"][-1], np.float32)
+            b = np.zeros(offs["B"][-1], np.float32)
+            for i, (A, B) in enumerate(host_ops):
+                a[self.off["A"][i]:self.off["A"][i] + A.size] = A.ravel()
+                b[self.off["B"][i]:self.off["B"][i] + B.size] = B.ravel()
+            self.A = torch.from_numpy(a).cuda()
+            self.B = torch.from_numpy(b).cuda()
+        self.C = torch.zeros(offs["C"][-1], device="cuda")
+        self.flops = sum(2.0 * M * N * K for M, N, K in self.shapes)
+
+    def descs(self, idx):
+        d = np.zeros(len(idx), dtype=abi.gemm_desc_dtype())
+        a0, b0, c0 = self.A.data_ptr(), self.B.data_ptr(), self.C.data_ptr()
+        for r, i in enumerate(idx):
+            M, N, K = self.shapes[i]
+            d[r] = (a0 + 4 * self.off["A"][i], b0 + 4 * self.off["B"][i], c0 + 4 * self.off["C"][i],
+                    K, N, N, M, N, K, 0)
+        return d
+
+    def result(self, i):
+        M, N, _ = self.shapes[i]
+        o = self.off["C"][i]
+        return self.C[o:o + M * N].view(M, N)
+
+
+class GroupedPlan:
+    """Device descriptors and prefix of one bucket for one variant."""
+
+    def __init__(self, batch, idx, vid):
+        import torch
+
+        d = batch.descs(idx)
+        self.total, prefix, self.vec = abi.sgemm_grouped_plan(vid, d)
+        self.vid, self.count = vid, len(idx)
+        self.d_descs = torch.from_numpy(d.view(np.uint8)).cuda()
+        self.d_prefix = torch.from_numpy(prefix).cuda()
+
+    def launch(self, alpha=1.0, beta=0.0, stream=None):
+        abi.sgemm_grouped(self.vid, self.count, self.d_descs, self.d_prefix, self.total, alpha, beta,
+                          self.vec, stream)
+
+
+def time_it(fn, reps=5, warmup=2):
+    import torch
+
+    for _ in range(warmup):
+        fn()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(reps):
+        fn()
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def tune_buckets(batch, bucket_of, nb, candidates, log=print):
+    """Fastest grouped variant per bucket: {bucket: (vid, ms)}."""
+    best = {}
+    for b in range(nb):
+        idx = [i for i in range(len(batch.shapes)) if bucket_of[i] == b]
+        if not idx:
+            continue
+        res = []
+        for vid in candidates:
+            plan = GroupedPlan(batch, idx, vid)
+            res.append((time_it(plan.launch, reps=3, warmup=1), vid))
+        res.sort()
+        best[b] = (res[0][1], res[0][0])
+        log(f"[batched] bucket {b}: {len(idx)} problems, best variant {res[0][1]} "
+            f"({res[0][0] * 1e3:.1f} us), median candidate {res[len(res) // 2][0] * 1e3:.1f} us")
+    return best
+
+
+def run(count=2000, nb=4, seed=0, log=print):
+    import torch
+
+    abi.variant_manifest_load(tuned.VARIANT_DIR)
+    fp32 = [vid for vid, _, prec in read_manifest(with_prec=True) if prec == 0]
+    shapes = batch_shapes(count, seed)
+    batch = Batch(shapes, seed=seed)
+    bucket_of = buckets_of(shapes, nb)
+    t0 = time.perf_counter()
+    best = tune_buckets(batch, bucket_of, nb, fp32, log)
+    tune_s = time.perf_counter() - t0
+    plans = [GroupedPlan(batch, [i for i in range(count) if bucket_of[i] == b], best[b][0]) for b in sorted(best)]
+    stream = torch.cuda.current_stream()
+
+    def grouped():
+        for p in plans:
+            p.launch(stream=stream)
+
+    def per_problem():
+        for i, (M, N, K) in enumerate(shapes):
+            o = batch.off
+            abi.sgemm_variant(best[bucket_of[i]][0], M, N, K, 1.0, batch.A.data_ptr() + 4 * o["A"][i], K,
+                              batch.B.data_ptr() + 4 * o["B"][i], N, 0.0, batch.C.data_ptr() + 4 * o["C"][i], N,
+                              stream)
+
+    ms_single = time_it(per_problem, reps=3, warmup=1)
+    ms_grouped = time_it(grouped, reps=10, warmup=2)
+    graph = torch.cuda.CUDAGraph()
+    side = torch.cuda.Stream()
+    side.wait_stream(stream)
+    with torch.cuda.stream(side):
+        grouped()                        # warm the side stream before capture
+    stream.wait_stream(side)
+    torch.cuda.synchronize()
+    with torch.cuda.graph(graph):
+        for p in plans:
+            p.launch(stream=torch.cuda.current_stream())
+    ms_graph = time_it(graph.replay, reps=20, warmup=2)
+    tf = lambda ms: batch.flops / ms / 1e9  # noqa: E731
+    rep = {"count": count, "buckets": nb, "seed": seed, "gflop": batch.flops / 1e9,
+           "algorithmic_gbytes": sum(4.0 * (M * K + K * N + M * N) for M, N, K in shapes) / 1e9,
+           "bucket_variants": {str(b): {"variant": v, "name": abi.variant_info(v).split()[1], "ms": ms,
+                                        "problems": int(np.sum(bucket_of == b))}
+                               for b, (v, ms) in best.items()},
+           "ms_per_problem_launches": ms_single, "ms_grouped": ms_grouped, "ms_grouped_graph": ms_graph,
+           "tflops_per_problem_launches": tf(ms_single), "tflops_grouped": tf(ms_grouped),
+           "tflops_grouped_graph": tf(ms_graph), "bucket_tuning_seconds": tune_s}
+    log(f"[batched] {count} GEMMs, {rep['gflop']:.1f} GFLOP: per-problem launches {ms_single:.3f} ms "
+        f"({tf(ms_single):.1f} TFLOP/s), grouped {ms_grouped:.3f} ms ({tf(ms_grouped):.1f}), "
+        f"grouped in a graph {ms_graph:.3f} ms ({tf(ms_graph):.1f})")
+    return rep
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
+    ap.add_argument("--count", type=int, default=2000)
+    ap.add_argument("--buckets", type=int, default=4)
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--out", default=None)
+    args = ap.parse_args(argv)
+    rep = run(args.count, args.buckets, args.seed, log=lambda s: print(s, flush=True))
+    if args.out:
+        with open(args.out, "w") as f:
+            json.dump(rep, f, indent=1)
+
+
+if __name__ == "__main__":
+    main()

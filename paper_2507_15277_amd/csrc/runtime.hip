@@ -59,6 +59,9 @@ struct Variant {
     hipModule_t mod = nullptr;
     hipFunction_t fvec = nullptr;  // VW-wide loads
     hipFunction_t fsca = nullptr;  // scalar loads
+    hipFunction_t fgrp = nullptr;  // grouped persistent, VW-wide loads (FP32 variants)
+    hipFunction_t fgrp1 = nullptr; // grouped persistent, scalar loads
+    int grp_blocks = 0;            // grouped grid: resident work-groups per device
     int threads() const { return 64 * wm * wn * sk; }
 };
 
@@ -140,6 +143,21 @@ int load_code_object(Variant& v, const std::string& path)
     v.mod = mod;
     v.fvec = fv;
     v.fsca = fs;
+    // Grouped forms are optional (the split-precision family has none).
+    hipFunction_t g = nullptr, g1 = nullptr;
+    if (hipModuleGetFunction(&g, mod, (v.name + "_g").c_str()) == hipSuccess &&
+        hipModuleGetFunction(&g1, mod, (v.name + "_g1").c_str()) == hipSuccess) {
+        int per_cu = 0, dev = 0, cus = 0;
+        if (hipModuleOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, g1, v.threads(), 0) == hipSuccess &&
+            hipGetDevice(&dev) == hipSuccess &&
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess &&
+            per_cu > 0 && cus > 0) {
+            v.fgrp = g;
+            v.fgrp1 = g1;
+            v.grp_blocks = per_cu * cus;
+        }
+    }
+    (void)hipGetLastError();
     return FF_OK;
 }
 
@@ -827,4 +845,54 @@ FF_EXPORT int screen_compare(int64_t M, int64_t N, const float* C, int64_t ldc, 
     if (err2) *err2 = e2;
     if (ref2) *ref2 = r2;
     return FF_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Grouped persistent launches (many independent problems in one launch)
+
+static_assert(sizeof(ff_gemm_desc) == 64, "descriptor layout shared with the kernels");
+
+FF_EXPORT int sgemm_grouped_plan(int id, int count, ff_gemm_desc* descs, int32_t* prefix, int* vec_ok)
+{
+    if (count < 1 || descs == nullptr || prefix == nullptr)
+        return fail(FF_ERR_ARG, "sgemm_grouped_plan: need count >= 1, descs and prefix");
+    auto v = find_variant(id);
+    if (!v) return fail(FF_ERR_VARIANT, "variant %d not registered", id);
+    if (v->prec != 0) return fail(FF_ERR_ARG, "variant %d has no grouped form", id);
+    const int w = v->vw;
+    bool vec = w > 1;
+    int64_t total = 0;
+    for (int g = 0; g < count; ++g) {
+        ff_gemm_desc& d = descs[g];
+        if (d.M < 1 || d.N < 1 || d.K < 1 || d.A == nullptr || d.B == nullptr || d.C == nullptr || d.lda < d.K ||
+            d.ldb < d.N || d.ldc < d.N)
+            return fail(FF_ERR_ARG, "sgemm_grouped_plan: problem %d invalid (sizes >= 1, lda >= K, ldb >= N, "
+                        "ldc >= N, non-null matrices)", g);
+        const int64_t tiles = (int64_t)((d.M + v->mwg - 1) / v->mwg) * ((d.N + v->nwg - 1) / v->nwg);
+        if (total + tiles > INT32_MAX) return fail(FF_ERR_TOO_LARGE, "sgemm_grouped_plan: too many tiles");
+        d.tiles = (int32_t)tiles;
+        prefix[g] = (int32_t)total;
+        total += tiles;
+        vec = vec && d.K % w == 0 && d.N % w == 0 && d.lda % w == 0 && d.ldb % w == 0 && aligned_for(d.A, w) &&
+              aligned_for(d.B, w);
+    }
+    if (vec_ok) *vec_ok = vec ? 1 : 0;
+    return (int)total;
+}
+
+FF_EXPORT int sgemm_grouped(int id, int count, const ff_gemm_desc* descs, const int32_t* prefix, int total,
+                            float alpha, float beta, int vec, void* stream)
+{
+    if (count < 1 || descs == nullptr || prefix == nullptr || total < 0)
+        return fail(FF_ERR_ARG, "sgemm_grouped: need count >= 1, device descs and prefix, total >= 0");
+    auto v = find_variant(id);
+    if (!v) return fail(FF_ERR_VARIANT, "variant %d not registered", id);
+    if (v->fgrp == nullptr) return fail(FF_ERR_ARG, "variant %d has no grouped form", id);
+    if (total == 0) return FF_OK;
+    const int blocks = std::min(total, v->grp_blocks);
+    hipFunction_t f = vec ? v->fgrp : v->fgrp1;
+    void* args[] = {(void*)&descs, (void*)&prefix, &count, &total, &alpha, &beta};
+    hipError_t e = hipModuleLaunchKernel(f, (unsigned)blocks, 1, 1, (unsigned)v->threads(), 1, 1, 0,
+                                         static_cast<hipStream_t>(stream), args, nullptr);
+    return e == hipSuccess ? FF_OK : hip_fail(e, ("launch grouped " + v->name).c_str());
 }

@@ -31,7 +31,9 @@
 //                    in a fixed order (deterministic) and applies alpha, beta
 //   FF_NAME          kernel symbol; a second kernel FF_NAME##_v1 is the same
 //                    configuration with scalar loads, for operands whose
-//                    alignment or leading dimension rules out vector loads
+//                    alignment or leading dimension rules out vector loads;
+//                    FF_NAME##_g and FF_NAME##_g1 are the grouped persistent
+//                    forms (many independent problems in one launch)
 //
 // Operand roles inside the MFMA.  The MFMA computes D[i][j] += sum_k X[i][k]
 // Y[k][j] with X held one value per lane as X[lane%MI][lane/MI] and Y as
@@ -180,16 +182,18 @@ __device__ __forceinline__ void tile_of(int bid, int nbm, int nbn, int splits, i
     tn = w / gsz;
 }
 
+// One work-group computes tile (tm, tn) of C over slabs [kt0, kt1) of K
+// (split `part` of `splits` when the K range is split over work-groups).
+// Every wave reaches every barrier and no wave returns early, so the
+// grouped kernel can call this once per tile in a loop.
 template <int V>
-__device__ __forceinline__ void gemm_body(int M, int N, int K, float alpha,
+__device__ __forceinline__ void tile_gemm(int M, int N, int K, float alpha,
                                           const float* __restrict__ A, long lda,
                                           const float* __restrict__ B, long ldb,
                                           float beta, float* __restrict__ C, long ldc,
-                                          float* __restrict__ ws, int splits, int kper, float* smem)
+                                          float* __restrict__ ws, int splits, int part,
+                                          int kt0, int kt1, int tm, int tn, float* smem)
 {
-    const int nbm = (M + MWG - 1) / MWG, nbn = (N + NWG - 1) / NWG;
-    int tm, tn, part;
-    tile_of(blockIdx.x, nbm, nbn, SG > 1 ? splits : 1, tm, tn, part);
     const int m0 = tm * MWG, n0 = tn * NWG;
 
     const int tid = threadIdx.x;
@@ -209,10 +213,6 @@ __device__ __forceinline__ void gemm_body(int M, int N, int K, float alpha,
         for (int j = 0; j < RN; ++j)
             acc[i][j] = acc_t{};
 
-    const int nkt = (K + KWG - 1) / KWG;
-    // This work-group's slabs [kt0, kt1): all of K unless the tile is split.
-    const int kt0 = (SG > 1) ? part * kper : 0;
-    const int kt1 = (SG > 1) ? min(nkt, kt0 + kper) : nkt;
 
     if constexpr (USE_LDS) {
         // ---- cooperative slab loads: global -> registers -> LDS ----------
@@ -397,7 +397,7 @@ __device__ __forceinline__ void gemm_body(int M, int N, int K, float alpha,
         }
     }
 
-    if (grp > 0) return;
+    if (grp > 0) return;   // waves of split groups > 0 hold no result
 
     // ---- epilogue: C = alpha*acc + beta*C ----------------------------------
     // With the K range split over work-groups the raw partial goes to this
@@ -448,6 +448,57 @@ __device__ __forceinline__ void gemm_body(int M, int N, int K, float alpha,
     }
 }
 
+template <int V>
+__device__ __forceinline__ void gemm_body(int M, int N, int K, float alpha,
+                                          const float* __restrict__ A, long lda,
+                                          const float* __restrict__ B, long ldb,
+                                          float beta, float* __restrict__ C, long ldc,
+                                          float* __restrict__ ws, int splits, int kper, float* smem)
+{
+    const int nbm = (M + MWG - 1) / MWG, nbn = (N + NWG - 1) / NWG;
+    int tm, tn, part;
+    tile_of(blockIdx.x, nbm, nbn, SG > 1 ? splits : 1, tm, tn, part);
+    const int nkt = (K + KWG - 1) / KWG;
+    // This work-group's slabs [kt0, kt1): all of K unless the tile is split.
+    const int kt0 = (SG > 1) ? part * kper : 0;
+    const int kt1 = (SG > 1) ? min(nkt, kt0 + kper) : nkt;
+    tile_gemm<V>(M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, ws, splits, part, kt0, kt1, tm, tn, smem);
+}
+
+// One problem of a grouped launch (layout shared with the runtime).
+struct GemmDesc {
+    const float* A;
+    const float* B;
+    float* C;
+    long lda, ldb, ldc;
+    int M, N, K, tiles;
+};
+
+// Grouped persistent launch: the tiles of `count` independent problems form
+// one work list (prefix[g] = tiles before problem g, total = all tiles);
+// work-group w takes tiles w, w + gridDim.x, ...  Each problem's tiles are
+// walked row by row.  K is never split here.
+template <int V>
+__device__ __forceinline__ void grouped_body(const GemmDesc* __restrict__ d, const int* __restrict__ prefix,
+                                             int count, int total, float alpha, float beta, float* smem)
+{
+    for (int t = blockIdx.x; t < total; t += gridDim.x) {
+        int lo = 0, hi = count - 1;   // last problem whose first tile is <= t
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (prefix[mid] <= t) lo = mid;
+            else hi = mid - 1;
+        }
+        const GemmDesc p = d[lo];
+        const int local = t - prefix[lo];
+        const int nbn = (p.N + NWG - 1) / NWG;
+        const int tm = local / nbn, tn = local - tm * nbn;
+        __syncthreads();   // the previous tile is done with LDS
+        tile_gemm<V>(p.M, p.N, p.K, alpha, p.A, p.lda, p.B, p.ldb, beta, p.C, p.ldc, nullptr, 1, 0, 0,
+                     (p.K + KWG - 1) / KWG, tm, tn, smem);
+    }
+}
+
 }  // namespace
 
 extern "C" __global__ void __launch_bounds__(NT)
@@ -466,4 +517,20 @@ FF_CAT(FF_NAME, _v1)(int M, int N, int K, float alpha, const float* __restrict__
 {
     __shared__ __attribute__((aligned(16))) float smem[LDS_FLOATS];
     gemm_body<1>(M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, ws, splits, kper, smem);
+}
+
+extern "C" __global__ void __launch_bounds__(NT)
+FF_CAT(FF_NAME, _g)(const GemmDesc* __restrict__ d, const int* __restrict__ prefix, int count, int total,
+                    float alpha, float beta)
+{
+    __shared__ __attribute__((aligned(16))) float smem[LDS_FLOATS];
+    grouped_body<VW>(d, prefix, count, total, alpha, beta, smem);
+}
+
+extern "C" __global__ void __launch_bounds__(NT)
+FF_CAT(FF_NAME, _g1)(const GemmDesc* __restrict__ d, const int* __restrict__ prefix, int count, int total,
+                     float alpha, float beta)
+{
+    __shared__ __attribute__((aligned(16))) float smem[LDS_FLOATS];
+    grouped_body<1>(d, prefix, count, total, alpha, beta, smem);
 }

@@ -86,7 +86,7 @@ def read_manifest(directory=VARIANT_DIR, with_prec=False):
         for line in f:
             if line.strip() and not line.startswith("#"):
                 p = line.split()
-                out.append((int(p[0]), p[1], int(p[14])) if with_prec else (int(p[0]), p[1]))
+                out.append((int(p[0]), p[1], int(p[13])) if with_prec else (int(p[0]), p[1]))
     return out
 
 

@@ -269,3 +269,13 @@ def test_tree_matches_oracle(seed):
         kap, leaf = abi.ptune_tree(t, k, shapes, feats)
         rk, rl = pr.tree_select(t.tolist(), k, shapes, feats)
         assert kap == rk and leaf == rl
+
+
+def test_manifest_matches_family():
+    # The manifest lists the compiled family in order: FP32 variants first,
+    # then the split-precision forms, each with its precision field.
+    from paper_2507_15277_amd.tune import read_manifest
+    fam = space.full_family()
+    man = read_manifest(with_prec=True)
+    assert [(i, v.name, v.prec) for i, v in enumerate(fam)] == man
+    assert man[0][1] == space.DEFAULT.name

@@ -1,0 +1,133 @@
+"""Grouped persistent launches: parity of every problem of a batch with the
+FP64 oracle, for the vector and the scalar kernels, and replays of a
+captured HIP graph checked against the eager result."""
+import os
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+import oracle
+from paper_2507_15277_amd import abi, batched, datagen, tuned
+from paper_2507_15277_amd.tune import read_manifest
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def loaded():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    abi.variant_manifest_load(tuned.VARIANT_DIR)
+    return [vid for vid, _, prec in read_manifest(with_prec=True) if prec == 0]
+
+
+def _small_batch(seed, count=40):
+    shapes = batched.batch_shapes(count, seed, lo=16, hi=320)
+    ops = [(datagen.uniform((60, seed, i, 0), M, K), datagen.uniform((60, seed, i, 1), K, N))
+           for i, (M, N, K) in enumerate(shapes)]
+    return shapes, ops
+
+
+def _check_batch(batch, ops, label):
+    fails = []
+    for i, (A, B) in enumerate(ops):
+        C = batch.result(i).cpu().numpy().astype(np.float64)
+        _, S, T = oracle.ref_gemm(A, B)
+        K = A.shape[1]
+        if not np.all(np.abs(C - S) <= 4 * K * 2.0 ** -24 * T):
+            fails.append(f"{label}: problem {i} {A.shape[0]}x{B.shape[1]}x{K}")
+    return fails
+
+
+def test_batch_shapes_recipe():
+    s = batched.batch_shapes(2000, 0)
+    a = np.array(s)
+    assert a.shape == (2000, 3) and a.min() >= 16 and a.max() <= 1024 and np.all(a % 16 == 0)
+    # log-uniform: the median size is near sqrt(16 * 1024) = 128
+    assert 96 <= np.median(a) <= 176
+
+
+def test_grouped_matches_oracle(loaded):
+    shapes, ops = _small_batch(1)
+    picks = loaded[:: max(1, len(loaded) // 24)]
+    fails = []
+    for vid in picks:
+        batch = batched.Batch(shapes, host_ops=ops)
+        plan = batched.GroupedPlan(batch, list(range(len(shapes))), vid)
+        plan.launch()
+        torch.cuda.synchronize()
+        fails += _check_batch(batch, ops, abi.variant_info(vid).split()[1] + (" vec" if plan.vec else ""))
+    assert not fails, fails[:10]
+
+
+def test_grouped_scalar_kernel_and_padding(loaded):
+    # Leading dimensions that are not multiples of 4: the plan falls back to
+    # the scalar-load kernel; padding columns hold NaN and must not leak in.
+    shapes = [(37, 29, 53), (16, 16, 16), (70, 45, 33), (5, 3, 2)]
+    ops, descs = [], []
+    buf = []
+    for i, (M, N, K) in enumerate(shapes):
+        A = datagen.uniform((61, i, 0), M, K, ld=K + 1)
+        B = datagen.uniform((61, i, 1), K, N, ld=N + 3)
+        ops.append((np.ascontiguousarray(A), np.ascontiguousarray(B)))
+        dA = torch.from_numpy(A.base.copy()).cuda()
+        dB = torch.from_numpy(B.base.copy()).cuda()
+        dC = torch.full((M, N + 2), float("nan"), device="cuda")
+        buf.append((dA, dB, dC))
+        descs.append((dA.data_ptr(), dB.data_ptr(), dC.data_ptr(), K + 1, N + 3, N + 2, M, N, K, 0))
+    for vid in loaded[:: max(1, len(loaded) // 12)]:
+        d = np.array(descs, dtype=abi.gemm_desc_dtype())
+        total, prefix, vec = abi.sgemm_grouped_plan(vid, d)
+        assert not vec
+        d_dev = torch.from_numpy(d.view(np.uint8)).cuda()
+        p_dev = torch.from_numpy(prefix).cuda()
+        for (_, _, dC) in buf:
+            dC.fill_(float("nan"))
+        abi.sgemm_grouped(vid, len(shapes), d_dev, p_dev, total, 1.0, 0.0, vec)
+        torch.cuda.synchronize()
+        for i, ((A, B), (_, _, dC)) in enumerate(zip(ops, buf)):
+            C = dC.cpu().numpy()
+            M, N = C.shape[0], shapes[i][1]
+            assert np.all(np.isnan(C[:, N:])), "padding written"
+            _, S, T = oracle.ref_gemm(A, B)
+            assert np.all(np.abs(C[:, :N] - S) <= 4 * A.shape[1] * 2.0 ** -24 * T), (vid, i)
+
+
+def test_grouped_graph_replays(loaded):
+    shapes, ops = _small_batch(2, count=30)
+    batch = batched.Batch(shapes, host_ops=ops)
+    idx = list(range(len(shapes)))
+    halves = [idx[::2], idx[1::2]]
+    plans = [batched.GroupedPlan(batch, h, loaded[(7 * j) % len(loaded)]) for j, h in enumerate(halves)]
+    for p in plans:
+        p.launch()
+    torch.cuda.synchronize()
+    eager = batch.C.clone()
+    assert not _check_batch(batch, ops, "eager")
+    graph = torch.cuda.CUDAGraph()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        for p in plans:
+            p.launch(stream=s)
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    with torch.cuda.graph(graph):
+        for p in plans:
+            p.launch(stream=torch.cuda.current_stream())
+    for r in range(3):
+        batch.C.zero_()                  # eager work between replays
+        torch.cuda.synchronize()
+        graph.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(batch.C, eager), f"replay {r} differs from the eager result"
+
+
+def test_plan_rejects_bad_problems(loaded):
+    d = np.zeros(2, dtype=abi.gemm_desc_dtype())
+    d[0] = (16, 16, 16, 4, 4, 4, 4, 4, 4, 0)
+    d[1] = (16, 16, 16, 3, 4, 4, 4, 4, 4, 0)     # lda < K
+    with pytest.raises(abi.FewfitError):
+        abi.sgemm_grouped_plan(loaded[0], d)

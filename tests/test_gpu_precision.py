@@ -28,8 +28,8 @@ def _split_variants():
     for line in open(os.path.join(VARIANT_DIR, "manifest.txt")):
         if not line.startswith("#"):
             f = line.split()
-            if int(f[14]) > 0:
-                out.append((int(f[0]), f[1], FORMS[int(f[14])]))
+            if int(f[13]) > 0:
+                out.append((int(f[0]), f[1], FORMS[int(f[13])]))
     return out
 
 

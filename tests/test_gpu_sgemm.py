@@ -29,7 +29,7 @@ def _manifest(prec=0):
     for line in open(os.path.join(VARIANT_DIR, "manifest.txt")):
         if not line.startswith("#"):
             f = line.split()
-            if int(f[14]) == prec:
+            if int(f[13]) == prec:
                 out.append((int(f[0]), f[1]))
     return out
 
