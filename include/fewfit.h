@@ -166,7 +166,7 @@ int variant_count(void);
 /*
  * Write variant `id`'s descriptor into buf (NUL-terminated, truncated to
  * len): "<id> <name> <MWG> <NWG> <KWG> <MI> <WM> <WN> <SK> <VW> <LDS> <GM> <SG>
- * <PREC>", PREC the precision form (FF_FORM_*).
+ * <PREC> <PD>", PREC the precision form (FF_FORM_*), PD the prefetch depth.
  * Returns the full length, or FF_ERR_VARIANT.
  */
 int variant_info(int id, char *buf, size_t len);

@@ -66,7 +66,7 @@ def build_variants(variants=None, outdir=VARIANT_DIR, jobs=None, verbose=False):
             if verbose:
                 print(f"  built {v.name} ({dt:.1f} s, {size} B)", flush=True)
     with open(os.path.join(outdir, "manifest.txt"), "w") as f:
-        f.write("# id name MWG NWG KWG MI WM WN SK VW LDS GM SG PREC\n")
+        f.write("# id name MWG NWG KWG MI WM WN SK VW LDS GM SG PREC PD\n")
         for vid, v in enumerate(variants):
             f.write(v.descriptor(vid) + "\n")
     with open(os.path.join(outdir, "build_stats.txt"), "w") as f:

@@ -56,6 +56,7 @@ struct Variant {
     std::string name;
     int mwg = 0, nwg = 0, kwg = 0, mi = 0, wm = 0, wn = 0, sk = 0, vw = 0, lds = 0, gm = 0, sg = 0;
     int prec = 0;  // 0 FP32 MFMA; 1 bf16x3, 2 bf16x6, 3 scaled fp16 (16-bit MFMA, FP32 accumulation)
+    int pd = 1;    // prefetch depth (compiled into the kernel; not a launch parameter)
     hipModule_t mod = nullptr;
     hipFunction_t fvec = nullptr;  // VW-wide loads
     hipFunction_t fsca = nullptr;  // scalar loads
@@ -65,12 +66,13 @@ struct Variant {
     int threads() const { return 64 * wm * wn * sk; }
 };
 
-// "<id> <name> MWG NWG KWG MI WM WN SK VW LDS GM SG PREC"
+// "<id> <name> MWG NWG KWG MI WM WN SK VW LDS GM SG PREC PD"
 bool parse_descriptor(std::istringstream& is, Variant& v)
 {
     if (!(is >> v.id >> v.name >> v.mwg >> v.nwg >> v.kwg >> v.mi >> v.wm >> v.wn >> v.sk >> v.vw >> v.lds >> v.gm >>
-          v.sg >> v.prec))
+          v.sg >> v.prec >> v.pd))
         return false;
+    if (v.pd < 1 || v.pd > 2) return false;
     if (v.id < 0 || v.mwg <= 0 || v.nwg <= 0 || v.kwg <= 0 || (v.mi != 16 && v.mi != 32) || v.wm <= 0 ||
         v.wn <= 0 || v.sk <= 0 || (v.vw != 1 && v.vw != 2 && v.vw != 4) || (v.lds != 0 && v.lds != 1) ||
         v.gm <= 0 || v.sg < 1 || v.sg > 64 || v.prec < 0 || v.prec > 3 || v.threads() > 1024)
@@ -572,8 +574,8 @@ FF_EXPORT int variant_info(int id, char* buf, size_t len)
     auto v = find_variant(id);
     if (!v) return fail(FF_ERR_VARIANT, "variant %d not registered", id);
     char tmp[512];
-    int n = snprintf(tmp, sizeof tmp, "%d %s %d %d %d %d %d %d %d %d %d %d %d %d", v->id, v->name.c_str(), v->mwg,
-                     v->nwg, v->kwg, v->mi, v->wm, v->wn, v->sk, v->vw, v->lds, v->gm, v->sg, v->prec);
+    int n = snprintf(tmp, sizeof tmp, "%d %s %d %d %d %d %d %d %d %d %d %d %d %d %d", v->id, v->name.c_str(),
+                     v->mwg, v->nwg, v->kwg, v->mi, v->wm, v->wn, v->sk, v->vw, v->lds, v->gm, v->sg, v->prec, v->pd);
     if (buf && len > 0) {
         size_t c = std::min(len - 1, (size_t)n);
         memcpy(buf, tmp, c);

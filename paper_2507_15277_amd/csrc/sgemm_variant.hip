@@ -22,6 +22,10 @@
 //                    waves; 0: each wave loads its own operands straight from
 //                    global memory into registers (no LDS, no barriers)
 //   FF_GM            tile-order group height (tiles of M per group)
+//   FF_PD            LDS variants: prefetch depth in slabs (1: the next
+//                    slab's global loads are in flight while the current one
+//                    is computed; 2: the one after next, through a second
+//                    register staging buffer, to cover longer load latency)
 //   FF_SG            largest number of work-groups that split one tile's K
 //                    range (1: no split).  The runtime passes the split count
 //                    actually used (<= FF_SG); with more than one split each
@@ -69,6 +73,9 @@
 #define FF_SG 1
 #define FF_NAME sgemm_m64n64k16_i32_w2x2_s1_v4_l1
 #endif
+#ifndef FF_PD
+#define FF_PD 1
+#endif
 
 #define FF_CAT2(a, b) a##b
 #define FF_CAT(a, b) FF_CAT2(a, b)
@@ -76,7 +83,7 @@
 namespace {
 
 constexpr int MWG = FF_MWG, NWG = FF_NWG, KWG = FF_KWG, MI = FF_MI;
-constexpr int WM = FF_WM, WN = FF_WN, SK = FF_SK, VW = FF_VW, GM = FF_GM, SG = FF_SG;
+constexpr int WM = FF_WM, WN = FF_WN, SK = FF_SK, VW = FF_VW, GM = FF_GM, SG = FF_SG, PD = FF_PD;
 constexpr bool USE_LDS = FF_LDS != 0;
 
 constexpr int MK = (MI == 32) ? 2 : 4;   // k per MFMA instruction
@@ -109,6 +116,7 @@ static_assert(VW == 1 || VW == 2 || VW == 4, "vector width");
 static_assert(NT <= 1024, "work-group size");
 static_assert(KWG % 4 == 0 && NWG % 4 == 0, "LDS vector alignment");
 static_assert(SG >= 1, "split count");
+static_assert(PD == 1 || PD == 2, "prefetch depth");
 
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
@@ -223,13 +231,13 @@ __device__ __forceinline__ void tile_gemm(int M, int N, int K, float alpha,
         constexpr int NVB = KWG * BVEC_ROW;
         constexpr int LB = (NVB + NT - 1) / NT;
         typedef typename VecT<V>::T vt;
-        vt ra[LA], rb[LB];
-        bool oka[LA], okb[LB];
+        vt ra[PD][LA], rb[PD][LB];     // register staging, one set per slab in flight
+        bool oka[PD][LA], okb[PD][LB];
 
         float* sA0 = smem;
         float* sB0 = smem + MWG * LDA_S;
 
-        auto gload = [&](int kt) {
+        auto gload = [&](int kt, int rbuf) {
             const int kb = kt * KWG;
 #pragma unroll
             for (int i = 0; i < LA; ++i) {
@@ -237,8 +245,8 @@ __device__ __forceinline__ void tile_gemm(int M, int N, int K, float alpha,
                 if (NVA % NT == 0 || v < NVA) {
                     const int row = v / AVEC_ROW, kk = (v % AVEC_ROW) * V;
                     const int m = m0 + row, k = kb + kk;
-                    oka[i] = (m < M) && (k < K);
-                    ra[i] = load_raw<V>(A + (long)m * lda + k, oka[i], A);
+                    oka[rbuf][i] = (m < M) && (k < K);
+                    ra[rbuf][i] = load_raw<V>(A + (long)m * lda + k, oka[rbuf][i], A);
                 }
             }
 #pragma unroll
@@ -247,12 +255,12 @@ __device__ __forceinline__ void tile_gemm(int M, int N, int K, float alpha,
                 if (NVB % NT == 0 || v < NVB) {
                     const int row = v / BVEC_ROW, nn = (v % BVEC_ROW) * V;
                     const int k = kb + row, n = n0 + nn;
-                    okb[i] = (k < K) && (n < N);
-                    rb[i] = load_raw<V>(B + (long)k * ldb + n, okb[i], B);
+                    okb[rbuf][i] = (k < K) && (n < N);
+                    rb[rbuf][i] = load_raw<V>(B + (long)k * ldb + n, okb[rbuf][i], B);
                 }
             }
         };
-        auto sstore = [&](int st) {
+        auto sstore = [&](int st, int rbuf) {
             float* sA = sA0 + st * STAGE_FLOATS;
             float* sB = sB0 + st * STAGE_FLOATS;
 #pragma unroll
@@ -260,7 +268,7 @@ __device__ __forceinline__ void tile_gemm(int M, int N, int K, float alpha,
                 const int v = tid + i * NT;
                 if (NVA % NT == 0 || v < NVA) {
                     const int row = v / AVEC_ROW, kk = (v % AVEC_ROW) * V;
-                    *reinterpret_cast<vt*>(sA + row * LDA_S + kk) = zsel<V>(ra[i], oka[i]);
+                    *reinterpret_cast<vt*>(sA + row * LDA_S + kk) = zsel<V>(ra[rbuf][i], oka[rbuf][i]);
                 }
             }
 #pragma unroll
@@ -268,20 +276,14 @@ __device__ __forceinline__ void tile_gemm(int M, int N, int K, float alpha,
                 const int v = tid + i * NT;
                 if (NVB % NT == 0 || v < NVB) {
                     const int row = v / BVEC_ROW, nn = (v % BVEC_ROW) * V;
-                    *reinterpret_cast<vt*>(sB + row * LDB_S + nn) = zsel<V>(rb[i], okb[i]);
+                    *reinterpret_cast<vt*>(sB + row * LDB_S + nn) = zsel<V>(rb[rbuf][i], okb[rbuf][i]);
                 }
             }
         };
 
-        gload(kt0);
-        sstore(0);
-        __syncthreads();
-
         const int arow0 = (wm * WTM + lr) * LDA_S + kg0;
         const int bcol0 = wn * WTN + lr;
-        for (int kt = kt0; kt < kt1; ++kt) {
-            const int st = (kt - kt0) & 1;
-            if (kt + 1 < kt1) gload(kt + 1);
+        auto compute = [&](int st) {
             const float* sA = sA0 + st * STAGE_FLOATS;
             const float* sB = sB0 + st * STAGE_FLOATS;
 #pragma unroll
@@ -305,8 +307,42 @@ __device__ __forceinline__ void tile_gemm(int M, int N, int K, float alpha,
                             acc[i][j] = mfma(bv[j], vget<AV>(av[i], t), acc[i][j]);
                 }
             }
-            if (kt + 1 < kt1) sstore(st ^ 1);
+        };
+
+        if constexpr (PD == 1) {
+            gload(kt0, 0);
+            sstore(0, 0);
             __syncthreads();
+            for (int kt = kt0; kt < kt1; ++kt) {
+                const int st = (kt - kt0) & 1;
+                if (kt + 1 < kt1) gload(kt + 1, 0);
+                compute(st);
+                if (kt + 1 < kt1) sstore(st ^ 1, 0);
+                __syncthreads();
+            }
+        } else {
+            // Slab j is loaded into register set (j - kt0) & 1 two slabs ahead
+            // and staged into LDS stage (j - kt0) & 1 one slab ahead.  Two
+            // slabs per trip keep the register sets statically indexed.  The
+            // loads are issued unconditionally (slabs past the end read the
+            // clamped safe address and are never staged): a conditional load
+            // makes the compiler wait for all loads before the next LDS store,
+            // which would take the second slab of prefetch away.
+            gload(kt0, 0);
+            gload(kt0 + 1, 1);
+            sstore(0, 0);
+            __syncthreads();
+            for (int kt = kt0; kt < kt1; kt += 2) {
+#pragma unroll
+                for (int b = 0; b < 2; ++b) {
+                    if (kt + b < kt1) {
+                        gload(kt + b + 2, b);
+                        compute(b);
+                        if (kt + b + 1 < kt1) sstore(b ^ 1, b ^ 1);
+                        __syncthreads();
+                    }
+                }
+            }
         }
     } else {
         // ---- direct loads: every wave fetches its own operands -------------

@@ -342,6 +342,8 @@ def run(table=TABLE, write_sets=False, splits=5, log=print):
     report["selectors"] = selector_comparison(t, shapes, train_idx, log=log)
     report["fleet"] = fleet_comparison(t, shapes, log=log)
     report["precision"] = precision_report(rows, variants, write_sets, log)
+    if write_sets:
+        tuned.write_fixed_set()
     report["screen"] = {
         "ok": sum(1 for r in rows if r.get("status") == "ok"),
         "wrong": sum(1 for r in rows if r.get("status") == "wrong"),

@@ -45,6 +45,7 @@ class Variant:
     gm: int = 8
     sg: int = 1
     prec: int = 0   # 0 FP32 MFMA; 1 bf16x3, 2 bf16x6, 3 scaled fp16 (csrc/sgemm_split.hip)
+    pd: int = 1     # prefetch depth in slabs (LDS-staged FP32 variants)
 
     @property
     def mk(self):
@@ -100,6 +101,8 @@ class Variant:
             n += f"_g{self.gm}"
         if self.sg != 1:
             n += f"_p{self.sg}"
+        if self.pd != 1:
+            n += f"_d{self.pd}"
         return n
 
     def defines(self):
@@ -109,12 +112,13 @@ class Variant:
                     "FF_NAME": self.name}
         return {"FF_MWG": self.mwg, "FF_NWG": self.nwg, "FF_KWG": self.kwg, "FF_MI": self.mi,
                 "FF_WM": self.wm, "FF_WN": self.wn, "FF_SK": self.sk, "FF_VW": self.vw,
-                "FF_LDS": self.lds, "FF_GM": self.gm, "FF_SG": self.sg, "FF_NAME": self.name}
+                "FF_LDS": self.lds, "FF_GM": self.gm, "FF_SG": self.sg, "FF_PD": self.pd,
+                "FF_NAME": self.name}
 
     def descriptor(self, vid):
-        """Manifest / set-file descriptor: id name MWG NWG KWG MI WM WN SK VW LDS GM SG PREC."""
+        """Manifest / set-file descriptor: id name MWG NWG KWG MI WM WN SK VW LDS GM SG PREC PD."""
         return (f"{vid} {self.name} {self.mwg} {self.nwg} {self.kwg} {self.mi} {self.wm} {self.wn} "
-                f"{self.sk} {self.vw} {self.lds} {self.gm} {self.sg} {self.prec}")
+                f"{self.sk} {self.vw} {self.lds} {self.gm} {self.sg} {self.prec} {self.pd}")
 
     def as_dict(self):
         return asdict(self)
@@ -126,7 +130,7 @@ MAX_SPLIT_LDS_BYTES = 160 * 1024
 
 def legal_split(v: Variant) -> bool:
     """Constraints of the split-precision kernel (csrc/sgemm_split.hip)."""
-    if v.mi not in (16, 32) or v.sk != 1 or v.sg != 1 or v.lds != 1 or v.vw != 4:
+    if v.mi not in (16, 32) or v.sk != 1 or v.sg != 1 or v.lds != 1 or v.vw != 4 or v.pd != 1:
         return False
     if v.mwg % (v.wm * v.mi) or v.nwg % (v.wn * v.mi) or v.kwg % v.mk:
         return False
@@ -144,7 +148,7 @@ def legal(v: Variant) -> bool:
         return legal_split(v)
     if v.mi not in (16, 32) or v.vw not in (1, 2, 4) or v.lds not in (0, 1):
         return False
-    if v.sg not in SPLITS:
+    if v.sg not in SPLITS or v.pd not in (1, 2) or (v.pd == 2 and not v.lds):
         return False
     if v.mwg % (v.wm * v.mi) or v.nwg % (v.wn * v.mi):
         return False
@@ -161,7 +165,7 @@ def legal(v: Variant) -> bool:
         # and the staged slab must fit in registers next to the accumulators.
         if v.mwg * v.kwg < v.threads * v.vw or v.kwg * v.nwg < v.threads * v.vw:
             return False
-        if (v.mwg * v.kwg + v.kwg * v.nwg) > MAX_STAGING * v.threads:
+        if v.pd * (v.mwg * v.kwg + v.kwg * v.nwg) > MAX_STAGING * v.threads:
             return False
     return True
 
@@ -174,10 +178,10 @@ SPLITS = (1, 2, 4, 8, 16)
 def enumerate_space():
     """All legal configurations, in a fixed order."""
     out = []
-    for mi, mwg, nwg, kwg, wm, wn, sk, vw, lds, sg in itertools.product(
+    for mi, mwg, nwg, kwg, wm, wn, sk, vw, lds, sg, pd in itertools.product(
             (32, 16), TILES, TILES, KSTEPS, (1, 2, 4), (1, 2, 4), (1, 2, 4), (1, 2, 4), (1, 0),
-            SPLITS):
-        v = Variant(mwg, nwg, kwg, mi, wm, wn, sk, vw, lds, 8, sg)
+            SPLITS, (1, 2)):
+        v = Variant(mwg, nwg, kwg, mi, wm, wn, sk, vw, lds, 8, sg, 0, pd)
         if legal(v):
             out.append(v)
     return out
@@ -236,6 +240,25 @@ HAND = [
     Variant(32, 32, 64, 32, 1, 1, 4, 4, 1),
     Variant(16, 16, 128, 16, 1, 1, 4, 4, 0, sg=4),
     Variant(32, 32, 128, 32, 1, 1, 4, 4, 0, sg=4),
+    # Prefetch depth 2 (and deeper slabs) for the LDS-staged shapes that win
+    # most often.
+    Variant(32, 32, 64, 32, 1, 1, 4, 4, 1, pd=2),
+    Variant(32, 32, 128, 32, 1, 1, 4, 4, 1),
+    Variant(32, 32, 32, 32, 1, 1, 4, 4, 1, pd=2),
+    Variant(64, 64, 32, 32, 2, 2, 2, 4, 1, pd=2),
+    Variant(64, 64, 64, 32, 2, 2, 2, 4, 1),
+    Variant(64, 64, 64, 32, 2, 2, 2, 4, 1, pd=2),
+    Variant(64, 64, 64, 32, 2, 2, 1, 4, 1, pd=2),
+    Variant(64, 64, 16, 32, 2, 2, 1, 4, 1, sg=4, pd=2),
+    Variant(64, 64, 32, 32, 2, 2, 2, 4, 1, sg=8, pd=2),
+    Variant(128, 128, 32, 32, 2, 2, 2, 4, 1, pd=2),
+    Variant(128, 128, 32, 32, 2, 2, 1, 4, 1, pd=2),
+    Variant(128, 128, 16, 32, 2, 2, 2, 4, 1, pd=2),
+    Variant(256, 128, 16, 32, 4, 2, 1, 4, 1, pd=2),
+    Variant(128, 256, 16, 32, 2, 4, 1, 4, 1, pd=2),
+    Variant(64, 128, 32, 16, 4, 2, 1, 4, 1, sg=4, pd=2),
+    Variant(64, 128, 32, 32, 1, 4, 1, 4, 1, sg=4, pd=2),
+    Variant(256, 128, 16, 32, 4, 2, 1, 4, 1, sg=2, pd=2),
 ]
 
 

@@ -279,3 +279,22 @@ def test_manifest_matches_family():
     man = read_manifest(with_prec=True)
     assert [(i, v.name, v.prec) for i, v in enumerate(fam)] == man
     assert man[0][1] == space.DEFAULT.name
+
+
+def test_committed_sets_match_manifest():
+    """Every member line of a committed set file repeats the manifest's
+    descriptor of that id, so a rebuilt family cannot leave a stale set."""
+    from paper_2507_15277_amd import tuned
+
+    man = {}
+    for line in open(os.path.join(tuned.VARIANT_DIR, "manifest.txt")):
+        if line.strip() and not line.startswith("#"):
+            man[int(line.split()[0])] = line.split()
+    sets_dir = os.path.dirname(tuned.set_path(4))
+    files = sorted(f for f in os.listdir(sets_dir) if f.endswith(".txt"))
+    assert files
+    for fn in files:
+        members = [ln.split()[1:] for ln in open(os.path.join(sets_dir, fn)) if ln.startswith("variant ")]
+        assert members, fn
+        for m in members:
+            assert man[int(m[0])] == m, (fn, m)
