@@ -22,6 +22,12 @@ Readings of the paper taken here (also listed in the design notes):
   nearest in (log2 M, log2 N, log2 K) under the L1 distance and, among the
   members of kappa, the one with the smallest summed log-slowdown over them
   (ties to the member listed first); a training shape gets its own winner.
+  Optionally each member's log-slowdown at a training shape is moved to the
+  query shape by its work-group wave efficiency (``wave_efficiency``): the
+  fraction of the device's compute units that its last wave of work-groups
+  keeps busy, averaged over the waves.  A member that launches too few
+  work-groups to fill the device at a training shape is not blamed for it
+  at a query shape where it does fill the device, and the reverse.
 """
 from __future__ import annotations
 
@@ -183,7 +189,17 @@ def _dist(a, b):
     return sum(abs(math.log2(max(1, a[j])) - math.log2(max(1, b[j]))) for j in range(3))
 
 
-def dispatch(train_shapes, members, cost, M, N, K):
+def wave_efficiency(groups, cus):
+    """Busy fraction of ``cus`` compute units over the waves needed to run
+    ``groups`` work-groups one per unit: groups / (ceil(groups / cus) * cus).
+    No work-groups (an empty problem) counts as fully efficient."""
+    if groups <= 0:
+        return 1.0
+    waves = -(-groups // cus)
+    return groups / (waves * cus)
+
+
+def dispatch(train_shapes, members, cost, M, N, K, groups_train=None, groups_query=None, cus=0):
     """Variant chosen for (M,N,K).
 
     ``cost[i][j]`` is log(t / best) of member j on training shape i.  All
@@ -191,11 +207,21 @@ def dispatch(train_shapes, members, cost, M, N, K):
     smallest total cost over them wins (first member on ties).  If every
     member is infinite somewhere among them, the member cheapest on the
     first nearest shape is taken.
+
+    With ``groups_train[i][j]`` (work-groups member j launches on training
+    shape i), ``groups_query[j]`` (the same at (M,N,K)) and ``cus`` >= 1, the
+    vote adds to each cost the wave correction
+    log(wave_efficiency(groups_train[i][j])) - log(wave_efficiency(groups_query[j])),
+    which is exactly 0 where the two launches have the same efficiency.
     """
     d = [_dist((M, N, K), s) for s in train_shapes]
     dmin = min(d)
     near = [i for i in range(len(train_shapes)) if d[i] <= dmin + 1e-9]
-    totals = [sum(cost[i][j] for i in near) for j in range(len(members))]
+    corr = lambda i, j: 0.0  # noqa: E731
+    if groups_train is not None and groups_query is not None and cus >= 1:
+        corr = lambda i, j: (math.log(wave_efficiency(groups_train[i][j], cus))  # noqa: E731
+                             - math.log(wave_efficiency(groups_query[j], cus)))
+    totals = [sum(cost[i][j] + corr(i, j) for i in near) for j in range(len(members))]
     best_j = min(range(len(members)), key=lambda j: (totals[j], j))
     if totals[best_j] == INF:
         i0 = near[0]

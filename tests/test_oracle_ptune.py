@@ -236,6 +236,82 @@ def test_dispatch_vote_hand_cases():
     assert pr.dispatch(train, members, cost4, 1024, 1024, 1024) == 7
 
 
+def test_wave_efficiency_closed_forms():
+    # One full wave, a partial first wave, one group past a full wave, and
+    # several full waves: groups / (ceil(groups / cus) * cus).
+    assert pr.wave_efficiency(256, 256) == 1.0
+    assert pr.wave_efficiency(64, 256) == 0.25
+    assert pr.wave_efficiency(257, 256) == 257 / 512
+    assert pr.wave_efficiency(1024, 256) == 1.0
+    assert pr.wave_efficiency(1, 256) == 1 / 256
+    assert pr.wave_efficiency(0, 256) == 1.0        # empty product: no launch
+    # Never above 1, never below 1/2 once there is more than one wave.
+    for g in range(257, 2000, 7):
+        assert 0.5 < pr.wave_efficiency(g, 256) <= 1.0
+
+
+def _groups(table, train, members, q):
+    gt = [[table[(j, s)] for j in range(len(members))] for s in train]
+    gq = [table[(j, q)] for j in range(len(members))]
+    return gt, gq
+
+
+def test_dispatch_wave_correction_hand_cases():
+    train, _ = datagen.checkerboard_split()
+    members = [7, 3]
+    q = (1024, 1024, 1024)          # six nearest training shapes, the two-1024 ones
+    near = [s for s in train if s.count(1024) == 2]
+    assert len(near) == 6
+    shapes = train + [q]
+    # Member 3 is the per-shape best everywhere (cost 0) and member 7 is
+    # 0.3 behind; member 7 launches 1024 groups on every shape (E = 1).
+    cost = [[0.3, 0.0] for _ in train]
+    # (a) Member 3 fills the device (512 groups, E = 1) on every training
+    # shape but launches only 64 groups at q (E = 1/4): its six corrections
+    # are log 1 - log(1/4) = log 4, total 6 log 4 = 8.32 > 6 * 0.3 = 1.8 -> 7.
+    tab = {(0, s): 1024 for s in shapes}
+    tab.update({(1, s): 512 for s in train})
+    tab[(1, q)] = 64
+    gt, gq = _groups(tab, train, members, q)
+    assert pr.dispatch(train, members, cost, *q) == 3                     # plain vote
+    assert pr.dispatch(train, members, cost, *q, gt, gq, 256) == 7
+    # (b) The reverse: member 3 is 0.5 behind everywhere but launched only
+    # 128 groups (E = 1/2) on the training shapes and fills the device at q:
+    # each term 0.5 + log(1/2) - log 1 = -0.193, total -1.16 < 0 -> 3.
+    cost_b = [[0.0, 0.5] for _ in train]
+    tab_b = {(0, s): 256 for s in shapes}
+    tab_b.update({(1, s): 128 for s in train})
+    tab_b[(1, q)] = 256
+    gt, gq = _groups(tab_b, train, members, q)
+    assert pr.dispatch(train, members, cost_b, *q) == 7
+    assert pr.dispatch(train, members, cost_b, *q, gt, gq, 256) == 3
+    # With cus = 0 or no groups the correction is off.
+    assert pr.dispatch(train, members, cost_b, *q, gt, gq, 0) == 7
+    assert pr.dispatch(train, members, cost_b, *q, None, gq, 256) == 7
+    # (c) A training shape keeps its own winner whatever the groups, as its
+    # launch at the query is the same launch.
+    s0 = (256, 1024, 1024)
+    tab_c = dict(tab)
+    tab_c[(0, s0)] = 3
+    tab_c[(1, s0)] = 5000
+    gt, gq = _groups(tab_c, train, members, s0)
+    assert pr.dispatch(train, members, cost, *s0, gt, gq, 256) == 3
+
+
+def test_dispatch_wave_correction_vanishes_on_full_waves():
+    # When every launch is a whole number of full waves, E = 1 everywhere and
+    # the corrected rule is the plain vote, for any costs and query.
+    rng = np.random.default_rng(5)
+    train, _ = datagen.checkerboard_split()
+    members = [11, 4, 8, 2]
+    for _ in range(20):
+        cost = rng.exponential(0.3, (len(train), len(members))).tolist()
+        gt = (rng.integers(1, 9, (len(train), len(members))) * 256).tolist()
+        gq = (rng.integers(1, 9, len(members)) * 256).tolist()
+        q = tuple(int(x) for x in 2 ** rng.integers(6, 14, 3))
+        assert pr.dispatch(train, members, cost, *q, gt, gq, 256) == pr.dispatch(train, members, cost, *q)
+
+
 def test_assign_winners():
     t = [[1.0, 5.0, 2.0], [2.0, 1.0, 2.0], [3.0, 3.0, 1.0]]
     assert pr.assign_winners(t, (0, 1), [0, 1, 2]) == [0, 1, 0]
