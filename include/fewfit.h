@@ -107,7 +107,8 @@ int sgemm(int64_t M, int64_t N, int64_t K, float alpha,
  * dispatch table of training shapes.  Only the k code
  * objects of the set are loaded (Sec. III-B-3: pre-selection keeps the
  * number of shipped variants small).  Replaces any previously loaded set
- * of the same form.
+ * of the same form.  At most 64 members.  The dispatch's wave correction is
+ * tabulated for the current device at load.
  * Not safe to call concurrently with sgemm() on another thread.
  * Returns k on success; FF_ERR_IO, FF_ERR_PARSE, FF_ERR_ARCH, FF_ERR_HIP.
  */
@@ -135,10 +136,14 @@ int sgemm_form(int form, int64_t M, int64_t N, int64_t K, float alpha,
  * Fig. 1 leaves the online picker open and Sec. V-I names unseen inputs as
  * a limitation; the rule used here (ptune_dispatch): find the training
  * shapes nearest to (M, N, K) in L1 distance over (log2 M, log2 N, log2 K),
- * sizes below 1 counted as 1; with one nearest shape take its winner, with
- * several take the member whose log-slowdowns summed over them is
- * smallest (ties to the member listed first).  A training shape therefore
- * always gets its own winner.  Returns the id (>= 0), FF_ERR_NO_SET, or an
+ * sizes below 1 counted as 1, and take the member whose log-slowdowns
+ * summed over them is smallest (ties to the member listed first), each
+ * log-slowdown moved from the training shape to (M, N, K) by the member's
+ * wave correction: log E(training launch) - log E(launch at (M, N, K)),
+ * with E(g) = g / (ceil(g / cus) * cus) for a launch of g work-groups
+ * (tiles times K splits) on the current device's cus compute units.  A
+ * training shape therefore always gets its own winner.  Returns the id
+ * (>= 0), FF_ERR_NO_SET, FF_ERR_HIP if the device cannot be queried, or an
  * argument error for negative sizes.
  */
 int variant_select(int64_t M, int64_t N, int64_t K);
@@ -349,11 +354,19 @@ int ptune_nearest(int ntrain, const int64_t *train_mnk, int64_t M, int64_t N, in
  * the set's variant ids, cost[i*k + j] = log(t[members[j]][i] / best[i])
  * on training shape i (+inf where member j failed there).  Among the
  * training shapes at the smallest distance (as in ptune_nearest, equal
- * within 1e-9), returns the member id with the smallest summed cost, ties
- * to the lower j.  Returns the id, or FF_ERR_ARG.
+ * within 1e-9), returns the member id with the smallest sum over them of
+ * cost[i*k + j] + (log E(groups_train[i*k + j]) - log E(groups_query[j])),
+ * ties to the lower j, where E(g) = g / (ceil(g / cus) * cus) (1 for
+ * g <= 0) and groups_* are work-group counts of member j's launch on
+ * training shape i and on (M, N, K).  With groups_train or groups_query
+ * NULL, or cus < 1, the correction is 0.  If every member's sum is +inf,
+ * the member cheapest on the first nearest shape.  Returns the id, or
+ * FF_ERR_ARG.
  */
 int ptune_dispatch(int ntrain, const int64_t *train_mnk, int k, const int *members,
-                   const double *cost, int64_t M, int64_t N, int64_t K);
+                   const double *cost, const int64_t *groups_train,
+                   const int64_t *groups_query, int cus, int64_t M, int64_t N,
+                   int64_t K);
 
 #ifdef __cplusplus
 }

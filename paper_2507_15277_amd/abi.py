@@ -70,7 +70,7 @@ def lib():
         L.ptune_select.argtypes = [i32, i32, vp, i32, vp, i32, i32, vp, vp, vp]
         L.ptune_assign.argtypes = [i32, i32, vp, i32, vp, i32, vp, vp]
         L.ptune_nearest.argtypes = [i32, vp, i64, i64, i64]
-        L.ptune_dispatch.argtypes = [i32, vp, i32, vp, vp, i64, i64, i64]
+        L.ptune_dispatch.argtypes = [i32, vp, i32, vp, vp, vp, vp, i32, i64, i64, i64]
         L.sgemm_grouped_plan.argtypes = [i32, i32, vp, vp, vp]
         L.sgemm_grouped.argtypes = [i32, i32, vp, vp, i32, f32, f32, i32, vp]
         L.ptune_select_total.argtypes = [i32, i32, vp, i32, vp, vp, i32, i32, vp, vp, vp]
@@ -283,14 +283,21 @@ def ptune_nearest(train_shapes, M, N, K):
     return _check(lib().ptune_nearest(tr.shape[0], tr.ctypes.data, M, N, K))
 
 
-def ptune_dispatch(train_shapes, members, cost, M, N, K):
-    """cost: ntrain x k log-slowdowns of the members on the training shapes."""
+def ptune_dispatch(train_shapes, members, cost, M, N, K, groups_train=None, groups_query=None, cus=0):
+    """cost: ntrain x k log-slowdowns of the members on the training shapes;
+    groups_train (ntrain x k) and groups_query (k): work-groups of each
+    member's launch, for the wave correction on ``cus`` compute units."""
     import numpy as np
     tr = np.ascontiguousarray(train_shapes, dtype=np.int64).reshape(-1, 3)
     mem = np.ascontiguousarray(members, dtype=np.int32)
     c = np.ascontiguousarray(cost, dtype=np.float64).reshape(tr.shape[0], mem.size)
+    gt = gq = None
+    if groups_train is not None and groups_query is not None:
+        gt = np.ascontiguousarray(groups_train, dtype=np.int64).reshape(tr.shape[0], mem.size)
+        gq = np.ascontiguousarray(groups_query, dtype=np.int64).reshape(mem.size)
     return _check(lib().ptune_dispatch(tr.shape[0], tr.ctypes.data, mem.size, mem.ctypes.data,
-                                       c.ctypes.data, M, N, K))
+                                       c.ctypes.data, None if gt is None else gt.ctypes.data,
+                                       None if gq is None else gq.ctypes.data, cus, M, N, K))
 
 
 def ptune_select_total(t, k, shapes, weights, method=-1):

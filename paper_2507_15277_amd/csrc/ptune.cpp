@@ -28,6 +28,7 @@
 #include <vector>
 
 #include "../../include/fewfit.h"
+#include "ptune_internal.h"
 
 #define FF_EXPORT extern "C" __attribute__((visibility("default")))
 
@@ -620,10 +621,16 @@ FF_EXPORT int ptune_nearest(int ntrain, const int64_t* train_mnk, int64_t M, int
     return best;
 }
 
-FF_EXPORT int ptune_dispatch(int ntrain, const int64_t* train_mnk, int k, const int* members, const double* cost,
-                             int64_t M, int64_t N, int64_t K)
+double ptune_log_wave_efficiency(int64_t groups, int cus)
 {
-    if (ntrain < 1 || train_mnk == nullptr || k < 1 || members == nullptr || cost == nullptr) return FF_ERR_ARG;
+    if (groups <= 0) return 0.0;
+    const int64_t waves = (groups + cus - 1) / cus;
+    return std::log((double)groups / (double)(waves * cus));
+}
+
+int ptune_dispatch_lw(int ntrain, const int64_t* train_mnk, int k, const int* members, const double* cost,
+                      const double* lw_train, const double* lw_query, int64_t M, int64_t N, int64_t K)
+{
     std::vector<double> d;
     shape_distances(ntrain, train_mnk, M, N, K, d);
     const double dmin = *std::min_element(d.begin(), d.end());
@@ -631,8 +638,11 @@ FF_EXPORT int ptune_dispatch(int ntrain, const int64_t* train_mnk, int k, const 
     double bs = kInf;
     for (int j = 0; j < k; ++j) {
         double sum = 0.0;
-        for (int i = 0; i < ntrain; ++i)
-            if (d[i] <= dmin + 1e-9) sum += cost[(size_t)i * k + j];
+        for (int i = 0; i < ntrain; ++i) {
+            if (d[i] > dmin + 1e-9) continue;
+            const double corr = lw_train ? lw_train[(size_t)i * k + j] - lw_query[j] : 0.0;
+            sum += cost[(size_t)i * k + j] + corr;
+        }
         if (bj < 0 || sum < bs) {
             bj = j;
             bs = sum;
@@ -648,4 +658,17 @@ FF_EXPORT int ptune_dispatch(int ntrain, const int64_t* train_mnk, int k, const 
             if (cost[(size_t)i0 * k + j] < cost[(size_t)i0 * k + bj]) bj = j;
     }
     return members[bj];
+}
+
+FF_EXPORT int ptune_dispatch(int ntrain, const int64_t* train_mnk, int k, const int* members, const double* cost,
+                             const int64_t* groups_train, const int64_t* groups_query, int cus, int64_t M,
+                             int64_t N, int64_t K)
+{
+    if (ntrain < 1 || train_mnk == nullptr || k < 1 || members == nullptr || cost == nullptr) return FF_ERR_ARG;
+    const bool waves = groups_train != nullptr && groups_query != nullptr && cus >= 1;
+    if (!waves) return ptune_dispatch_lw(ntrain, train_mnk, k, members, cost, nullptr, nullptr, M, N, K);
+    std::vector<double> lt((size_t)ntrain * k), lq(k);
+    for (size_t x = 0; x < lt.size(); ++x) lt[x] = ptune_log_wave_efficiency(groups_train[x], cus);
+    for (int j = 0; j < k; ++j) lq[j] = ptune_log_wave_efficiency(groups_query[j], cus);
+    return ptune_dispatch_lw(ntrain, train_mnk, k, members, cost, lt.data(), lq.data(), M, N, K);
 }

@@ -25,6 +25,7 @@
 #include <vector>
 
 #include "../../include/fewfit.h"
+#include "ptune_internal.h"
 
 #define FF_EXPORT extern "C" __attribute__((visibility("default")))
 
@@ -89,9 +90,16 @@ struct VarSet {
     std::vector<int64_t> flat;                   // the same, as M,N,K triples
     std::vector<int> winners;                    // member chosen per training shape
     std::vector<double> cost;                    // ntrain x k log-slowdowns of the members
+    std::vector<Variant> members;                // descriptors, in member order
+    // Wave correction of the dispatch, for the device the set was loaded on:
+    // its compute-unit count and the log wave efficiency of every member's
+    // launch on every training shape (ntrain x k).
+    int dev = -1, cus = 0;
+    std::vector<double> lw_train;
 };
 
 constexpr int kForms = 4;
+constexpr int kMaxMembers = 64;  // variants in one set
 std::mutex g_mu;
 std::map<int, std::shared_ptr<Variant>> g_variants;
 std::shared_ptr<const VarSet> g_set[kForms];  // one loaded set per precision form
@@ -119,7 +127,7 @@ int ensure_workspace()
     e = hipMalloc(&w.ws, kWsBytes);
     if (e == hipSuccess) e = hipMalloc(&w.scale, (2 * kMaxBlocks + 4) * sizeof(float));
     if (e != hipSuccess) {
-        if (w.ws) hipFree(w.ws);
+        if (w.ws) (void)hipFree(w.ws);
         w = Workspace{};
         return hip_fail(e, "allocate workspace");
     }
@@ -139,7 +147,7 @@ int load_code_object(Variant& v, const std::string& path)
     e = hipModuleGetFunction(&fv, mod, v.name.c_str());
     if (e == hipSuccess) e = hipModuleGetFunction(&fs, mod, (v.name + "_v1").c_str());
     if (e != hipSuccess) {
-        hipModuleUnload(mod);
+        (void)hipModuleUnload(mod);
         return hip_fail(e, ("hipModuleGetFunction " + v.name).c_str());
     }
     v.mod = mod;
@@ -340,6 +348,37 @@ __global__ void __launch_bounds__(64) ff_fp16_prescale(int nb, float* __restrict
     o[2] = ldexpf(1.0f, -(ea + eb));
 }
 
+// The current device's K-split workspace, or nullptr if it has none.
+float* current_workspace()
+{
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return nullptr;
+    return g_ws[dev].ws;
+}
+
+// K split over work-groups: as many as the variant allows, no more than
+// there are slabs, every split non-empty, and within the workspace.  M, N >= 1.
+int split_count(const Variant& v, int64_t M, int64_t N, int64_t K, bool have_ws)
+{
+    const int64_t nkt = (K + v.kwg - 1) / v.kwg;
+    if (!(v.sg > 1 && nkt > 1 && v.prec == 0 && have_ws)) return 1;
+    const int64_t nb = ((M + v.mwg - 1) / v.mwg) * ((N + v.nwg - 1) / v.nwg);
+    int64_t sp = std::min<int64_t>(v.sg, nkt);
+    sp = std::min<int64_t>(sp, (int64_t)(kWsBytes / (size_t)(M * N * 4)));
+    if (sp < 2 || nb * sp > INT32_MAX) return 1;
+    const int64_t per = (nkt + sp - 1) / sp;
+    return (int)((nkt + per - 1) / per);
+}
+
+// Work-groups of the GEMM kernel launch of variant v on (M, N, K): tiles
+// times K splits; 0 for an empty product (nothing is launched).
+int64_t launch_groups(const Variant& v, int64_t M, int64_t N, int64_t K, bool have_ws)
+{
+    if (M <= 0 || N <= 0) return 0;
+    const int64_t nb = ((M + v.mwg - 1) / v.mwg) * ((N + v.nwg - 1) / v.nwg);
+    return nb * split_count(v, M, N, K, have_ws);
+}
+
 int launch_variant(const Variant& v, int64_t M, int64_t N, int64_t K, float alpha, const float* A,
                    int64_t lda, const float* B, int64_t ldb, float beta, float* C, int64_t ldc, hipStream_t s)
 {
@@ -370,23 +409,10 @@ int launch_variant(const Variant& v, int64_t M, int64_t N, int64_t K, float alph
         if (e0 != hipSuccess) return hip_fail(e0, "launch fp16 prescale");
         prescale = buf + 2 * kMaxBlocks;
     }
-    // K split over work-groups: as many as the variant allows, no more than
-    // there are slabs, every split non-empty, and within the workspace.
     const int64_t nkt = (K + v.kwg - 1) / v.kwg;
-    int splits = 1;
-    float* ws = nullptr;
-    if (v.sg > 1 && nkt > 1 && v.prec == 0) {
-        int dev = 0;
-        if (hipGetDevice(&dev) == hipSuccess && dev >= 0 && dev < kMaxDevices && g_ws[dev].ws != nullptr) {
-            int64_t sp = std::min<int64_t>(v.sg, nkt);
-            sp = std::min<int64_t>(sp, (int64_t)(kWsBytes / (size_t)(M * N * 4)));
-            if (sp >= 2 && nb * sp <= INT32_MAX) {
-                const int64_t per = (nkt + sp - 1) / sp;
-                splits = (int)((nkt + per - 1) / per);
-                ws = g_ws[dev].ws;
-            }
-        }
-    }
+    float* ws = current_workspace();
+    int splits = split_count(v, M, N, K, ws != nullptr);
+    if (splits == 1) ws = nullptr;
     int kper = (int)((nkt + splits - 1) / splits);
     int Mi = (int)M, Ni = (int)N, Ki = (int)K;
     long la = (long)lda, lb = (long)ldb, lc = (long)ldc;
@@ -596,6 +622,33 @@ FF_EXPORT int variant_info(int id, char* buf, size_t len)
 //                          lines): its winner, a member, and every member's
 //                          log-slowdown on it ("inf" where it failed)
 //   end
+static int device_cus(int& dev, int& cus)
+{
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e != hipSuccess) return hip_fail(e, "query compute units");
+    if (cus < 1) return fail(FF_ERR_HIP, "device reports %d compute units", cus);
+    return FF_OK;
+}
+
+// Log wave efficiency of every member on every training shape, for the
+// current device (its compute units and whether it holds a workspace).
+static int wave_table(VarSet& set)
+{
+    int rc = device_cus(set.dev, set.cus);
+    if (rc != FF_OK) return rc;
+    const bool ws = current_workspace() != nullptr;
+    const size_t k = set.members.size();
+    set.lw_train.assign(set.shapes.size() * k, 0.0);
+    for (size_t i = 0; i < set.shapes.size(); ++i)
+        for (size_t j = 0; j < k; ++j) {
+            const auto& s = set.shapes[i];
+            set.lw_train[i * k + j] =
+                ptune_log_wave_efficiency(launch_groups(set.members[j], s[0], s[1], s[2], ws), set.cus);
+        }
+    return FF_OK;
+}
+
 FF_EXPORT int variant_set_load(const char* path)
 {
     if (path == nullptr) return fail(FF_ERR_ARG, "variant_set_load: path is NULL");
@@ -680,6 +733,8 @@ FF_EXPORT int variant_set_load(const char* path)
         return fail(FF_ERR_PARSE, "%s: needs arch, codedir, at least one variant and one rule", path);
     for (const Variant& v : members)
         if (v.prec != form) return fail(FF_ERR_PARSE, "%s: variant %d is not of the set's form", path, v.id);
+    if (members.size() > (size_t)kMaxMembers)
+        return fail(FF_ERR_PARSE, "%s: %zu members exceed the limit of %d", path, members.size(), kMaxMembers);
 
     std::string dev;
     int rc = device_arch(dev);
@@ -692,6 +747,9 @@ FF_EXPORT int variant_set_load(const char* path)
         rc = register_variant(v, dir);
         if (rc != FF_OK) return rc;
     }
+    set->members = members;
+    rc = wave_table(*set);
+    if (rc != FF_OK) return rc;
     g_set[form] = set;
     return (int)set->ids.size();
 }
@@ -708,8 +766,29 @@ FF_EXPORT int variant_select_form(int form, int64_t M, int64_t N, int64_t K)
         set = g_set[form];
     }
     if (!set) return fail(FF_ERR_NO_SET, "no variant set loaded for form %d", form);
-    const int id = ptune_dispatch((int)set->shapes.size(), set->flat.data(), (int)set->ids.size(), set->ids.data(),
-                                  set->cost.data(), M, N, K);
+    // Wave correction with the training-shape table of the device the set
+    // was loaded on; on another device both sides are computed afresh.
+    int dev = 0, cus = 0;
+    int rc = device_cus(dev, cus);
+    if (rc != FF_OK) return rc;
+    const bool ws = current_workspace() != nullptr;
+    const size_t k = set->members.size();
+    double lq[kMaxMembers];
+    std::vector<double> lt_other;
+    const double* lt = set->lw_train.data();
+    for (size_t j = 0; j < k; ++j) lq[j] = ptune_log_wave_efficiency(launch_groups(set->members[j], M, N, K, ws), cus);
+    if (dev != set->dev || cus != set->cus) {
+        lt_other.resize(set->shapes.size() * k);
+        for (size_t i = 0; i < set->shapes.size(); ++i)
+            for (size_t j = 0; j < k; ++j) {
+                const auto& s = set->shapes[i];
+                lt_other[i * k + j] =
+                    ptune_log_wave_efficiency(launch_groups(set->members[j], s[0], s[1], s[2], ws), cus);
+            }
+        lt = lt_other.data();
+    }
+    const int id = ptune_dispatch_lw((int)set->shapes.size(), set->flat.data(), (int)k, set->ids.data(),
+                                     set->cost.data(), lt, lq, M, N, K);
     if (id < 0) return fail(FF_ERR_NO_SET, "variant set has no training shapes");
     return id;
 }
@@ -759,7 +838,7 @@ FF_EXPORT int sgemm_time(int id, int64_t M, int64_t N, int64_t K, float alpha, c
     if (e != hipSuccess) return hip_fail(e, "hipEventCreate");
     e = hipEventCreate(&e1);
     if (e != hipSuccess) {
-        hipEventDestroy(e0);
+        (void)hipEventDestroy(e0);
         return hip_fail(e, "hipEventCreate");
     }
     rc = FF_OK;
@@ -776,8 +855,8 @@ FF_EXPORT int sgemm_time(int id, int64_t M, int64_t N, int64_t K, float alpha, c
         if (e != hipSuccess) { rc = hip_fail(e, "timing events"); break; }
         trial_ms[t] = ms / (float)reps;
     }
-    hipEventDestroy(e0);
-    hipEventDestroy(e1);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
     return rc;
 }
 

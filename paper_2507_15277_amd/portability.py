@@ -10,7 +10,8 @@ Steps (Sec. IV, Sec. V-C, Sec. V-E), all arithmetic in libfewfit:
 * the dispatch table for the set file: the in-set winner of each training
   shape and every member's log-slowdown there; an unseen shape goes to the
   member with the smallest summed log-slowdown over its nearest training
-  shapes (``ptune_dispatch``);
+  shapes, each moved to the unseen shape by the member's work-group wave
+  efficiency on the device (``ptune_dispatch``);
 * evaluation (Sec. V-E figures of merit): fraction of the per-shape best
   (1 / slowdown-over-best, geometric mean) on the held-out shapes as
   realised by the dispatch rule, and over all 27 shapes with a perfect
@@ -74,6 +75,22 @@ def tflops(shape, ms):
     return 2.0 * M * N * K / ms / 1e9
 
 
+# Compute units of the device the table was measured on (MI355X); the
+# runtime queries the device it runs on.
+DEVICE_CUS = 256
+_VARIANTS = {}
+
+
+def dispatch(train, kappa, costs, M, N, K):
+    """The runtime's pick for (M, N, K): the neighbour vote with the wave
+    correction for DEVICE_CUS compute units (``ptune_dispatch``)."""
+    if not _VARIANTS:
+        _VARIANTS.update(read_variants())
+    gt = [[_VARIANTS[v].work_groups(*s) for v in kappa] for s in train]
+    gq = [_VARIANTS[v].work_groups(M, N, K) for v in kappa]
+    return abi.ptune_dispatch(train, kappa, costs, M, N, K, gt, gq, DEVICE_CUS)
+
+
 def member_costs(t, kappa, train_idx):
     """ntrain x k matrix of ln(t[member][shape] / best[shape])."""
     best, _, _, _, _ = abi.ptune_postprocess(t)
@@ -94,7 +111,7 @@ def evaluate(t, shapes, train_idx, kappa, extra=()):
     held_idx = [j for j in range(len(shapes)) if j not in set(train_idx)]
     realised = {}
     for j, s in enumerate(shapes):
-        realised[j] = abi.ptune_dispatch(train, kappa, costs, *s)
+        realised[j] = dispatch(train, kappa, costs, *s)
     frac = lambda idx, pick: geomean(best[j] / t[pick(j), j] for j in idx)  # noqa: E731
     in_set = lambda j: min(kappa, key=lambda v: (t[v, j], v))  # noqa: E731
     return {
@@ -319,7 +336,7 @@ def run(table=TABLE, write_sets=False, splits=5, log=print):
         for k in KS:
             ev = report["sets"][str(k)]
             trs = [shapes[j] for j in train_idx]
-            picks = [abi.ptune_dispatch(trs, ev["kappa"], ev["costs"], *s) for s in extra_shapes]
+            picks = [dispatch(trs, ev["kappa"], ev["costs"], *s) for s in extra_shapes]
             ex[f"k{k}"] = [float(be[j] / te[p, j]) for j, p in enumerate(picks)]
         report["default_example_shapes"] = {"shapes": extra_shapes, "frac_of_best": ex}
     # Square sweep (beta 0 and 0.5): per-shape best and whether beta moves it.

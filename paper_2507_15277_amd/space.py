@@ -24,6 +24,7 @@ import numpy as np
 # Per-lane register budgets used to reject configurations that would spill
 # or leave no room for the pipeline (gfx950: 512 VGPR+AGPR per lane at one
 # wave per SIMD).
+WORKSPACE_BYTES = 128 << 20  # per-device K-split workspace of the runtime
 MAX_ACC = 128            # accumulator floats per lane
 MAX_DIRECT_OPERANDS = 64  # double-buffered operand registers, direct loads
 MAX_LDS_BYTES = 80 * 1024  # keeps >= 2 work-groups per CU possible (160 KB LDS)
@@ -114,6 +115,22 @@ class Variant:
                 "FF_WM": self.wm, "FF_WN": self.wn, "FF_SK": self.sk, "FF_VW": self.vw,
                 "FF_LDS": self.lds, "FF_GM": self.gm, "FF_SG": self.sg, "FF_PD": self.pd,
                 "FF_NAME": self.name}
+
+    def work_groups(self, M, N, K, have_ws=True):
+        """Work-groups of this variant's GEMM launch on (M, N, K): tiles times
+        K splits, the split count chosen as the runtime chooses it (as many
+        as SG allows, no more than there are slabs, every split non-empty,
+        within the 128 MiB workspace); 0 for an empty product."""
+        if M <= 0 or N <= 0:
+            return 0
+        nb = -(-M // self.mwg) * -(-N // self.nwg)
+        nkt = -(-K // self.kwg)
+        if self.sg > 1 and nkt > 1 and self.prec == 0 and have_ws:
+            sp = min(self.sg, nkt, WORKSPACE_BYTES // (M * N * 4))
+            if sp >= 2 and nb * sp <= 2**31 - 1:
+                per = -(-nkt // sp)
+                return nb * -(-nkt // per)
+        return nb
 
     def descriptor(self, vid):
         """Manifest / set-file descriptor: id name MWG NWG KWG MI WM WN SK VW LDS GM SG PREC PD."""

@@ -214,6 +214,15 @@ def test_dispatch_matches_oracle(seed):
         assert abi.ptune_dispatch(train, members, cost, *q) == pr.dispatch(train, members, cost.tolist(), *q), q
     for i, s in enumerate(train):
         assert abi.ptune_nearest(train, *s) == i
+    # With the wave correction: work-group counts from 1 to a few waves of
+    # 256 compute units (and 0, an empty launch), per member and shape.
+    gt = rng.integers(0, 1100, (len(train), k))
+    for q in queries:
+        gq = rng.integers(0, 1100, k)
+        for cus in (256, 304, 0):
+            got = abi.ptune_dispatch(train, members, cost, *q, gt, gq, cus)
+            want = pr.dispatch(train, members, cost.tolist(), *q, gt.tolist(), gq.tolist(), cus)
+            assert got == want, (q, cus)
 
 
 def test_select_argument_errors():
