@@ -32,6 +32,8 @@
 
 #define FF_EXPORT extern "C" __attribute__((visibility("default")))
 
+double ptune_log2_size(int64_t x) { return std::log2((double)std::max<int64_t>(1, x)); }
+
 namespace {
 
 const double kInf = std::numeric_limits<double>::infinity();
@@ -597,15 +599,18 @@ FF_EXPORT int ptune_assign(int nv, int ns, const double* t, int k, const int* ka
 namespace {
 
 // L1 distance over log2 sizes (sizes below 1 count as 1).
-void shape_distances(int ntrain, const int64_t* train_mnk, int64_t M, int64_t N, int64_t K,
+// L1 distances over log2 sizes (sizes below 1 count as 1).  train_lg, when
+// given, holds the training shapes' log2 sizes already computed.
+void shape_distances(int ntrain, const int64_t* train_mnk, const double* train_lg, int64_t M, int64_t N, int64_t K,
                      std::vector<double>& d)
 {
-    auto lg = [](int64_t x) { return std::log2((double)std::max<int64_t>(1, x)); };
-    const double q[3] = {lg(M), lg(N), lg(K)};
+    const double q[3] = {ptune_log2_size(M), ptune_log2_size(N), ptune_log2_size(K)};
     d.resize(ntrain);
-    for (int i = 0; i < ntrain; ++i)
-        d[i] = std::fabs(q[0] - lg(train_mnk[3 * i])) + std::fabs(q[1] - lg(train_mnk[3 * i + 1])) +
-               std::fabs(q[2] - lg(train_mnk[3 * i + 2]));
+    for (int i = 0; i < ntrain; ++i) {
+        double t[3];
+        for (int c = 0; c < 3; ++c) t[c] = train_lg ? train_lg[3 * i + c] : ptune_log2_size(train_mnk[3 * i + c]);
+        d[i] = std::fabs(q[0] - t[0]) + std::fabs(q[1] - t[1]) + std::fabs(q[2] - t[2]);
+    }
 }
 
 }  // namespace
@@ -614,7 +619,7 @@ FF_EXPORT int ptune_nearest(int ntrain, const int64_t* train_mnk, int64_t M, int
 {
     if (ntrain < 1 || train_mnk == nullptr) return FF_ERR_ARG;
     std::vector<double> d;
-    shape_distances(ntrain, train_mnk, M, N, K, d);
+    shape_distances(ntrain, train_mnk, nullptr, M, N, K, d);
     int best = 0;
     for (int i = 1; i < ntrain; ++i)
         if (d[i] < d[best]) best = i;
@@ -628,11 +633,12 @@ double ptune_log_wave_efficiency(int64_t groups, int cus)
     return std::log((double)groups / (double)(waves * cus));
 }
 
-int ptune_dispatch_lw(int ntrain, const int64_t* train_mnk, int k, const int* members, const double* cost,
-                      const double* lw_train, const double* lw_query, int64_t M, int64_t N, int64_t K)
+int ptune_dispatch_lw(int ntrain, const int64_t* train_mnk, const double* train_lg, int k, const int* members,
+                      const double* cost, const double* lw_train, const double* lw_query, int64_t M, int64_t N,
+                      int64_t K)
 {
     std::vector<double> d;
-    shape_distances(ntrain, train_mnk, M, N, K, d);
+    shape_distances(ntrain, train_mnk, train_lg, M, N, K, d);
     const double dmin = *std::min_element(d.begin(), d.end());
     int bj = -1;
     double bs = kInf;
@@ -666,9 +672,9 @@ FF_EXPORT int ptune_dispatch(int ntrain, const int64_t* train_mnk, int k, const 
 {
     if (ntrain < 1 || train_mnk == nullptr || k < 1 || members == nullptr || cost == nullptr) return FF_ERR_ARG;
     const bool waves = groups_train != nullptr && groups_query != nullptr && cus >= 1;
-    if (!waves) return ptune_dispatch_lw(ntrain, train_mnk, k, members, cost, nullptr, nullptr, M, N, K);
+    if (!waves) return ptune_dispatch_lw(ntrain, train_mnk, nullptr, k, members, cost, nullptr, nullptr, M, N, K);
     std::vector<double> lt((size_t)ntrain * k), lq(k);
     for (size_t x = 0; x < lt.size(); ++x) lt[x] = ptune_log_wave_efficiency(groups_train[x], cus);
     for (int j = 0; j < k; ++j) lq[j] = ptune_log_wave_efficiency(groups_query[j], cus);
-    return ptune_dispatch_lw(ntrain, train_mnk, k, members, cost, lt.data(), lq.data(), M, N, K);
+    return ptune_dispatch_lw(ntrain, train_mnk, nullptr, k, members, cost, lt.data(), lq.data(), M, N, K);
 }

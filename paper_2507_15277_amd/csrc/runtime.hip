@@ -11,6 +11,7 @@
 
 #include <algorithm>
 #include <array>
+#include <atomic>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -78,7 +79,7 @@ bool parse_descriptor(std::istringstream& is, Variant& v)
         v.wn <= 0 || v.sk <= 0 || (v.vw != 1 && v.vw != 2 && v.vw != 4) || (v.lds != 0 && v.lds != 1) ||
         v.gm <= 0 || v.sg < 1 || v.sg > 64 || v.prec < 0 || v.prec > 3 || v.threads() > 1024)
         return false;
-    if (v.prec > 0 && (v.sk != 1 || v.sg != 1 || v.lds != 1)) return false;
+    if (v.prec > 0 && (v.sk != 1 || v.lds != 1)) return false;
     for (char c : v.name)
         if (!(isalnum((unsigned char)c) || c == '_')) return false;
     return true;
@@ -96,6 +97,7 @@ struct VarSet {
     // launch on every training shape (ntrain x k).
     int dev = -1, cus = 0;
     std::vector<double> lw_train;
+    std::vector<double> train_lg;                // log2 sizes of the training shapes
 };
 
 constexpr int kForms = 4;
@@ -361,7 +363,7 @@ float* current_workspace()
 int split_count(const Variant& v, int64_t M, int64_t N, int64_t K, bool have_ws)
 {
     const int64_t nkt = (K + v.kwg - 1) / v.kwg;
-    if (!(v.sg > 1 && nkt > 1 && v.prec == 0 && have_ws)) return 1;
+    if (!(v.sg > 1 && nkt > 1 && have_ws)) return 1;
     const int64_t nb = ((M + v.mwg - 1) / v.mwg) * ((N + v.nwg - 1) / v.nwg);
     int64_t sp = std::min<int64_t>(v.sg, nkt);
     sp = std::min<int64_t>(sp, (int64_t)(kWsBytes / (size_t)(M * N * 4)));
@@ -622,12 +624,21 @@ FF_EXPORT int variant_info(int id, char* buf, size_t len)
 //                          lines): its winner, a member, and every member's
 //                          log-slowdown on it ("inf" where it failed)
 //   end
+// Current device and its compute-unit count (queried once per device: the
+// attribute query costs more than the rest of a dispatch).
+static std::atomic<int> g_cus[kMaxDevices];
+
 static int device_cus(int& dev, int& cus)
 {
     hipError_t e = hipGetDevice(&dev);
-    if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    if (dev < 0 || dev >= kMaxDevices) return fail(FF_ERR_ARG, "device %d beyond the supported %d", dev, kMaxDevices);
+    cus = g_cus[dev].load(std::memory_order_relaxed);
+    if (cus > 0) return FF_OK;
+    e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
     if (e != hipSuccess) return hip_fail(e, "query compute units");
     if (cus < 1) return fail(FF_ERR_HIP, "device reports %d compute units", cus);
+    g_cus[dev].store(cus, std::memory_order_relaxed);
     return FF_OK;
 }
 
@@ -640,6 +651,8 @@ static int wave_table(VarSet& set)
     const bool ws = current_workspace() != nullptr;
     const size_t k = set.members.size();
     set.lw_train.assign(set.shapes.size() * k, 0.0);
+    set.train_lg.clear();
+    for (int64_t x : set.flat) set.train_lg.push_back(ptune_log2_size(x));
     for (size_t i = 0; i < set.shapes.size(); ++i)
         for (size_t j = 0; j < k; ++j) {
             const auto& s = set.shapes[i];
@@ -787,8 +800,8 @@ FF_EXPORT int variant_select_form(int form, int64_t M, int64_t N, int64_t K)
             }
         lt = lt_other.data();
     }
-    const int id = ptune_dispatch_lw((int)set->shapes.size(), set->flat.data(), (int)k, set->ids.data(),
-                                     set->cost.data(), lt, lq, M, N, K);
+    const int id = ptune_dispatch_lw((int)set->shapes.size(), set->flat.data(), set->train_lg.data(), (int)k,
+                                     set->ids.data(), set->cost.data(), lt, lq, M, N, K);
     if (id < 0) return fail(FF_ERR_NO_SET, "variant set has no training shapes");
     return id;
 }

@@ -23,8 +23,15 @@
 // Compile-time parameters: FF_MWG, FF_NWG (work-group tile), FF_KWG (slab
 // depth, a multiple of the MFMA k: 16 for MI 32, 32 for MI 16), FF_MI
 // (MFMA block edge 32 or 16), FF_WM x FF_WN (wave grid), FF_PREC, FF_GM
-// (tile-order group height), FF_NAME (kernel symbol; FF_NAME##_v1 is the
-// scalar-load kernel of the same configuration).
+// (tile-order group height), FF_SG (largest number of work-groups that
+// split one tile's K range; 1: no split), FF_NAME (kernel symbol;
+// FF_NAME##_v1 is the scalar-load kernel of the same configuration).
+//
+// With the K range split over work-groups (splits > 1, at most FF_SG), each
+// work-group takes a contiguous range of slabs and writes its raw partial
+// product (after the FP16 form's exact unscale) to its split's M x N slice
+// of the workspace; the runtime's reduction adds the slices in split order
+// and applies alpha and beta, as for the FP32 variants.
 //
 // Data flow: each slab of A (M rows, 8 consecutive k per item) and of B (8
 // consecutive k of one column per item; consecutive threads take
@@ -51,6 +58,9 @@
 #define FF_GM 8
 #define FF_NAME sgemmx_bf16x3_m128n128k32_i32_w2x2
 #endif
+#ifndef FF_SG
+#define FF_SG 1
+#endif
 
 #define FF_CAT2(a, b) a##b
 #define FF_CAT(a, b) FF_CAT2(a, b)
@@ -58,7 +68,7 @@
 namespace {
 
 constexpr int MWG = FF_MWG, NWG = FF_NWG, KWG = FF_KWG, MI = FF_MI;
-constexpr int WM = FF_WM, WN = FF_WN, PREC = FF_PREC, GM = FF_GM;
+constexpr int WM = FF_WM, WN = FF_WN, PREC = FF_PREC, GM = FF_GM, SG = FF_SG;
 constexpr int TERMS = PREC == 1 ? 2 : (PREC == 2 ? 3 : 1);
 constexpr int KB = 8 * (64 / MI);        // MFMA k depth: 16 (MI 32) or 32 (MI 16)
 constexpr int WTM = MWG / WM, WTN = NWG / WN;
@@ -79,6 +89,7 @@ static_assert(MI == 32 || MI == 16, "MFMA block edge");
 static_assert(MWG % (WM * MI) == 0 && NWG % (WN * MI) == 0, "tile must split into MFMA blocks");
 static_assert(KWG % KB == 0, "slab depth must be a multiple of the MFMA k");
 static_assert(NT <= 1024, "work-group size");
+static_assert(SG >= 1, "split count");
 
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
@@ -132,12 +143,18 @@ __device__ __forceinline__ void split8(const float (&x)[8], float scale, i16x8 (
     }
 }
 
-__device__ __forceinline__ void tile_of(int bid, int nbm, int nbn, int& tm, int& tn)
+// Work-group index -> (tile row, tile column, K split): work-groups are
+// dealt to the 8 XCDs round-robin and renumbered so that each XCD owns a
+// contiguous range (the splits of one tile, then neighbouring tiles in
+// groups of GM tile rows).
+__device__ __forceinline__ void tile_of(int bid, int nbm, int nbn, int splits, int& tm, int& tn, int& part)
 {
-    const int nb = nbm * nbn;
+    const int nb = nbm * nbn * splits;
     const int q = nb >> 3, r = nb & 7;
     const int x = bid & 7, i = bid >> 3;
-    const int lin = (x < r) ? x * (q + 1) + i : r * (q + 1) + (x - r) * q + i;
+    const int lin2 = (x < r) ? x * (q + 1) + i : r * (q + 1) + (x - r) * q + i;
+    const int lin = lin2 / splits;
+    part = lin2 - lin * splits;
     const int width = GM * nbn;
     const int grp = lin / width;
     const int first = grp * GM;
@@ -157,11 +174,12 @@ constexpr int NPAIRS = PREC == 1 ? 3 : (PREC == 2 ? 6 : 1);
 template <bool VEC>
 __device__ __forceinline__ void body(int M, int N, int K, float alpha, const float* __restrict__ A, long lda,
                                      const float* __restrict__ B, long ldb, float beta, float* __restrict__ C,
-                                     long ldc, const float* __restrict__ prescale, short* smem)
+                                     long ldc, float* __restrict__ ws, int splits, int kper,
+                                     const float* __restrict__ prescale, short* smem)
 {
     const int nbm = (M + MWG - 1) / MWG, nbn = (N + NWG - 1) / NWG;
-    int tm, tn;
-    tile_of(blockIdx.x, nbm, nbn, tm, tn);
+    int tm, tn, part;
+    tile_of(blockIdx.x, nbm, nbn, SG > 1 ? splits : 1, tm, tn, part);
     const int m0 = tm * MWG, n0 = tn * NWG;
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
     const int wm = wid / WN, wn = wid % WN;
@@ -185,7 +203,10 @@ __device__ __forceinline__ void body(int M, int N, int K, float alpha, const flo
     constexpr int NA = MWG * KC, NB = NWG * KC;
     constexpr int LA = (NA + NT - 1) / NT, LB = (NB + NT - 1) / NT;
     float ra[LA][8], rb[LB][8];
+    // This work-group's slabs [kt0, kt1): all of K unless the tile is split.
     const int nkt = (K + KWG - 1) / KWG;
+    const int kt0 = (SG > 1) ? part * kper : 0;
+    const int kt1 = (SG > 1) ? min(nkt, kt0 + kper) : nkt;
 
     // Loads read clamped addresses and keep raw values; validity is
     // recomputed and applied when the slab is split into LDS, so the loads of
@@ -265,14 +286,14 @@ __device__ __forceinline__ void body(int M, int N, int K, float alpha, const flo
         }
     };
 
-    gload(0);
-    sstore(0, 0);
+    gload(kt0);
+    sstore(0, kt0);
     __syncthreads();
     const int arow = (wm * WTM + lr) * LDK + lh * 8;
     const int bcol = (wn * WTN + lr) * LDK + lh * 8;
-    for (int kt = 0; kt < nkt; ++kt) {
-        const int st = kt & 1;
-        if (kt + 1 < nkt) gload(kt + 1);
+    for (int kt = kt0; kt < kt1; ++kt) {
+        const int st = (kt - kt0) & 1;
+        if (kt + 1 < kt1) gload(kt + 1);
         const short* sA = smem + st * STAGE;
         const short* sB = sA + TERMS * A_TERM;
 #pragma unroll
@@ -296,12 +317,21 @@ __device__ __forceinline__ void body(int M, int N, int K, float alpha, const flo
                     for (int j = 0; j < RN; ++j) acc[i][j] = mfma16(bv[pr.b][j], av[pr.a][i], acc[i][j]);
             }
         }
-        if (kt + 1 < nkt) sstore(st ^ 1, kt + 1);
+        if (kt + 1 < kt1) sstore(st ^ 1, kt + 1);
         __syncthreads();
     }
 
     // Epilogue as in the FP32 kernel; the FP16 form first removes its
-    // prescale (a power of two, exact).
+    // prescale (a power of two, exact).  A split tile writes its raw partial
+    // to its slice of the workspace (alpha 1, beta 0).
+    if constexpr (SG > 1) {
+        if (splits > 1) {
+            C = ws + (size_t)part * (size_t)M * (size_t)N;
+            ldc = N;
+            alpha = 1.0f;
+            beta = 0.0f;
+        }
+    }
     const bool cvec = ((reinterpret_cast<uintptr_t>(C) & 15) == 0) && ((ldc & 3) == 0);
     const bool use_beta = (beta != 0.0f);
 #pragma unroll
@@ -338,18 +368,15 @@ __device__ __forceinline__ void body(int M, int N, int K, float alpha, const flo
 
 }  // namespace
 
-// Same argument list as the FP32 variants; `ws`, `splits` and `kper` are
-// unused here, `prescale` (FP16 form only) points to {2^eA, 2^eB, 2^-(eA+eB)}.
+// Same argument list as the FP32 variants; `prescale` (FP16 form only)
+// points to {2^eA, 2^eB, 2^-(eA+eB)}.
 extern "C" __global__ void __launch_bounds__(NT)
 FF_NAME(int M, int N, int K, float alpha, const float* __restrict__ A, long lda, const float* __restrict__ B,
         long ldb, float beta, float* __restrict__ C, long ldc, float* __restrict__ ws, int splits, int kper,
         const float* __restrict__ prescale)
 {
-    (void)ws;
-    (void)splits;
-    (void)kper;
     __shared__ __attribute__((aligned(16))) short smem[LDS_ELEMS];
-    body<true>(M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, prescale, smem);
+    body<true>(M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, ws, splits, kper, prescale, smem);
 }
 
 extern "C" __global__ void __launch_bounds__(NT)
@@ -357,9 +384,6 @@ FF_CAT(FF_NAME, _v1)(int M, int N, int K, float alpha, const float* __restrict__
                      const float* __restrict__ B, long ldb, float beta, float* __restrict__ C, long ldc,
                      float* __restrict__ ws, int splits, int kper, const float* __restrict__ prescale)
 {
-    (void)ws;
-    (void)splits;
-    (void)kper;
     __shared__ __attribute__((aligned(16))) short smem[LDS_ELEMS];
-    body<false>(M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, prescale, smem);
+    body<false>(M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, ws, splits, kper, prescale, smem);
 }

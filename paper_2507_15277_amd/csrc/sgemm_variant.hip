@@ -283,29 +283,36 @@ __device__ __forceinline__ void tile_gemm(int M, int N, int K, float alpha,
 
         const int arow0 = (wm * WTM + lr) * LDA_S + kg0;
         const int bcol0 = wn * WTN + lr;
+        // One slab from LDS: the steps go in chunks of AV (one A vector read
+        // per MFMA row block); the fragments of chunk q + 1 are read while
+        // the MFMAs of chunk q run, so LDS latency overlaps matrix work.
         auto compute = [&](int st) {
             const float* sA = sA0 + st * STAGE_FLOATS;
             const float* sB = sB0 + st * STAGE_FLOATS;
-#pragma unroll
-            for (int q = 0; q < S / AV; ++q) {
-                typename VecT<AV>::T av[RM];
+            typedef typename VecT<AV>::T avt;
+            avt av[2][RM];
+            float bv[2][AV][RN];
+            auto fragments = [&](int q, int buf) {
 #pragma unroll
                 for (int i = 0; i < RM; ++i)
-                    av[i] = *reinterpret_cast<const typename VecT<AV>::T*>(
-                        sA + arow0 + i * MI * LDA_S + q * AV);
+                    av[buf][i] = *reinterpret_cast<const avt*>(sA + arow0 + i * MI * LDA_S + q * AV);
 #pragma unroll
-                for (int t = 0; t < AV; ++t) {
-                    const int s = q * AV + t;
-                    float bv[RN];
+                for (int t = 0; t < AV; ++t)
 #pragma unroll
                     for (int j = 0; j < RN; ++j)
-                        bv[j] = sB[(kg0 + s) * LDB_S + bcol0 + j * MI];
+                        bv[buf][t][j] = sB[(kg0 + q * AV + t) * LDB_S + bcol0 + j * MI];
+            };
+            fragments(0, 0);
+#pragma unroll
+            for (int q = 0; q < S / AV; ++q) {
+                if (q + 1 < S / AV) fragments(q + 1, (q + 1) & 1);
+#pragma unroll
+                for (int t = 0; t < AV; ++t)
 #pragma unroll
                     for (int i = 0; i < RM; ++i)
 #pragma unroll
                         for (int j = 0; j < RN; ++j)
-                            acc[i][j] = mfma(bv[j], vget<AV>(av[i], t), acc[i][j]);
-                }
+                            acc[i][j] = mfma(bv[q & 1][t][j], vget<AV>(av[q & 1][i], t), acc[i][j]);
             }
         };
 
@@ -328,21 +335,39 @@ __device__ __forceinline__ void tile_gemm(int M, int N, int K, float alpha,
             // clamped safe address and are never staged): a conditional load
             // makes the compiler wait for all loads before the next LDS store,
             // which would take the second slab of prefetch away.
+            // The last one or two slabs are peeled off so that every trip of
+            // the steady loop stages both of its successors: with a stage
+            // under a branch, the compiler's wait counts merge over the
+            // path that skips it and it waits for all loads at the top of
+            // the loop.
             gload(kt0, 0);
             gload(kt0 + 1, 1);
             sstore(0, 0);
             __syncthreads();
-            for (int kt = kt0; kt < kt1; kt += 2) {
-#pragma unroll
-                for (int b = 0; b < 2; ++b) {
-                    if (kt + b < kt1) {
-                        gload(kt + b + 2, b);
-                        compute(b);
-                        if (kt + b + 1 < kt1) sstore(b ^ 1, b ^ 1);
-                        __syncthreads();
-                    }
-                }
+            // A scheduling barrier keeps each stage after its MFMAs: without
+            // it the (branch-free) loop lets the scheduler hoist the stage's
+            // selects and stores above the MFMAs, which then wait on loads
+            // issued a moment earlier.
+            int kt = kt0;
+            for (; kt + 2 < kt1; kt += 2) {
+                gload(kt + 2, 0);
+                compute(0);
+                __builtin_amdgcn_sched_barrier(0);
+                sstore(1, 1);
+                __syncthreads();
+                gload(kt + 3, 1);
+                compute(1);
+                __builtin_amdgcn_sched_barrier(0);
+                sstore(0, 0);
+                __syncthreads();
             }
+            compute(0);
+            if (kt + 1 < kt1) {
+                sstore(1, 1);
+                __syncthreads();
+                compute(1);
+            }
+            __syncthreads();
         }
     } else {
         // ---- direct loads: every wave fetches its own operands -------------

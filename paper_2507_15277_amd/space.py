@@ -95,7 +95,8 @@ class Variant:
     def name(self):
         if self.prec:
             form = PREC_NAMES[self.prec]
-            return f"sgemmx_{form}_m{self.mwg}n{self.nwg}k{self.kwg}_i{self.mi}_w{self.wm}x{self.wn}"
+            n = f"sgemmx_{form}_m{self.mwg}n{self.nwg}k{self.kwg}_i{self.mi}_w{self.wm}x{self.wn}"
+            return n + (f"_p{self.sg}" if self.sg != 1 else "")
         n = (f"sgemm_m{self.mwg}n{self.nwg}k{self.kwg}_i{self.mi}_w{self.wm}x{self.wn}"
              f"_s{self.sk}_v{self.vw}_l{self.lds}")
         if self.gm != 8:
@@ -110,7 +111,7 @@ class Variant:
         if self.prec:
             return {"FF_MWG": self.mwg, "FF_NWG": self.nwg, "FF_KWG": self.kwg, "FF_MI": self.mi,
                     "FF_WM": self.wm, "FF_WN": self.wn, "FF_PREC": self.prec, "FF_GM": self.gm,
-                    "FF_NAME": self.name}
+                    "FF_SG": self.sg, "FF_NAME": self.name}
         return {"FF_MWG": self.mwg, "FF_NWG": self.nwg, "FF_KWG": self.kwg, "FF_MI": self.mi,
                 "FF_WM": self.wm, "FF_WN": self.wn, "FF_SK": self.sk, "FF_VW": self.vw,
                 "FF_LDS": self.lds, "FF_GM": self.gm, "FF_SG": self.sg, "FF_PD": self.pd,
@@ -125,7 +126,7 @@ class Variant:
             return 0
         nb = -(-M // self.mwg) * -(-N // self.nwg)
         nkt = -(-K // self.kwg)
-        if self.sg > 1 and nkt > 1 and self.prec == 0 and have_ws:
+        if self.sg > 1 and nkt > 1 and have_ws:
             sp = min(self.sg, nkt, WORKSPACE_BYTES // (M * N * 4))
             if sp >= 2 and nb * sp <= 2**31 - 1:
                 per = -(-nkt // sp)
@@ -147,7 +148,7 @@ MAX_SPLIT_LDS_BYTES = 160 * 1024
 
 def legal_split(v: Variant) -> bool:
     """Constraints of the split-precision kernel (csrc/sgemm_split.hip)."""
-    if v.mi not in (16, 32) or v.sk != 1 or v.sg != 1 or v.lds != 1 or v.vw != 4 or v.pd != 1:
+    if v.mi not in (16, 32) or v.sk != 1 or v.sg not in SPLITS or v.lds != 1 or v.vw != 4 or v.pd != 1:
         return False
     if v.mwg % (v.wm * v.mi) or v.nwg % (v.wn * v.mi) or v.kwg % v.mk:
         return False
@@ -325,11 +326,29 @@ SPLIT_SHAPES = [
 ]
 
 
+# Split-precision shapes with the K range split over work-groups, for the
+# shapes with few tiles and long K.  (MWG, NWG, KWG, MI, WM, WN, SG)
+SPLIT_K_SHAPES = [
+    (64, 64, 32, 32, 2, 2, 4),
+    (64, 64, 64, 32, 2, 2, 8),
+    (128, 128, 32, 32, 2, 2, 4),
+    (32, 32, 64, 32, 1, 1, 8),
+    (32, 32, 32, 16, 2, 2, 4),
+    (64, 64, 32, 16, 2, 2, 8),
+]
+
+
 def split_family(precs=(1, 2, 3)):
     out = []
     for prec in precs:
         for (mwg, nwg, kwg, mi, wm, wn) in SPLIT_SHAPES:
             v = Variant(mwg, nwg, kwg, mi, wm, wn, 1, 4, 1, 8, 1, prec)
+            if legal(v):
+                out.append(v)
+    # Appended after all forms' plain shapes, so earlier ids stay put.
+    for prec in precs:
+        for (mwg, nwg, kwg, mi, wm, wn, sg) in SPLIT_K_SHAPES:
+            v = Variant(mwg, nwg, kwg, mi, wm, wn, 1, 4, 1, 8, sg, prec)
             if legal(v):
                 out.append(v)
     return out
