@@ -366,7 +366,7 @@ int split_count(const Variant& v, int64_t M, int64_t N, int64_t K, bool have_ws)
     if (!(v.sg > 1 && nkt > 1 && have_ws)) return 1;
     const int64_t nb = ((M + v.mwg - 1) / v.mwg) * ((N + v.nwg - 1) / v.nwg);
     int64_t sp = std::min<int64_t>(v.sg, nkt);
-    sp = std::min<int64_t>(sp, (int64_t)(kWsBytes / (size_t)(M * N * 4)));
+    sp = std::min<int64_t>(sp, (int64_t)(kWsBytes / 4) / (M * N));   // slices that fit the workspace
     if (sp < 2 || nb * sp > INT32_MAX) return 1;
     const int64_t per = (nkt + sp - 1) / sp;
     return (int)((nkt + per - 1) / per);
@@ -612,18 +612,6 @@ FF_EXPORT int variant_info(int id, char* buf, size_t len)
     return n;
 }
 
-// Set file format (text, '#' comments):
-//   fewfit-set 1
-//   arch <gfx name>
-//   codedir <dir>          code objects, relative to the set file's directory
-//   form <name>            optional: fp32 (default), bf16x3, bf16x6 or fp16s;
-//                          every member must be of that form
-//   variant <descriptor>   k lines, descriptor as in the manifest
-//   rule <M> <N> <K> <id> <c_1> ... <c_k>
-//                          one line per training shape (after the variant
-//                          lines): its winner, a member, and every member's
-//                          log-slowdown on it ("inf" where it failed)
-//   end
 // Current device and its compute-unit count (queried once per device: the
 // attribute query costs more than the rest of a dispatch).
 static std::atomic<int> g_cus[kMaxDevices];
@@ -662,6 +650,18 @@ static int wave_table(VarSet& set)
     return FF_OK;
 }
 
+// Set file format (text, '#' comments):
+//   fewfit-set 1
+//   arch <gfx name>
+//   codedir <dir>          code objects, relative to the set file's directory
+//   form <name>            optional: fp32 (default), bf16x3, bf16x6 or fp16s;
+//                          every member must be of that form
+//   variant <descriptor>   k lines, descriptor as in the manifest
+//   rule <M> <N> <K> <id> <c_1> ... <c_k>
+//                          one line per training shape (after the variant
+//                          lines): its winner, a member, and every member's
+//                          log-slowdown on it ("inf" where it failed)
+//   end
 FF_EXPORT int variant_set_load(const char* path)
 {
     if (path == nullptr) return fail(FF_ERR_ARG, "variant_set_load: path is NULL");
