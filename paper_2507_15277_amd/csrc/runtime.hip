@@ -76,7 +76,7 @@ bool parse_descriptor(std::istringstream& is, Variant& v)
         return false;
     if (v.pd < 1 || v.pd > 2) return false;
     if (v.id < 0 || v.mwg <= 0 || v.nwg <= 0 || v.kwg <= 0 || (v.mi != 16 && v.mi != 32) || v.wm <= 0 ||
-        v.wn <= 0 || v.sk <= 0 || (v.vw != 1 && v.vw != 2 && v.vw != 4) || (v.lds != 0 && v.lds != 1) ||
+        v.wn <= 0 || v.sk <= 0 || (v.vw != 1 && v.vw != 2 && v.vw != 4) || v.lds < 0 || v.lds > 2 || (v.lds == 2 && v.vw != 4) ||
         v.gm <= 0 || v.sg < 1 || v.sg > 64 || v.prec < 0 || v.prec > 3 || v.threads() > 1024)
         return false;
     if (v.prec > 0 && (v.sk != 1 || v.lds != 1)) return false;

@@ -22,6 +22,12 @@
 //                    waves; 0: each wave loads its own operands straight from
 //                    global memory into registers (no LDS, no barriers)
 //   FF_GM            tile-order group height (tiles of M per group)
+//                    (FF_LDS 2: slabs are copied from global memory straight
+//                    into LDS by the load-to-LDS instruction, each lane one
+//                    16-byte unit of the padded slab image, with PD + 1 LDS
+//                    stages in flight; no register staging.  Needs the
+//                    vector kernel's conditions; the scalar-load kernel of
+//                    the same code object stages through registers.)
 //   FF_PD            LDS variants: prefetch depth in slabs (1: the next
 //                    slab's global loads are in flight while the current one
 //                    is computed; 2: the one after next, through a second
@@ -85,6 +91,7 @@ namespace {
 constexpr int MWG = FF_MWG, NWG = FF_NWG, KWG = FF_KWG, MI = FF_MI;
 constexpr int WM = FF_WM, WN = FF_WN, SK = FF_SK, VW = FF_VW, GM = FF_GM, SG = FF_SG, PD = FF_PD;
 constexpr bool USE_LDS = FF_LDS != 0;
+constexpr bool DMA = FF_LDS == 2;        // load-to-LDS staging (vector kernel only)
 
 constexpr int MK = (MI == 32) ? 2 : 4;   // k per MFMA instruction
 constexpr int WTM = MWG / WM;            // wave sub-tile rows
@@ -106,7 +113,20 @@ constexpr int LDA_S = KWG + PA;          // LDS row stride of the A slab [m][k]
 constexpr int LDB_S = NWG + PB;          // LDS row stride of the B slab [k][n]
 constexpr int STAGE_FLOATS = MWG * LDA_S + KWG * LDB_S;
 constexpr int RED_FLOATS = (SK - 1) * MWG * NWG;
-constexpr int LDS_FLOATS = USE_LDS ? (2 * STAGE_FLOATS > RED_FLOATS ? 2 * STAGE_FLOATS : RED_FLOATS)
+
+// Load-to-LDS staging: a stage is the padded slab image (A then B) rounded
+// up to whole wave copies of 64 x 16 bytes; the wave copies of a stage are
+// dealt to the waves round-robin, DPS per wave (the surplus copies of the
+// last round land in a 1 KB scratch area after the stages), so every wave
+// issues the same number of copies per slab and the wait counts are exact.
+constexpr int NS = PD + 1;                               // LDS stages in flight
+constexpr int STAGE_UNITS = (STAGE_FLOATS / 4 + 63) / 64 * 64;   // 16-byte units
+constexpr int STAGE_DMA = STAGE_UNITS * 4;               // floats per stage
+constexpr int NWI = STAGE_UNITS / 64;                    // wave copies per stage
+constexpr int DPS = (NWI + NWAVE - 1) / NWAVE;           // copies per wave per slab
+constexpr int STAGE_STRIDE = DMA ? STAGE_DMA : STAGE_FLOATS;
+constexpr int STAGE_AREA = DMA ? NS * STAGE_DMA + 256 : 2 * STAGE_FLOATS;
+constexpr int LDS_FLOATS = USE_LDS ? (STAGE_AREA > RED_FLOATS ? STAGE_AREA : RED_FLOATS)
                                    : (RED_FLOATS > 0 ? RED_FLOATS : 1);
 
 static_assert(MI == 32 || MI == 16, "MFMA block edge must be 16 or 32");
@@ -117,6 +137,9 @@ static_assert(NT <= 1024, "work-group size");
 static_assert(KWG % 4 == 0 && NWG % 4 == 0, "LDS vector alignment");
 static_assert(SG >= 1, "split count");
 static_assert(PD == 1 || PD == 2, "prefetch depth");
+static_assert(FF_LDS >= 0 && FF_LDS <= 2, "LDS staging mode");
+static_assert(!DMA || VW == 4, "load-to-LDS staging moves 16-byte units");
+static_assert(!DMA || (NS - 2) * DPS <= 63, "wait count range");
 
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
@@ -190,6 +213,118 @@ __device__ __forceinline__ void tile_of(int bid, int nbm, int nbn, int splits, i
     tn = w / gsz;
 }
 
+// s_waitcnt immediate (gfx9 encoding): at most `vm` vector-memory operations
+// outstanding, no LDS/scalar-memory operations outstanding, exports untouched.
+constexpr int waitcnt_vm(int vm) { return (vm & 15) | (((vm >> 4) & 3) << 14) | (7 << 4); }
+
+typedef __attribute__((address_space(3))) void* lds_ptr;
+
+// Slabs [kt0, kt1) of one tile through load-to-LDS copies, NS stages deep,
+// calling compute(stage) for each.  Unit u of a stage (16 bytes) holds floats
+// 4u..4u+3 of the padded slab image: A rows of LDA_S floats, then B rows of
+// LDB_S floats; units in the row padding or past the image copy from a safe
+// address.  Rows past M and columns past N copy a clamped row or column:
+// they only reach C rows and columns that are never stored.  Units past K
+// also copy a clamped address and are zeroed in LDS before the slab is used,
+// so the tail slab contributes exact zeros.  Needs K, N, lda, ldb multiples
+// of 4 and 16-byte aligned A and B (the vector kernel's conditions).
+template <typename Compute>
+__device__ __forceinline__ void dma_slabs(int M, int N, int K, const float* __restrict__ A, long lda,
+                                          const float* __restrict__ B, long ldb, int m0, int n0, int kt0,
+                                          int kt1, int wid, int lane, float* smem, Compute&& compute)
+{
+    constexpr int UA = MWG * LDA_S / 4, UB = KWG * LDB_S / 4;
+    constexpr int RA = LDA_S / 4, RB = LDB_S / 4;        // units per LDS row
+    // Per copy slot: the unit's source without the slab's k offset, its k
+    // within the slab, and the source step per unit of k (1 along an A row,
+    // ldb down the B rows, 0 for padding units, which copy from A itself).
+    const float* base[DPS];
+    int kl[DPS];
+    long step[DPS];
+#pragma unroll
+    for (int j = 0; j < DPS; ++j) {
+        const int wi = wid + j * NWAVE;
+        const int u = wi * 64 + lane;
+        base[j] = A;
+        kl[j] = 0;
+        step[j] = 0;
+        if (wi < NWI && u < UA) {
+            const int row = u / RA, c = u % RA;
+            if (c < KWG / 4) {
+                base[j] = A + (long)min(m0 + row, M - 1) * lda;
+                kl[j] = 4 * c;
+                step[j] = 1;
+            }
+        } else if (wi < NWI && u < UA + UB) {
+            const int v = u - UA;
+            const int row = v / RB, c = v % RB;
+            if (c < NWG / 4) {
+                base[j] = B + min(n0 + 4 * c, N - 4);
+                kl[j] = row;
+                step[j] = ldb;
+            }
+        }
+    }
+    auto issue = [&](int kt, int st) {
+        const int kb = kt * KWG;
+#pragma unroll
+        for (int j = 0; j < DPS; ++j) {
+            const int wi = wid + j * NWAVE;
+            const int k = kb + kl[j];
+            const float* src = base[j] + ((k < K) ? (long)k * step[j] : 0L);
+            float* dst = (wi < NWI) ? smem + st * STAGE_DMA + wi * 256 : smem + NS * STAGE_DMA;
+            __builtin_amdgcn_global_load_lds(src, (lds_ptr)dst, 16, 0, 0);
+        }
+    };
+    // Zero the k >= K part of a tail slab's A columns and B rows.
+    auto zero_tail = [&](int kt, int st) {
+        const int kv = K - kt * KWG;                     // valid k in this slab, 0 < kv < KWG
+        float* sA = smem + st * STAGE_DMA;
+        float* sB = sA + MWG * LDA_S;
+        const int tid = wid * 64 + lane;
+        for (int e = tid; e < MWG * (KWG - kv); e += NT) {
+            const int r = e / (KWG - kv), c = kv + e % (KWG - kv);
+            sA[r * LDA_S + c] = 0.0f;
+        }
+        for (int e = tid; e < (KWG - kv) * NWG; e += NT) {
+            const int r = kv + e / NWG, c = e % NWG;
+            sB[r * LDB_S + c] = 0.0f;
+        }
+    };
+
+#pragma unroll
+    for (int p = 0; p < NS - 1; ++p)
+        if (kt0 + p < kt1) issue(kt0 + p, p);
+    int st = 0;
+    for (int kt = kt0; kt < kt1; ++kt) {
+        // This slab's copies are done when only the later slabs' copies may
+        // still be outstanding; then every wave's copies are (barrier), and
+        // every wave has finished the slab before (so its stage is free).
+        // (The empty asm statements keep the compiler from moving LDS
+        // accesses across the wait and barrier; a fenced barrier would also
+        // wait for the copies still in flight.)
+        asm volatile("" ::: "memory");
+        if (kt + NS - 2 < kt1)
+            __builtin_amdgcn_s_waitcnt(waitcnt_vm((NS - 2) * DPS));
+        else
+            __builtin_amdgcn_s_waitcnt(waitcnt_vm(0));
+        __builtin_amdgcn_s_barrier();
+        asm volatile("" ::: "memory");
+        if ((kt + 1) * KWG > K) {                        // tail slab (uniform)
+            zero_tail(kt, st);
+            __syncthreads();
+        }
+        if (kt + NS - 1 < kt1) {
+            int nx = st + NS - 1;
+            if (nx >= NS) nx -= NS;
+            issue(kt + NS - 1, nx);
+        }
+        compute(st);
+        if (++st == NS) st = 0;
+    }
+    __syncthreads();                                     // LDS reused by the caller
+}
+
 // One work-group computes tile (tm, tn) of C over slabs [kt0, kt1) of K
 // (split `part` of `splits` when the K range is split over work-groups).
 // Every wave reaches every barrier and no wave returns early, so the
@@ -261,8 +396,8 @@ __device__ __forceinline__ void tile_gemm(int M, int N, int K, float alpha,
             }
         };
         auto sstore = [&](int st, int rbuf) {
-            float* sA = sA0 + st * STAGE_FLOATS;
-            float* sB = sB0 + st * STAGE_FLOATS;
+            float* sA = sA0 + st * STAGE_STRIDE;
+            float* sB = sB0 + st * STAGE_STRIDE;
 #pragma unroll
             for (int i = 0; i < LA; ++i) {
                 const int v = tid + i * NT;
@@ -287,8 +422,8 @@ __device__ __forceinline__ void tile_gemm(int M, int N, int K, float alpha,
         // per MFMA row block); the fragments of chunk q + 1 are read while
         // the MFMAs of chunk q run, so LDS latency overlaps matrix work.
         auto compute = [&](int st) {
-            const float* sA = sA0 + st * STAGE_FLOATS;
-            const float* sB = sB0 + st * STAGE_FLOATS;
+            const float* sA = sA0 + st * STAGE_STRIDE;
+            const float* sB = sB0 + st * STAGE_STRIDE;
             typedef typename VecT<AV>::T avt;
             avt av[2][RM];
             float bv[2][AV][RN];
@@ -316,7 +451,9 @@ __device__ __forceinline__ void tile_gemm(int M, int N, int K, float alpha,
             }
         };
 
-        if constexpr (PD == 1) {
+        if constexpr (DMA && V == 4) {
+            dma_slabs(M, N, K, A, lda, B, ldb, m0, n0, kt0, kt1, wid, lane, smem, compute);
+        } else if constexpr (PD == 1) {
             gload(kt0, 0);
             sstore(0, 0);
             __syncthreads();

@@ -28,6 +28,7 @@ WORKSPACE_BYTES = 128 << 20  # per-device K-split workspace of the runtime
 MAX_ACC = 128            # accumulator floats per lane
 MAX_DIRECT_OPERANDS = 64  # double-buffered operand registers, direct loads
 MAX_LDS_BYTES = 80 * 1024  # keeps >= 2 work-groups per CU possible (160 KB LDS)
+MAX_DMA_LDS_BYTES = 160 * 1024  # load-to-LDS staging may fill the CU's LDS
 MAX_THREADS = 512
 MAX_STAGING = 64          # floats per thread held in flight between global loads and LDS
 
@@ -89,7 +90,19 @@ class Variant:
             return 2 * 2 * self.terms * (self.mwg + self.nwg) * (self.kwg + 8)
         stage = self.mwg * (self.kwg + 4) + self.kwg * (self.nwg + 4)
         red = (self.sk - 1) * self.mwg * self.nwg
+        if self.lds == 2:
+            # PD + 1 stages, each rounded up to whole 1 KB wave copies, plus
+            # 1 KB for the surplus copies.
+            stage_dma = -(-stage // 256) * 256
+            return 4 * max((self.pd + 1) * stage_dma + 256, red)
         return 4 * (max(2 * stage, red) if self.lds else max(red, 1))
+
+    @property
+    def dma_copies(self):
+        """Load-to-LDS copies per wave per slab (LDS mode 2)."""
+        stage = self.mwg * (self.kwg + 4) + self.kwg * (self.nwg + 4)
+        waves = self.wm * self.wn * self.sk
+        return -(-(-(-stage // 256)) // waves)
 
     @property
     def name(self):
@@ -164,15 +177,18 @@ def legal(v: Variant) -> bool:
     """Constraints of the kernel template plus resource budgets."""
     if v.prec:
         return legal_split(v)
-    if v.mi not in (16, 32) or v.vw not in (1, 2, 4) or v.lds not in (0, 1):
+    if v.mi not in (16, 32) or v.vw not in (1, 2, 4) or v.lds not in (0, 1, 2):
         return False
     if v.sg not in SPLITS or v.pd not in (1, 2) or (v.pd == 2 and not v.lds):
+        return False
+    if v.lds == 2 and (v.vw != 4 or (v.pd - 1) * v.dma_copies > 63):
         return False
     if v.mwg % (v.wm * v.mi) or v.nwg % (v.wn * v.mi):
         return False
     if v.kwg % (v.sk * v.mk) or v.kwg % 4 or v.nwg % 4:
         return False
-    if v.threads > MAX_THREADS or v.acc_regs > MAX_ACC or v.lds_bytes > MAX_LDS_BYTES:
+    lds_cap = MAX_DMA_LDS_BYTES if v.lds == 2 else MAX_LDS_BYTES
+    if v.threads > MAX_THREADS or v.acc_regs > MAX_ACC or v.lds_bytes > lds_cap:
         return False
     if max(v.mwg, v.nwg) > 4 * min(v.mwg, v.nwg):
         return False  # elongated tiles re-read the long operand too often
@@ -197,7 +213,7 @@ def enumerate_space():
     """All legal configurations, in a fixed order."""
     out = []
     for mi, mwg, nwg, kwg, wm, wn, sk, vw, lds, sg, pd in itertools.product(
-            (32, 16), TILES, TILES, KSTEPS, (1, 2, 4), (1, 2, 4), (1, 2, 4), (1, 2, 4), (1, 0),
+            (32, 16), TILES, TILES, KSTEPS, (1, 2, 4), (1, 2, 4), (1, 2, 4), (1, 2, 4), (1, 0, 2),
             SPLITS, (1, 2)):
         v = Variant(mwg, nwg, kwg, mi, wm, wn, sk, vw, lds, 8, sg, 0, pd)
         if legal(v):
@@ -277,6 +293,24 @@ HAND = [
     Variant(64, 128, 32, 16, 4, 2, 1, 4, 1, sg=4, pd=2),
     Variant(64, 128, 32, 32, 1, 4, 1, 4, 1, sg=4, pd=2),
     Variant(256, 128, 16, 32, 4, 2, 1, 4, 1, sg=2, pd=2),
+    # Load-to-LDS staging (LDS mode 2) for the frequent winners.
+    Variant(64, 64, 64, 32, 2, 2, 2, 4, 2),
+    Variant(64, 64, 64, 32, 2, 2, 2, 4, 2, pd=2),
+    Variant(64, 64, 32, 32, 2, 2, 2, 4, 2),
+    Variant(64, 64, 32, 32, 2, 2, 2, 4, 2, pd=2),
+    Variant(64, 64, 128, 32, 2, 2, 2, 4, 2),
+    Variant(32, 32, 128, 32, 1, 1, 4, 4, 2),
+    Variant(32, 32, 128, 32, 1, 1, 4, 4, 2, pd=2),
+    Variant(128, 128, 32, 32, 2, 2, 2, 4, 2),
+    Variant(128, 128, 32, 32, 2, 2, 2, 4, 2, pd=2),
+    Variant(128, 128, 64, 32, 2, 2, 2, 4, 2),
+    Variant(256, 128, 16, 32, 4, 2, 1, 4, 2),
+    Variant(256, 128, 16, 32, 4, 2, 1, 4, 2, pd=2),
+    Variant(256, 128, 32, 32, 4, 2, 1, 4, 2),
+    Variant(128, 256, 16, 32, 2, 4, 1, 4, 2, pd=2),
+    Variant(64, 64, 32, 32, 2, 2, 2, 4, 2, sg=8, pd=2),
+    Variant(16, 32, 128, 16, 1, 1, 4, 4, 2, sg=4),
+    Variant(64, 128, 32, 32, 1, 4, 1, 4, 2, pd=2),
 ]
 
 
