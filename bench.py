@@ -15,6 +15,13 @@ table, timed live beside the dispatched one), the roofline of the dominant
 kernel, and the FP64 oracle on the host cores as a CPU baseline.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--k 4] [--no-cpu-baseline]
+                    [--form fp32|bf16x3|bf16x6|fp16s]
+
+``--form`` other than fp32 runs the same protocol for a split-precision form
+(its own k-variant set, ``sgemm_form``) on the precision workload: the 27
+grid shapes with lognormal operands.  Its roofline is priced against the
+16-bit dense MFMA peak with the MFMA work the form issues (its number of
+term products times 2MNK); no CPU baseline is taken for it.
 """
 from __future__ import annotations
 
@@ -30,6 +37,9 @@ sys.path.insert(0, ROOT)
 
 METRIC = "SGEMM TFLOP/s geomean over (M,N,K) grid; % of per-shape best with k variants"
 FP32_MFMA_PEAK_TFLOPS = 157.3     # MI355X dense FP32 matrix peak (256 CU x 2.4 GHz x 256 flop/clk)
+MFMA16_PEAK_TFLOPS = 2500.0       # MI355X dense bf16 / fp16 matrix peak
+FORMS = {"fp32": 0, "bf16x3": 1, "bf16x6": 2, "fp16s": 3}
+FORM_PRODUCTS = {"fp32": 1, "bf16x3": 3, "bf16x6": 6, "fp16s": 1}   # MFMA term products per GEMM
 TARGET_MS_PER_SHAPE = 1.0
 
 
@@ -94,7 +104,10 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--phase", choices=("all", "dispatch"), default="all",
                     help="dispatch: only the timed dispatch steps (for profiler runs)")
+    ap.add_argument("--form", choices=tuple(FORMS), default="fp32",
+                    help="precision form (fp32: the plain SGEMM metric)")
     args = ap.parse_args()
+    form, fid = args.form, FORMS[args.form]
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
               "(run with --gpus 1)", file=sys.stderr)
@@ -105,29 +118,36 @@ def main():
 
     from paper_2507_15277_amd import abi, datagen, tuned
     from paper_2507_15277_amd.portability import TABLE, matrix
-    from paper_2507_15277_amd.tune import kernel_hash, load_rows
+    from paper_2507_15277_amd.tune import CFG_PRECISION, current_hashes, kernel_hash, load_rows, read_manifest
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
     stream = torch.cuda.current_stream()
     shapes = datagen.grid27()
-    set_file = tuned.set_path(args.k)
+    set_file = tuned.set_path(args.k, form)
     if not os.path.exists(set_file):
         raise SystemExit(f"{set_file} missing: run the tuner and portability selection first")
     k_loaded = abi.variant_set_load(set_file)
     abi.variant_manifest_load(tuned.VARIANT_DIR)
-    rows = load_rows(TABLE, kernel_hash())
-    t_table = matrix(rows, shapes, 0.0)
+    data = "uniform" if fid == 0 else "lognormal"
+    rows = load_rows(TABLE, kernel_hash() if fid == 0 else current_hashes())
+    t_table = matrix(rows, shapes, 0.0, data=data)
+    of_form = np.array([prec == fid for _, _, prec in sorted(read_manifest(with_prec=True))])
+    t_table[~of_form[:t_table.shape[0]], :] = np.inf
     best_ids = [int(np.argmin(t_table[:, j])) for j in range(len(shapes))]
 
     # Inputs resident in HBM before timing.
     ops = []
     for (M, N, K) in shapes:
-        A, B, _ = datagen.gemm_operands(3, M, N, K)
+        if fid == 0:
+            A, B, _ = datagen.gemm_operands(3, M, N, K)
+        else:
+            A = datagen.lognormal((CFG_PRECISION, M, N, K, datagen.OP_A), M, K)
+            B = datagen.lognormal((CFG_PRECISION, M, N, K, datagen.OP_B), K, N)
         ops.append((torch.from_numpy(A).cuda(), torch.from_numpy(B).cuda(),
                     torch.empty(M, N, dtype=torch.float32, device="cuda")))
     torch.cuda.synchronize()
-    picks = [abi.variant_select(*s) for s in shapes]
+    picks = [abi.variant_select_form(fid, *s) for s in shapes]
     reps = []
     for j, s in enumerate(shapes):
         est = float(t_table[picks[j], j]) if np.isfinite(t_table[picks[j], j]) else 1.0
@@ -138,8 +158,10 @@ def main():
             dA, dB, dC = ops[j]
             ev[j][0].record(stream)
             for _ in range(reps[j]):
-                if vids is None:
+                if vids is None and fid == 0:
                     abi.sgemm(M, N, K, 1.0, dA, K, dB, N, 0.0, dC, N, stream)
+                elif vids is None:
+                    abi.sgemm_form(fid, M, N, K, 1.0, dA, K, dB, N, 0.0, dC, N, stream)
                 else:
                     abi.sgemm_variant(vids[j], M, N, K, 1.0, dA, K, dB, N, 0.0, dC, N, stream)
             ev[j][1].record(stream)
@@ -187,31 +209,40 @@ def main():
     dom = max(share, key=lambda v: share[v][1])
     fl, tm, by = share[dom]
     launches = sum(reps[j] for j in range(len(shapes)) if picks[j] == dom)
-    achieved = fl / tm / 1e9
     dom_name = abi.variant_info(dom).split()[1]
-    roofline = {"bound": "mfma", "achieved": achieved, "peak": FP32_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s",
-                "frac": achieved / FP32_MFMA_PEAK_TFLOPS,
-                "traffic": measured_traffic(dom_name, args.k, kernel_hash()), "kernel": dom_name,
-                "launches_per_step": launches, "flop_per_launch": fl / launches,
-                "algorithmic_bytes_per_launch": by / launches, "ms_per_launch": tm / launches,
-                "shapes": ["x".join(map(str, s)) for j, s in enumerate(shapes) if picks[j] == dom]}
+    if fid == 0:
+        achieved = fl / tm / 1e9
+        roofline = {"bound": "mfma", "achieved": achieved, "peak": FP32_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s",
+                    "frac": achieved / FP32_MFMA_PEAK_TFLOPS,
+                    "traffic": measured_traffic(dom_name, args.k, kernel_hash())}
+    else:
+        # MFMA work the form issues: its term products, each 2MNK on 16-bit MFMA.
+        achieved = FORM_PRODUCTS[form] * fl / tm / 1e9
+        roofline = {"bound": "mfma", "achieved": achieved, "peak": MFMA16_PEAK_TFLOPS, "unit": "TFLOP/s",
+                    "frac": achieved / MFMA16_PEAK_TFLOPS, "traffic": None,
+                    "fp32_equivalent_tflops": fl / tm / 1e9, "mfma_products": FORM_PRODUCTS[form]}
+    roofline.update({"kernel": dom_name, "launches_per_step": launches, "flop_per_launch": fl / launches,
+                     "algorithmic_bytes_per_launch": by / launches, "ms_per_launch": tm / launches,
+                     "shapes": ["x".join(map(str, s)) for j, s in enumerate(shapes) if picks[j] == dom]})
 
+    metric = METRIC if fid == 0 else METRIC.replace("SGEMM", f"SGEMM ({form} form)", 1)
+    workload = ("27-shape grid {256,1024,4096}^3 FP32 SGEMM, alpha=1 beta=0" if fid == 0 else
+                f"27-shape grid {{256,1024,4096}}^3 SGEMM in the {form} form, lognormal operands, alpha=1 beta=0")
     out = {
-        "metric": METRIC, "value": value, "unit": "TFLOP/s", "n_gpus": 1,
+        "metric": metric, "value": value, "unit": "TFLOP/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": wall / args.steps * 1e3,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f32", "data": "synthetic",
+        "dtype": "f32" if fid == 0 else form, "data": "synthetic",
         "pct_of_per_shape_best": 100.0 * frac,
-        "config": {"workload": "27-shape grid {256,1024,4096}^3 FP32 SGEMM, alpha=1 beta=0, "
-                               f"dispatched over a k={k_loaded} portability-tuned variant set",
+        "config": {"workload": f"{workload}, dispatched over a k={k_loaded} portability-tuned variant set",
                    "k": k_loaded, "set_file": os.path.relpath(set_file, ROOT),
                    "launches_per_shape_per_step": reps,
                    "pct_of_best_uncapped": 100.0 * frac_raw,
                    "per_shape_tflops": {"x".join(map(str, s)): round(x, 3) for s, x in zip(shapes, tf)}},
         "roofline": roofline,
     }
-    if not args.no_cpu_baseline and args.phase == "all":
+    if not args.no_cpu_baseline and args.phase == "all" and fid == 0:
         out["cpu_baseline"] = cpu_baseline(shapes)
     print(json.dumps(out), flush=True)
 

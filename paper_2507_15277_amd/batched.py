@@ -14,6 +14,7 @@ role of the paper's environments and the total time of the batch is the
 single-device form of the fleet objective (Eq. 2).
 
     python -m paper_2507_15277_amd.batched [--count 2000] [--buckets 4] [--out report.json]
+                                           [--bucket-variants ID,ID,ID,ID]
 """
 from __future__ import annotations
 
@@ -139,7 +140,9 @@ def tune_buckets(batch, bucket_of, nb, candidates, log=print):
     return best
 
 
-def run(count=2000, nb=4, seed=0, log=print):
+def run(count=2000, nb=4, seed=0, log=print, bucket_variants=None):
+    """Tune the bucket variants (or take ``bucket_variants``, one id per
+    bucket), then time per-problem launches, grouped launches and the graph."""
     import torch
 
     abi.variant_manifest_load(tuned.VARIANT_DIR)
@@ -148,7 +151,12 @@ def run(count=2000, nb=4, seed=0, log=print):
     batch = Batch(shapes, seed=seed)
     bucket_of = buckets_of(shapes, nb)
     t0 = time.perf_counter()
-    best = tune_buckets(batch, bucket_of, nb, fp32, log)
+    if bucket_variants is None:
+        best = tune_buckets(batch, bucket_of, nb, fp32, log)
+    else:
+        if len(bucket_variants) != nb or any(v not in fp32 for v in bucket_variants):
+            raise ValueError(f"need {nb} FP32 variant ids, one per bucket")
+        best = {b: (v, float("nan")) for b, v in enumerate(bucket_variants) if np.any(bucket_of == b)}
     tune_s = time.perf_counter() - t0
     plans = [GroupedPlan(batch, [i for i in range(count) if bucket_of[i] == b], best[b][0]) for b in sorted(best)]
     stream = torch.cuda.current_stream()
@@ -198,8 +206,11 @@ def main(argv=None):
     ap.add_argument("--buckets", type=int, default=4)
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--out", default=None)
+    ap.add_argument("--bucket-variants", default=None,
+                    help="comma-separated variant ids, one per bucket (skips the bucket tuning)")
     args = ap.parse_args(argv)
-    rep = run(args.count, args.buckets, args.seed, log=lambda s: print(s, flush=True))
+    bv = [int(x) for x in args.bucket_variants.split(",")] if args.bucket_variants else None
+    rep = run(args.count, args.buckets, args.seed, log=lambda s: print(s, flush=True), bucket_variants=bv)
     if args.out:
         with open(args.out, "w") as f:
             json.dump(rep, f, indent=1)
