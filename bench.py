@@ -153,18 +153,32 @@ def main():
         est = float(t_table[picks[j], j]) if np.isfinite(t_table[picks[j], j]) else 1.0
         reps.append(max(1, min(1000, int(round(TARGET_MS_PER_SHAPE / est)))))
 
+    # The C entry points are called straight through ctypes with the device
+    # pointers and stream handle prepared once (the same calls the abi
+    # wrappers make, without their per-call conversions); every call's status
+    # is checked.
+    L = abi.lib()
+    h = stream.cuda_stream
+    ptrs = [(a.data_ptr(), b.data_ptr(), c.data_ptr()) for a, b, c in ops]
+
     def run_step(vids, ev):
+        bad = 0
         for j, (M, N, K) in enumerate(shapes):
-            dA, dB, dC = ops[j]
+            pa, pb, pc = ptrs[j]
             ev[j][0].record(stream)
-            for _ in range(reps[j]):
-                if vids is None and fid == 0:
-                    abi.sgemm(M, N, K, 1.0, dA, K, dB, N, 0.0, dC, N, stream)
-                elif vids is None:
-                    abi.sgemm_form(fid, M, N, K, 1.0, dA, K, dB, N, 0.0, dC, N, stream)
-                else:
-                    abi.sgemm_variant(vids[j], M, N, K, 1.0, dA, K, dB, N, 0.0, dC, N, stream)
+            if vids is None and fid == 0:
+                for _ in range(reps[j]):
+                    bad |= L.sgemm(M, N, K, 1.0, pa, K, pb, N, 0.0, pc, N, h)
+            elif vids is None:
+                for _ in range(reps[j]):
+                    bad |= L.sgemm_form(fid, M, N, K, 1.0, pa, K, pb, N, 0.0, pc, N, h)
+            else:
+                v = vids[j]
+                for _ in range(reps[j]):
+                    bad |= L.sgemm_variant(v, M, N, K, 1.0, pa, K, pb, N, 0.0, pc, N, h)
             ev[j][1].record(stream)
+        if bad:
+            raise RuntimeError("sgemm failed: " + abi.last_error())
 
     def timed(vids, steps, warmup):
         ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))

@@ -104,6 +104,27 @@ def test_every_variant_vector_path(loaded):
     assert not fails, "\n".join(fails[:10])
 
 
+def test_every_variant_vector_path_padded(loaded):
+    # The vector kernel's conditions (sizes and leading dimensions multiples
+    # of 4) with NaN in the padding of every operand and K ragged against
+    # every K-step: a slab unit past K that reached LDS (load-to-LDS staging
+    # copies whole 16-byte units) would turn every element of C into NaN.
+    M, N, K = 200, 328, 132
+    lda, ldb, ldc = K + 4, N + 8, N + 4
+    A = datagen.uniform((24, M, N, K, 0), M, K)
+    B = datagen.uniform((24, M, N, K, 1), K, N)
+    C0 = datagen.uniform((24, M, N, K, 2), M, N)
+    fails = []
+    for vid, name in loaded:
+        C, guard = run_gemm(vid, A, B, C0, 1.5, -0.5, lda, ldb, ldc)
+        try:
+            _check(C, A, B, C0, 1.5, -0.5, name)
+            assert guard, f"{name}: wrote outside C"
+        except AssertionError as e:
+            fails.append(str(e))
+    assert not fails, "\n".join(fails[:10])
+
+
 def test_every_variant_integers_bitwise(loaded):
     # Integer entries in [-8, 8], K = 260: partial sums stay below 2^24, so
     # every variant must reproduce the exact integer result bit for bit.
