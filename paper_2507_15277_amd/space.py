@@ -311,6 +311,19 @@ HAND = [
     Variant(64, 64, 32, 32, 2, 2, 2, 4, 2, sg=8, pd=2),
     Variant(16, 32, 128, 16, 1, 1, 4, 4, 2, sg=4),
     Variant(64, 128, 32, 32, 1, 4, 1, 4, 2, pd=2),
+    # Larger tiles and deeper slabs with load-to-LDS staging.
+    Variant(256, 256, 32, 16, 2, 4, 1, 4, 2),
+    Variant(256, 256, 16, 16, 2, 4, 1, 4, 2, pd=2),
+    Variant(256, 256, 32, 32, 4, 2, 1, 4, 2),
+    Variant(256, 128, 32, 32, 4, 2, 1, 4, 2, pd=2),
+    Variant(128, 256, 32, 32, 2, 4, 1, 4, 2),
+    Variant(128, 128, 64, 32, 2, 2, 1, 4, 2),
+    Variant(64, 64, 128, 32, 2, 2, 2, 4, 2, sg=4),
+    Variant(64, 64, 64, 32, 2, 2, 2, 4, 2, sg=8),
+    Variant(64, 128, 64, 32, 2, 2, 2, 4, 2),
+    Variant(128, 64, 64, 32, 2, 2, 2, 4, 2),
+    Variant(32, 32, 128, 32, 1, 1, 4, 4, 2, sg=4),
+    Variant(32, 16, 128, 16, 1, 1, 4, 4, 2),
 ]
 
 
