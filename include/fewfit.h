@@ -124,7 +124,12 @@ int variant_set_load(const char *path);
  * within 2^25 of each matrix's largest magnitude), plus FP32 accumulation.
  * The fp16s form first reduces max|A| and max|B| on the device into the
  * per-device workspace (calls on one device must not overlap in time) and
- * needs finite inputs.  Other semantics as sgemm(); FF_ERR_ARG for an
+ * needs finite inputs.  Pre-split variants (LDS mode 2) first form the
+ * pieces of A and B into a 1 GiB per-device pieces workspace (allocated
+ * when such a variant is loaded; calls on one device must not overlap in
+ * time) and return FF_ERR_TOO_LARGE when 2 * T * (Mp + Np) * Kp bytes
+ * exceed it (T pieces per value, Mp, Np rounded up to the tile, Kp = K
+ * rounded up to 64).  Other semantics as sgemm(); FF_ERR_ARG for an
  * unknown form.
  */
 int sgemm_form(int form, int64_t M, int64_t N, int64_t K, float alpha,

@@ -65,6 +65,10 @@ struct Variant {
     hipFunction_t fgrp = nullptr;  // grouped persistent, VW-wide loads (FP32 variants)
     hipFunction_t fgrp1 = nullptr; // grouped persistent, scalar loads
     int grp_blocks = 0;            // grouped grid: resident work-groups per device
+    hipFunction_t fpa = nullptr;   // pre-split forms (LDS mode 2): pieces of A
+    hipFunction_t fpb = nullptr;   // pre-split forms: pieces of B, transposed
+    bool presplit() const { return prec > 0 && lds == 2; }
+    int terms() const { return prec == 1 ? 2 : (prec == 2 ? 3 : 1); }
     int threads() const { return 64 * wm * wn * sk; }
 };
 
@@ -79,7 +83,7 @@ bool parse_descriptor(std::istringstream& is, Variant& v)
         v.wn <= 0 || v.sk <= 0 || (v.vw != 1 && v.vw != 2 && v.vw != 4) || v.lds < 0 || v.lds > 2 || (v.lds == 2 && v.vw != 4) ||
         v.gm <= 0 || v.sg < 1 || v.sg > 64 || v.prec < 0 || v.prec > 3 || v.threads() > 1024)
         return false;
-    if (v.prec > 0 && (v.sk != 1 || v.lds != 1)) return false;
+    if (v.prec > 0 && (v.sk != 1 || v.lds < 1)) return false;
     for (char c : v.name)
         if (!(isalnum((unsigned char)c) || c == '_')) return false;
     return true;
@@ -114,7 +118,12 @@ constexpr int kMaxDevices = 16;
 struct Workspace {
     float* ws = nullptr;
     float* scale = nullptr;  // FP16 form: block maxima of |A| and |B|, then {2^eA, 2^eB, 2^-(eA+eB)}
+    short* pieces = nullptr; // pre-split forms: 16-bit pieces of A and B
 };
+// Pieces of the pre-split forms: TERMS planes of A (Mp x Kp) and of B
+// (Np x Kp) 16-bit values, Mp, Np rounded up to the tile and Kp to 64.
+constexpr size_t kPieceBytes = size_t(1) << 30;
+constexpr int kPieceKPad = 64;
 Workspace g_ws[kMaxDevices];
 constexpr int kMaxBlocks = 1024;  // per matrix, for the |A|, |B| maxima
 
@@ -136,6 +145,21 @@ int ensure_workspace()
     return FF_OK;
 }
 
+int ensure_pieces()
+{
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    if (dev < 0 || dev >= kMaxDevices) return fail(FF_ERR_ARG, "device %d beyond the supported %d", dev, kMaxDevices);
+    if (g_ws[dev].pieces != nullptr) return FF_OK;
+    e = hipMalloc(&g_ws[dev].pieces, kPieceBytes);
+    if (e != hipSuccess) {
+        g_ws[dev].pieces = nullptr;
+        return hip_fail(e, "allocate the pieces workspace");
+    }
+    return FF_OK;
+}
+
 int load_code_object(Variant& v, const std::string& path)
 {
     {
@@ -147,7 +171,15 @@ int load_code_object(Variant& v, const std::string& path)
     if (e != hipSuccess) return hip_fail(e, ("hipModuleLoad " + path).c_str());
     hipFunction_t fv = nullptr, fs = nullptr;
     e = hipModuleGetFunction(&fv, mod, v.name.c_str());
-    if (e == hipSuccess) e = hipModuleGetFunction(&fs, mod, (v.name + "_v1").c_str());
+    if (v.presplit()) {
+        // One GEMM kernel (pieces are always aligned and padded) and the two
+        // split passes.
+        fs = fv;
+        if (e == hipSuccess) e = hipModuleGetFunction(&v.fpa, mod, (v.name + "_pa").c_str());
+        if (e == hipSuccess) e = hipModuleGetFunction(&v.fpb, mod, (v.name + "_pb").c_str());
+    } else if (e == hipSuccess) {
+        e = hipModuleGetFunction(&fs, mod, (v.name + "_v1").c_str());
+    }
     if (e != hipSuccess) {
         (void)hipModuleUnload(mod);
         return hip_fail(e, ("hipModuleGetFunction " + v.name).c_str());
@@ -189,6 +221,10 @@ int register_variant(const Variant& d, const std::string& dir)
     if (rc != FF_OK) return rc;
     if (d.sg > 1 || d.prec == 3) {
         rc = ensure_workspace();
+        if (rc != FF_OK) return rc;
+    }
+    if (d.presplit()) {
+        rc = ensure_pieces();
         if (rc != FF_OK) return rc;
     }
     g_variants[d.id] = v;
@@ -360,8 +396,15 @@ float* current_workspace()
 
 // K split over work-groups: as many as the variant allows, no more than
 // there are slabs, every split non-empty, and within the workspace.  M, N >= 1.
+// K as the GEMM kernel sees it: pre-split forms run over K padded to 64.
+int64_t launch_k(const Variant& v, int64_t K)
+{
+    return v.presplit() ? (K + kPieceKPad - 1) / kPieceKPad * kPieceKPad : K;
+}
+
 int split_count(const Variant& v, int64_t M, int64_t N, int64_t K, bool have_ws)
 {
+    K = launch_k(v, K);
     const int64_t nkt = (K + v.kwg - 1) / v.kwg;
     if (!(v.sg > 1 && nkt > 1 && have_ws)) return 1;
     const int64_t nb = ((M + v.mwg - 1) / v.mwg) * ((N + v.nwg - 1) / v.nwg);
@@ -411,19 +454,48 @@ int launch_variant(const Variant& v, int64_t M, int64_t N, int64_t K, float alph
         if (e0 != hipSuccess) return hip_fail(e0, "launch fp16 prescale");
         prescale = buf + 2 * kMaxBlocks;
     }
-    const int64_t nkt = (K + v.kwg - 1) / v.kwg;
+    const int64_t nkt = (launch_k(v, K) + v.kwg - 1) / v.kwg;
     float* ws = current_workspace();
     int splits = split_count(v, M, N, K, ws != nullptr);
     if (splits == 1) ws = nullptr;
     int kper = (int)((nkt + splits - 1) / splits);
     int Mi = (int)M, Ni = (int)N, Ki = (int)K;
     long la = (long)lda, lb = (long)ldb, lc = (long)ldc;
-    // FP32 variants take 14 arguments; split-precision variants add the
-    // FP16 prescale pointer.
-    void* args[] = {&Mi, &Ni, &Ki, &alpha, (void*)&A, &la, (void*)&B, &lb, &beta, (void*)&C, &lc,
-                    (void*)&ws, &splits, &kper, (void*)&prescale};
-    hipError_t e = hipModuleLaunchKernel(f, (unsigned)(nb * splits), 1, 1, (unsigned)v.threads(), 1, 1, 0, s, args,
-                                         nullptr);
+    hipError_t e;
+    if (v.presplit()) {
+        // Form the pieces of A and B, then the GEMM on them.
+        int dev = 0;
+        if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices || g_ws[dev].pieces == nullptr)
+            return fail(FF_ERR_HIP, "pre-split form: no pieces workspace on this device");
+        int Mp = (int)(nbm * v.mwg), Np = (int)(nbn * v.nwg), Kp = (int)launch_k(v, K);
+        const int64_t T = v.terms();
+        const int64_t need = 2 * T * ((int64_t)Mp + Np) * Kp;
+        if (need > (int64_t)kPieceBytes)
+            return fail(FF_ERR_TOO_LARGE, "pre-split form: %lld bytes of pieces exceed the %zu-byte workspace",
+                        (long long)need, kPieceBytes);
+        short* PA = g_ws[dev].pieces;
+        short* PB = PA + T * (int64_t)Mp * Kp;
+        long pa_plane = (long)Mp * Kp, pb_plane = (long)Np * Kp;
+        int vecA = (K % 4 == 0 && lda % 4 == 0 && aligned_for(A, 4)) ? 1 : 0;
+        void* aa[] = {&Mi, &Ki, (void*)&A, &la, &vecA, (void*)&prescale, (void*)&PA, &Mp, &Kp, &pa_plane};
+        void* ab[] = {&Ki, &Ni, (void*)&B, &lb, (void*)&prescale, (void*)&PB, &Np, &Kp, &pb_plane};
+        const int64_t ia = (int64_t)Mp * (Kp / 8), ib = (int64_t)Np * (Kp / 8);
+        e = hipModuleLaunchKernel(v.fpa, (unsigned)((ia + 255) / 256), 1, 1, 256, 1, 1, 0, s, aa, nullptr);
+        if (e == hipSuccess)
+            e = hipModuleLaunchKernel(v.fpb, (unsigned)((ib + 255) / 256), 1, 1, 256, 1, 1, 0, s, ab, nullptr);
+        if (e != hipSuccess) return hip_fail(e, ("launch split passes of " + v.name).c_str());
+        void* ag[] = {&Mi, &Ni, &Kp, &alpha, (void*)&PA, &pa_plane, (void*)&PB, &pb_plane, &beta, (void*)&C, &lc,
+                      (void*)&ws, &splits, &kper, (void*)&prescale};
+        e = hipModuleLaunchKernel(v.fvec, (unsigned)(nb * splits), 1, 1, (unsigned)v.threads(), 1, 1, 0, s, ag,
+                                  nullptr);
+    } else {
+        // FP32 variants take 14 arguments; split-precision variants add the
+        // FP16 prescale pointer.
+        void* args[] = {&Mi, &Ni, &Ki, &alpha, (void*)&A, &la, (void*)&B, &lb, &beta, (void*)&C, &lc,
+                        (void*)&ws, &splits, &kper, (void*)&prescale};
+        e = hipModuleLaunchKernel(f, (unsigned)(nb * splits), 1, 1, (unsigned)v.threads(), 1, 1, 0, s, args,
+                                  nullptr);
+    }
     if (e != hipSuccess) return hip_fail(e, ("launch " + v.name).c_str());
     if (splits > 1) {
         const int64_t work = M * ((N + 3) / 4);

@@ -27,6 +27,14 @@
 // split one tile's K range; 1: no split), FF_NAME (kernel symbol;
 // FF_NAME##_v1 is the scalar-load kernel of the same configuration).
 //
+// FF_LDS 2 (pre-split): two small kernels of the same code object first form
+// the 16-bit pieces of A and B once per call into a workspace, K-major and
+// zero-padded to whole tiles and to a multiple of 64 in K (FF_NAME##_pa
+// for A, FF_NAME##_pb for B, which also transposes B to [n][k]); the GEMM
+// kernel then copies slabs of pieces straight into LDS with load-to-LDS
+// copies (16 bytes = 8 pieces per lane) and runs only the MFMAs, with no
+// splitting, masking or register staging in its loop.
+//
 // With the K range split over work-groups (splits > 1, at most FF_SG), each
 // work-group takes a contiguous range of slabs and writes its raw partial
 // product (after the FP16 form's exact unscale) to its split's M x N slice
@@ -61,6 +69,9 @@
 #ifndef FF_SG
 #define FF_SG 1
 #endif
+#ifndef FF_LDS
+#define FF_LDS 1
+#endif
 
 #define FF_CAT2(a, b) a##b
 #define FF_CAT(a, b) FF_CAT2(a, b)
@@ -69,6 +80,7 @@ namespace {
 
 constexpr int MWG = FF_MWG, NWG = FF_NWG, KWG = FF_KWG, MI = FF_MI;
 constexpr int WM = FF_WM, WN = FF_WN, PREC = FF_PREC, GM = FF_GM, SG = FF_SG;
+constexpr bool PRESPLIT = FF_LDS == 2;
 constexpr int TERMS = PREC == 1 ? 2 : (PREC == 2 ? 3 : 1);
 constexpr int KB = 8 * (64 / MI);        // MFMA k depth: 16 (MI 32) or 32 (MI 16)
 constexpr int WTM = MWG / WM, WTN = NWG / WN;
@@ -81,8 +93,15 @@ constexpr int ACC = MI * MI / 64;
 // reads of 8 consecutive rows fall in disjoint banks.
 constexpr int LDK = KWG + 8;
 constexpr int A_TERM = MWG * LDK, B_TERM = NWG * LDK;   // 16-bit elements
-constexpr int STAGE = TERMS * (A_TERM + B_TERM);
-constexpr int LDS_ELEMS = 2 * STAGE;
+constexpr int STAGE_RAW = TERMS * (A_TERM + B_TERM);
+// Pre-split: a stage is rounded up to whole wave copies (64 lanes x 8
+// pieces); surplus copies land in a 1 KB scratch area after the stages.
+constexpr int STAGE = PRESPLIT ? (STAGE_RAW + 511) / 512 * 512 : STAGE_RAW;
+constexpr int NWI = STAGE / 512;                         // wave copies per stage
+constexpr int NWAVE = WM * WN;
+constexpr int DPS = (NWI + NWAVE - 1) / NWAVE;           // copies per wave per slab
+constexpr int LDS_ELEMS = 2 * STAGE + (PRESPLIT ? 512 : 0);
+constexpr int KPAD = 64;                                 // pre-split pieces: K padded to this
 
 static_assert(PREC >= 1 && PREC <= 3, "precision form");
 static_assert(MI == 32 || MI == 16, "MFMA block edge");
@@ -90,6 +109,9 @@ static_assert(MWG % (WM * MI) == 0 && NWG % (WN * MI) == 0, "tile must split int
 static_assert(KWG % KB == 0, "slab depth must be a multiple of the MFMA k");
 static_assert(NT <= 1024, "work-group size");
 static_assert(SG >= 1, "split count");
+static_assert(FF_LDS == 1 || FF_LDS == 2, "staging mode");
+static_assert(KPAD % KWG == 0, "pre-split K padding must be whole slabs");
+static_assert(DPS <= 63, "wait count range");
 
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
@@ -170,6 +192,83 @@ __device__ constexpr Pair kPairs3[3] = {{1, 0}, {0, 1}, {0, 0}};
 __device__ constexpr Pair kPairs6[6] = {{2, 0}, {0, 2}, {1, 1}, {1, 0}, {0, 1}, {0, 0}};
 __device__ constexpr Pair kPairs1[1] = {{0, 0}};
 constexpr int NPAIRS = PREC == 1 ? 3 : (PREC == 2 ? 6 : 1);
+
+// The MFMAs of one LDS slab: every kept term product of the lane's A rows
+// and B columns, smallest first.
+__device__ __forceinline__ void mma_slab(const short* sA, const short* sB, int arow, int bcol,
+                                         acc_t (&acc)[RM][RN])
+{
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+        i16x8 av[TERMS][RM], bv[TERMS][RN];
+#pragma unroll
+        for (int q = 0; q < TERMS; ++q) {
+#pragma unroll
+            for (int i = 0; i < RM; ++i)
+                av[q][i] = *reinterpret_cast<const i16x8*>(sA + q * A_TERM + arow + i * MI * LDK + s * KB);
+#pragma unroll
+            for (int j = 0; j < RN; ++j)
+                bv[q][j] = *reinterpret_cast<const i16x8*>(sB + q * B_TERM + bcol + j * MI * LDK + s * KB);
+        }
+#pragma unroll
+        for (int p = 0; p < NPAIRS; ++p) {
+            const Pair pr = PREC == 1 ? kPairs3[p] : (PREC == 2 ? kPairs6[p] : kPairs1[p]);
+#pragma unroll
+            for (int i = 0; i < RM; ++i)
+#pragma unroll
+                for (int j = 0; j < RN; ++j) acc[i][j] = mfma16(bv[pr.b][j], av[pr.a][i], acc[i][j]);
+        }
+    }
+}
+
+// Epilogue as in the FP32 kernel; the FP16 form first removes its prescale
+// (a power of two, exact).  A split tile writes its raw partial to its slice
+// of the workspace (alpha 1, beta 0).
+__device__ __forceinline__ void store_tile(const acc_t (&acc)[RM][RN], int M, int N, float alpha, float beta,
+                                           float* __restrict__ C, long ldc, float unscale, float* __restrict__ ws,
+                                           int splits, int part, int m0, int n0, int wm, int wn, int lr, int lh)
+{
+    if constexpr (SG > 1) {
+        if (splits > 1) {
+            C = ws + (size_t)part * (size_t)M * (size_t)N;
+            ldc = N;
+            alpha = 1.0f;
+            beta = 0.0f;
+        }
+    }
+    const bool cvec = ((reinterpret_cast<uintptr_t>(C) & 15) == 0) && ((ldc & 3) == 0);
+    const bool use_beta = (beta != 0.0f);
+#pragma unroll
+    for (int i = 0; i < RM; ++i) {
+        const int m = m0 + wm * WTM + i * MI + lr;
+        if (m >= M) continue;
+        float* crow = C + (long)m * ldc;
+#pragma unroll
+        for (int j = 0; j < RN; ++j) {
+#pragma unroll
+            for (int g = 0; g < ACC / 4; ++g) {
+                const int n = n0 + wn * WTN + j * MI + (MI == 32 ? 8 * g : 0) + 4 * lh;
+                f32x4 v;
+#pragma unroll
+                for (int c = 0; c < 4; ++c) v[c] = acc[i][j][4 * g + c] * unscale;
+                if (cvec && n + 4 <= N) {
+                    f32x4 o = alpha * v;
+                    if (use_beta) o += beta * *reinterpret_cast<const f32x4*>(crow + n);
+                    *reinterpret_cast<f32x4*>(crow + n) = o;
+                } else {
+#pragma unroll
+                    for (int c = 0; c < 4; ++c) {
+                        if (n + c < N) {
+                            float o = alpha * v[c];
+                            if (use_beta) o += beta * crow[n + c];
+                            crow[n + c] = o;
+                        }
+                    }
+                }
+            }
+        }
+    }
+}
 
 template <bool VEC>
 __device__ __forceinline__ void body(int M, int N, int K, float alpha, const float* __restrict__ A, long lda,
@@ -295,79 +394,177 @@ __device__ __forceinline__ void body(int M, int N, int K, float alpha, const flo
         const int st = (kt - kt0) & 1;
         if (kt + 1 < kt1) gload(kt + 1);
         const short* sA = smem + st * STAGE;
-        const short* sB = sA + TERMS * A_TERM;
-#pragma unroll
-        for (int s = 0; s < S; ++s) {
-            i16x8 av[TERMS][RM], bv[TERMS][RN];
-#pragma unroll
-            for (int q = 0; q < TERMS; ++q) {
-#pragma unroll
-                for (int i = 0; i < RM; ++i)
-                    av[q][i] = *reinterpret_cast<const i16x8*>(sA + q * A_TERM + arow + i * MI * LDK + s * KB);
-#pragma unroll
-                for (int j = 0; j < RN; ++j)
-                    bv[q][j] = *reinterpret_cast<const i16x8*>(sB + q * B_TERM + bcol + j * MI * LDK + s * KB);
-            }
-#pragma unroll
-            for (int p = 0; p < NPAIRS; ++p) {
-                const Pair pr = PREC == 1 ? kPairs3[p] : (PREC == 2 ? kPairs6[p] : kPairs1[p]);
-#pragma unroll
-                for (int i = 0; i < RM; ++i)
-#pragma unroll
-                    for (int j = 0; j < RN; ++j) acc[i][j] = mfma16(bv[pr.b][j], av[pr.a][i], acc[i][j]);
-            }
-        }
+        mma_slab(sA, sA + TERMS * A_TERM, arow, bcol, acc);
         if (kt + 1 < kt1) sstore(st ^ 1, kt + 1);
         __syncthreads();
     }
+    store_tile(acc, M, N, alpha, beta, C, ldc, unscale, ws, splits, part, m0, n0, wm, wn, lr, lh);
+}
 
-    // Epilogue as in the FP32 kernel; the FP16 form first removes its
-    // prescale (a power of two, exact).  A split tile writes its raw partial
-    // to its slice of the workspace (alpha 1, beta 0).
-    if constexpr (SG > 1) {
-        if (splits > 1) {
-            C = ws + (size_t)part * (size_t)M * (size_t)N;
-            ldc = N;
-            alpha = 1.0f;
-            beta = 0.0f;
-        }
-    }
-    const bool cvec = ((reinterpret_cast<uintptr_t>(C) & 15) == 0) && ((ldc & 3) == 0);
-    const bool use_beta = (beta != 0.0f);
+// ---- pre-split mode --------------------------------------------------------
+
+// s_waitcnt immediate (gfx9 encoding): at most `vm` vector-memory operations
+// outstanding, no LDS/scalar-memory operations outstanding, exports untouched.
+constexpr int waitcnt_vm(int vm) { return (vm & 15) | (((vm >> 4) & 3) << 14) | (7 << 4); }
+typedef __attribute__((address_space(3))) void* lds_ptr;
+
+// GEMM on pieces formed by the split-pass kernels: PA holds TERMS planes of
+// Mp x Kp pieces of A (row m, k contiguous), PB TERMS planes of Np x Kp
+// pieces of B (row n, k contiguous), zero past M, N and K, so every copy is
+// in bounds and every slab is whole.  Slabs are copied into LDS with
+// load-to-LDS copies, two stages deep; unit u (16 bytes) of a stage holds
+// pieces 8u..8u+7 of the stage image [term][row][LDK] (A rows, then B rows);
+// units in the row padding or past the image copy from PA itself.
+__device__ __forceinline__ void body_pieces(int M, int N, int Kp, float alpha, const short* __restrict__ PA,
+                                            long pa_plane, const short* __restrict__ PB, long pb_plane,
+                                            float beta, float* __restrict__ C, long ldc, float* __restrict__ ws,
+                                            int splits, int kper, const float* __restrict__ prescale, short* smem)
+{
+    const int nbm = (M + MWG - 1) / MWG, nbn = (N + NWG - 1) / NWG;
+    int tm, tn, part;
+    tile_of(blockIdx.x, nbm, nbn, SG > 1 ? splits : 1, tm, tn, part);
+    const int m0 = tm * MWG, n0 = tn * NWG;
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    const int wm = wid / WN, wn = wid % WN;
+    const int lr = lane % MI, lh = lane / MI;
+    const float unscale = (PREC == 3) ? prescale[2] : 1.0f;
+
+    acc_t acc[RM][RN];
 #pragma unroll
-    for (int i = 0; i < RM; ++i) {
-        const int m = m0 + wm * WTM + i * MI + lr;
-        if (m >= M) continue;
-        float* crow = C + (long)m * ldc;
+    for (int i = 0; i < RM; ++i)
 #pragma unroll
-        for (int j = 0; j < RN; ++j) {
+        for (int j = 0; j < RN; ++j) acc[i][j] = acc_t{};
+
+    const int nkt = Kp / KWG;
+    const int kt0 = (SG > 1) ? part * kper : 0;
+    const int kt1 = (SG > 1) ? min(nkt, kt0 + kper) : nkt;
+
+    // Per copy slot: the unit's source at k = 0 (pieces advance by KWG per slab).
+    constexpr int RU = LDK / 8;                          // units per LDS row
+    constexpr int UA = TERMS * MWG * RU;
+    constexpr int UB = TERMS * NWG * RU;
+    const short* base[DPS];
+    bool real[DPS];
 #pragma unroll
-            for (int g = 0; g < ACC / 4; ++g) {
-                const int n = n0 + wn * WTN + j * MI + (MI == 32 ? 8 * g : 0) + 4 * lh;
-                f32x4 v;
-#pragma unroll
-                for (int c = 0; c < 4; ++c) v[c] = acc[i][j][4 * g + c] * unscale;
-                if (cvec && n + 4 <= N) {
-                    f32x4 o = alpha * v;
-                    if (use_beta) o += beta * *reinterpret_cast<const f32x4*>(crow + n);
-                    *reinterpret_cast<f32x4*>(crow + n) = o;
-                } else {
-#pragma unroll
-                    for (int c = 0; c < 4; ++c) {
-                        if (n + c < N) {
-                            float o = alpha * v[c];
-                            if (use_beta) o += beta * crow[n + c];
-                            crow[n + c] = o;
-                        }
-                    }
-                }
+    for (int j = 0; j < DPS; ++j) {
+        const int wi = wid + j * NWAVE;
+        const int u = wi * 64 + lane;
+        base[j] = PA;
+        real[j] = false;
+        if (wi < NWI && u < UA) {
+            const int q = u / (MWG * RU), rem = u % (MWG * RU), row = rem / RU, c = rem % RU;
+            if (c < KWG / 8) {
+                base[j] = PA + q * pa_plane + (long)(m0 + row) * Kp + 8 * c;
+                real[j] = true;
+            }
+        } else if (wi < NWI && u < UA + UB) {
+            const int v = u - UA;
+            const int q = v / (NWG * RU), rem = v % (NWG * RU), row = rem / RU, c = rem % RU;
+            if (c < KWG / 8) {
+                base[j] = PB + q * pb_plane + (long)(n0 + row) * Kp + 8 * c;
+                real[j] = true;
             }
         }
     }
+    auto issue = [&](int kt, int st) {
+#pragma unroll
+        for (int j = 0; j < DPS; ++j) {
+            const int wi = wid + j * NWAVE;
+            const short* src = base[j] + (real[j] ? kt * KWG : 0);
+            short* dst = (wi < NWI) ? smem + st * STAGE + wi * 512 : smem + 2 * STAGE;
+            __builtin_amdgcn_global_load_lds(src, (lds_ptr)dst, 16, 0, 0);
+        }
+    };
+
+    const int arow = (wm * WTM + lr) * LDK + lh * 8;
+    const int bcol = (wn * WTN + lr) * LDK + lh * 8;
+    issue(kt0, 0);
+    int st = 0;
+    for (int kt = kt0; kt < kt1; ++kt) {
+        // This slab's copies are done, and every wave is done with the other
+        // stage (the empty asm statements keep LDS accesses from moving across).
+        asm volatile("" ::: "memory");
+        __builtin_amdgcn_s_waitcnt(waitcnt_vm(0));
+        __builtin_amdgcn_s_barrier();
+        asm volatile("" ::: "memory");
+        if (kt + 1 < kt1) issue(kt + 1, st ^ 1);
+        const short* sA = smem + st * STAGE;
+        mma_slab(sA, sA + TERMS * A_TERM, arow, bcol, acc);
+        st ^= 1;
+    }
+    __syncthreads();
+    store_tile(acc, M, N, alpha, beta, C, ldc, unscale, ws, splits, part, m0, n0, wm, wn, lr, lh);
+}
+
+// Pieces of one 8-value chunk of k.  `x` holds the FP32 values (0 past the
+// matrix), written as TERMS 16-byte vectors to planes of `plane` elements.
+__device__ __forceinline__ void put_pieces(const float (&x)[8], float scale, short* __restrict__ out, long plane)
+{
+    i16x8 t[TERMS];
+    split8(x, scale, t);
+#pragma unroll
+    for (int q = 0; q < TERMS; ++q) *reinterpret_cast<i16x8*>(out + q * plane) = t[q];
 }
 
 }  // namespace
 
+#if FF_LDS == 2
+// Split pass over A (M x K, row stride lda): item (m, k8) writes pieces of
+// A[m][8 k8 .. 8 k8 + 7] to row m of the Mp x Kp planes; zeros past M and K.
+// vec: K and lda multiples of 4 and A 16-byte aligned (two vector loads).
+extern "C" __global__ void __launch_bounds__(256)
+FF_CAT(FF_NAME, _pa)(int M, int K, const float* __restrict__ A, long lda, int vec,
+                     const float* __restrict__ prescale, short* __restrict__ P, int Mp, int Kp, long plane)
+{
+    const long items = (long)Mp * (Kp / 8);
+    const long idx = (long)blockIdx.x * 256 + threadIdx.x;
+    if (idx >= items) return;
+    const int m = (int)(idx / (Kp / 8)), k = (int)(idx % (Kp / 8)) * 8;
+    float x[8];
+    const float* p = A + (long)m * lda + k;
+    if (vec && m < M && k + 8 <= K) {
+        const f32x4 v0 = *reinterpret_cast<const f32x4*>(p);
+        const f32x4 v1 = *reinterpret_cast<const f32x4*>(p + 4);
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            x[e] = v0[e];
+            x[4 + e] = v1[e];
+        }
+    } else {
+#pragma unroll
+        for (int e = 0; e < 8; ++e) x[e] = (m < M && k + e < K) ? p[e] : 0.0f;
+    }
+    put_pieces(x, PREC == 3 ? prescale[0] : 1.0f, P + (long)m * Kp + k, plane);
+}
+
+// Split pass over B (K x N, row stride ldb), transposed: item (n, k8) writes
+// pieces of B[8 k8 .. 8 k8 + 7][n] to row n of the Np x Kp planes; zeros past
+// N and K.  Consecutive threads take consecutive n, so each load instruction
+// reads consecutive addresses.
+extern "C" __global__ void __launch_bounds__(256)
+FF_CAT(FF_NAME, _pb)(int K, int N, const float* __restrict__ B, long ldb, const float* __restrict__ prescale,
+                     short* __restrict__ P, int Np, int Kp, long plane)
+{
+    const long items = (long)Np * (Kp / 8);
+    const long idx = (long)blockIdx.x * 256 + threadIdx.x;
+    if (idx >= items) return;
+    const int n = (int)(idx % Np), k = (int)(idx / Np) * 8;
+    float x[8];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) x[e] = (n < N && k + e < K) ? B[(long)(k + e) * ldb + n] : 0.0f;
+    put_pieces(x, PREC == 3 ? prescale[1] : 1.0f, P + (long)n * Kp + k, plane);
+}
+
+// GEMM on the pieces (see body_pieces).
+extern "C" __global__ void __launch_bounds__(NT)
+FF_NAME(int M, int N, int Kp, float alpha, const short* __restrict__ PA, long pa_plane,
+        const short* __restrict__ PB, long pb_plane, float beta, float* __restrict__ C, long ldc,
+        float* __restrict__ ws, int splits, int kper, const float* __restrict__ prescale)
+{
+    __shared__ __attribute__((aligned(16))) short smem[LDS_ELEMS];
+    body_pieces(M, N, Kp, alpha, PA, pa_plane, PB, pb_plane, beta, C, ldc, ws, splits, kper, prescale, smem);
+}
+#else
 // Same argument list as the FP32 variants; `prescale` (FP16 form only)
 // points to {2^eA, 2^eB, 2^-(eA+eB)}.
 extern "C" __global__ void __launch_bounds__(NT)
@@ -387,3 +584,4 @@ FF_CAT(FF_NAME, _v1)(int M, int N, int K, float alpha, const float* __restrict__
     __shared__ __attribute__((aligned(16))) short smem[LDS_ELEMS];
     body<false>(M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, ws, splits, kper, prescale, smem);
 }
+#endif

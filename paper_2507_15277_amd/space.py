@@ -87,7 +87,10 @@ class Variant:
     @property
     def lds_bytes(self):
         if self.prec:
-            return 2 * 2 * self.terms * (self.mwg + self.nwg) * (self.kwg + 8)
+            stage = 2 * self.terms * (self.mwg + self.nwg) * (self.kwg + 8)     # bytes
+            if self.lds == 2:
+                return 2 * (-(-stage // 1024) * 1024) + 1024
+            return 2 * stage
         stage = self.mwg * (self.kwg + 4) + self.kwg * (self.nwg + 4)
         red = (self.sk - 1) * self.mwg * self.nwg
         if self.lds == 2:
@@ -109,7 +112,7 @@ class Variant:
         if self.prec:
             form = PREC_NAMES[self.prec]
             n = f"sgemmx_{form}_m{self.mwg}n{self.nwg}k{self.kwg}_i{self.mi}_w{self.wm}x{self.wn}"
-            return n + (f"_p{self.sg}" if self.sg != 1 else "")
+            return n + (f"_p{self.sg}" if self.sg != 1 else "") + ("_l2" if self.lds == 2 else "")
         n = (f"sgemm_m{self.mwg}n{self.nwg}k{self.kwg}_i{self.mi}_w{self.wm}x{self.wn}"
              f"_s{self.sk}_v{self.vw}_l{self.lds}")
         if self.gm != 8:
@@ -124,7 +127,7 @@ class Variant:
         if self.prec:
             return {"FF_MWG": self.mwg, "FF_NWG": self.nwg, "FF_KWG": self.kwg, "FF_MI": self.mi,
                     "FF_WM": self.wm, "FF_WN": self.wn, "FF_PREC": self.prec, "FF_GM": self.gm,
-                    "FF_SG": self.sg, "FF_NAME": self.name}
+                    "FF_SG": self.sg, "FF_LDS": self.lds, "FF_NAME": self.name}
         return {"FF_MWG": self.mwg, "FF_NWG": self.nwg, "FF_KWG": self.kwg, "FF_MI": self.mi,
                 "FF_WM": self.wm, "FF_WN": self.wn, "FF_SK": self.sk, "FF_VW": self.vw,
                 "FF_LDS": self.lds, "FF_GM": self.gm, "FF_SG": self.sg, "FF_PD": self.pd,
@@ -137,6 +140,8 @@ class Variant:
         within the 128 MiB workspace); 0 for an empty product."""
         if M <= 0 or N <= 0:
             return 0
+        if self.prec and self.lds == 2:
+            K = -(-K // 64) * 64          # pre-split forms run over K padded to 64
         nb = -(-M // self.mwg) * -(-N // self.nwg)
         nkt = -(-K // self.kwg)
         if self.sg > 1 and nkt > 1 and have_ws:
@@ -161,12 +166,15 @@ MAX_SPLIT_LDS_BYTES = 160 * 1024
 
 def legal_split(v: Variant) -> bool:
     """Constraints of the split-precision kernel (csrc/sgemm_split.hip)."""
-    if v.mi not in (16, 32) or v.sk != 1 or v.sg not in SPLITS or v.lds != 1 or v.vw != 4 or v.pd != 1:
+    if v.mi not in (16, 32) or v.sk != 1 or v.sg not in SPLITS or v.lds not in (1, 2) or v.vw != 4 or v.pd != 1:
         return False
     if v.mwg % (v.wm * v.mi) or v.nwg % (v.wn * v.mi) or v.kwg % v.mk:
         return False
     if v.threads > MAX_THREADS or v.acc_regs > MAX_ACC or v.lds_bytes > MAX_SPLIT_LDS_BYTES:
         return False
+    if v.lds == 2:
+        # Pre-split: K is padded to 64, so a slab must divide it.
+        return 64 % v.kwg == 0
     # Staged FP32 slab values per thread (8 per load item).
     if (v.mwg + v.nwg) * v.kwg > MAX_STAGING * v.threads:
         return False
@@ -385,6 +393,22 @@ SPLIT_K_SHAPES = [
 ]
 
 
+# Pre-split shapes (LDS mode 2: pieces formed once per call, copied to LDS).
+# (MWG, NWG, KWG, MI, WM, WN, SG)
+PRESPLIT_SHAPES = [
+    (128, 128, 32, 32, 2, 2, 1),
+    (128, 128, 64, 32, 2, 2, 1),
+    (256, 128, 32, 32, 4, 2, 1),
+    (128, 256, 32, 32, 2, 4, 1),
+    (256, 256, 32, 32, 4, 2, 1),
+    (64, 64, 64, 32, 2, 2, 1),
+    (64, 64, 64, 32, 2, 2, 8),
+    (128, 128, 32, 32, 2, 2, 4),
+    (128, 128, 64, 16, 4, 4, 1),
+    (32, 32, 64, 32, 1, 1, 8),
+]
+
+
 def split_family(precs=(1, 2, 3)):
     out = []
     for prec in precs:
@@ -396,6 +420,11 @@ def split_family(precs=(1, 2, 3)):
     for prec in precs:
         for (mwg, nwg, kwg, mi, wm, wn, sg) in SPLIT_K_SHAPES:
             v = Variant(mwg, nwg, kwg, mi, wm, wn, 1, 4, 1, 8, sg, prec)
+            if legal(v):
+                out.append(v)
+    for prec in precs:
+        for (mwg, nwg, kwg, mi, wm, wn, sg) in PRESPLIT_SHAPES:
+            v = Variant(mwg, nwg, kwg, mi, wm, wn, 1, 4, 2, 8, sg, prec)
             if legal(v):
                 out.append(v)
     return out
