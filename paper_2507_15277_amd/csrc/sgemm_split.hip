@@ -72,6 +72,9 @@
 #ifndef FF_LDS
 #define FF_LDS 1
 #endif
+#ifndef FF_PD
+#define FF_PD 1
+#endif
 
 #define FF_CAT2(a, b) a##b
 #define FF_CAT(a, b) FF_CAT2(a, b)
@@ -81,6 +84,7 @@ namespace {
 constexpr int MWG = FF_MWG, NWG = FF_NWG, KWG = FF_KWG, MI = FF_MI;
 constexpr int WM = FF_WM, WN = FF_WN, PREC = FF_PREC, GM = FF_GM, SG = FF_SG;
 constexpr bool PRESPLIT = FF_LDS == 2;
+constexpr int NS = PRESPLIT ? FF_PD + 1 : 2;            // LDS stages (pre-split: PD slabs in flight)
 constexpr int TERMS = PREC == 1 ? 2 : (PREC == 2 ? 3 : 1);
 constexpr int KB = 8 * (64 / MI);        // MFMA k depth: 16 (MI 32) or 32 (MI 16)
 constexpr int WTM = MWG / WM, WTN = NWG / WN;
@@ -100,7 +104,7 @@ constexpr int STAGE = PRESPLIT ? (STAGE_RAW + 511) / 512 * 512 : STAGE_RAW;
 constexpr int NWI = STAGE / 512;                         // wave copies per stage
 constexpr int NWAVE = WM * WN;
 constexpr int DPS = (NWI + NWAVE - 1) / NWAVE;           // copies per wave per slab
-constexpr int LDS_ELEMS = 2 * STAGE + (PRESPLIT ? 512 : 0);
+constexpr int LDS_ELEMS = NS * STAGE + (PRESPLIT ? 512 : 0);
 constexpr int KPAD = 64;                                 // pre-split pieces: K padded to this
 
 static_assert(PREC >= 1 && PREC <= 3, "precision form");
@@ -111,7 +115,8 @@ static_assert(NT <= 1024, "work-group size");
 static_assert(SG >= 1, "split count");
 static_assert(FF_LDS == 1 || FF_LDS == 2, "staging mode");
 static_assert(KPAD % KWG == 0, "pre-split K padding must be whole slabs");
-static_assert(DPS <= 63, "wait count range");
+static_assert((NS - 1) * DPS <= 63, "wait count range");
+static_assert(FF_PD == 1 || (PRESPLIT && FF_PD == 2), "prefetch depth");
 
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
@@ -195,28 +200,34 @@ constexpr int NPAIRS = PREC == 1 ? 3 : (PREC == 2 ? 6 : 1);
 
 // The MFMAs of one LDS slab: every kept term product of the lane's A rows
 // and B columns, smallest first.
+// The fragments of step s + 1 are read while the products of step s issue.
 __device__ __forceinline__ void mma_slab(const short* sA, const short* sB, int arow, int bcol,
                                          acc_t (&acc)[RM][RN])
 {
-#pragma unroll
-    for (int s = 0; s < S; ++s) {
-        i16x8 av[TERMS][RM], bv[TERMS][RN];
+    i16x8 av[2][TERMS][RM], bv[2][TERMS][RN];
+    auto fragments = [&](int s, int buf) {
 #pragma unroll
         for (int q = 0; q < TERMS; ++q) {
 #pragma unroll
             for (int i = 0; i < RM; ++i)
-                av[q][i] = *reinterpret_cast<const i16x8*>(sA + q * A_TERM + arow + i * MI * LDK + s * KB);
+                av[buf][q][i] = *reinterpret_cast<const i16x8*>(sA + q * A_TERM + arow + i * MI * LDK + s * KB);
 #pragma unroll
             for (int j = 0; j < RN; ++j)
-                bv[q][j] = *reinterpret_cast<const i16x8*>(sB + q * B_TERM + bcol + j * MI * LDK + s * KB);
+                bv[buf][q][j] = *reinterpret_cast<const i16x8*>(sB + q * B_TERM + bcol + j * MI * LDK + s * KB);
         }
+    };
+    fragments(0, 0);
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+        if (s + 1 < S) fragments(s + 1, (s + 1) & 1);
 #pragma unroll
         for (int p = 0; p < NPAIRS; ++p) {
             const Pair pr = PREC == 1 ? kPairs3[p] : (PREC == 2 ? kPairs6[p] : kPairs1[p]);
 #pragma unroll
             for (int i = 0; i < RM; ++i)
 #pragma unroll
-                for (int j = 0; j < RN; ++j) acc[i][j] = mfma16(bv[pr.b][j], av[pr.a][i], acc[i][j]);
+                for (int j = 0; j < RN; ++j)
+                    acc[i][j] = mfma16(bv[s & 1][pr.b][j], av[s & 1][pr.a][i], acc[i][j]);
         }
     }
 }
@@ -412,7 +423,7 @@ typedef __attribute__((address_space(3))) void* lds_ptr;
 // Mp x Kp pieces of A (row m, k contiguous), PB TERMS planes of Np x Kp
 // pieces of B (row n, k contiguous), zero past M, N and K, so every copy is
 // in bounds and every slab is whole.  Slabs are copied into LDS with
-// load-to-LDS copies, two stages deep; unit u (16 bytes) of a stage holds
+// load-to-LDS copies, NS = PD + 1 stages deep; unit u (16 bytes) of a stage holds
 // pieces 8u..8u+7 of the stage image [term][row][LDK] (A rows, then B rows);
 // units in the row padding or past the image copy from PA itself.
 __device__ __forceinline__ void body_pieces(int M, int N, int Kp, float alpha, const short* __restrict__ PA,
@@ -471,26 +482,37 @@ __device__ __forceinline__ void body_pieces(int M, int N, int Kp, float alpha, c
         for (int j = 0; j < DPS; ++j) {
             const int wi = wid + j * NWAVE;
             const short* src = base[j] + (real[j] ? kt * KWG : 0);
-            short* dst = (wi < NWI) ? smem + st * STAGE + wi * 512 : smem + 2 * STAGE;
+            short* dst = (wi < NWI) ? smem + st * STAGE + wi * 512 : smem + NS * STAGE;
             __builtin_amdgcn_global_load_lds(src, (lds_ptr)dst, 16, 0, 0);
         }
     };
 
     const int arow = (wm * WTM + lr) * LDK + lh * 8;
     const int bcol = (wn * WTN + lr) * LDK + lh * 8;
-    issue(kt0, 0);
+#pragma unroll
+    for (int p = 0; p < NS - 1; ++p)
+        if (kt0 + p < kt1) issue(kt0 + p, p);
     int st = 0;
     for (int kt = kt0; kt < kt1; ++kt) {
-        // This slab's copies are done, and every wave is done with the other
-        // stage (the empty asm statements keep LDS accesses from moving across).
+        // This slab's copies are done when at most the later slabs' copies are
+        // outstanding (every wave issues DPS per slab), every wave's are after
+        // the barrier, and every wave is then done with the stage refilled next
+        // (the empty asm statements keep LDS accesses from moving across).
         asm volatile("" ::: "memory");
-        __builtin_amdgcn_s_waitcnt(waitcnt_vm(0));
+        if (kt + NS - 2 < kt1)
+            __builtin_amdgcn_s_waitcnt(waitcnt_vm((NS - 2) * DPS));
+        else
+            __builtin_amdgcn_s_waitcnt(waitcnt_vm(0));
         __builtin_amdgcn_s_barrier();
         asm volatile("" ::: "memory");
-        if (kt + 1 < kt1) issue(kt + 1, st ^ 1);
+        if (kt + NS - 1 < kt1) {
+            int nx = st + NS - 1;
+            if (nx >= NS) nx -= NS;
+            issue(kt + NS - 1, nx);
+        }
         const short* sA = smem + st * STAGE;
         mma_slab(sA, sA + TERMS * A_TERM, arow, bcol, acc);
-        st ^= 1;
+        if (++st == NS) st = 0;
     }
     __syncthreads();
     store_tile(acc, M, N, alpha, beta, C, ldc, unscale, ws, splits, part, m0, n0, wm, wn, lr, lh);

@@ -89,7 +89,7 @@ class Variant:
         if self.prec:
             stage = 2 * self.terms * (self.mwg + self.nwg) * (self.kwg + 8)     # bytes
             if self.lds == 2:
-                return 2 * (-(-stage // 1024) * 1024) + 1024
+                return (self.pd + 1) * (-(-stage // 1024) * 1024) + 1024
             return 2 * stage
         stage = self.mwg * (self.kwg + 4) + self.kwg * (self.nwg + 4)
         red = (self.sk - 1) * self.mwg * self.nwg
@@ -112,7 +112,8 @@ class Variant:
         if self.prec:
             form = PREC_NAMES[self.prec]
             n = f"sgemmx_{form}_m{self.mwg}n{self.nwg}k{self.kwg}_i{self.mi}_w{self.wm}x{self.wn}"
-            return n + (f"_p{self.sg}" if self.sg != 1 else "") + ("_l2" if self.lds == 2 else "")
+            return (n + (f"_p{self.sg}" if self.sg != 1 else "") + ("_l2" if self.lds == 2 else "")
+                    + (f"_d{self.pd}" if self.pd != 1 else ""))
         n = (f"sgemm_m{self.mwg}n{self.nwg}k{self.kwg}_i{self.mi}_w{self.wm}x{self.wn}"
              f"_s{self.sk}_v{self.vw}_l{self.lds}")
         if self.gm != 8:
@@ -127,7 +128,7 @@ class Variant:
         if self.prec:
             return {"FF_MWG": self.mwg, "FF_NWG": self.nwg, "FF_KWG": self.kwg, "FF_MI": self.mi,
                     "FF_WM": self.wm, "FF_WN": self.wn, "FF_PREC": self.prec, "FF_GM": self.gm,
-                    "FF_SG": self.sg, "FF_LDS": self.lds, "FF_NAME": self.name}
+                    "FF_SG": self.sg, "FF_LDS": self.lds, "FF_PD": self.pd, "FF_NAME": self.name}
         return {"FF_MWG": self.mwg, "FF_NWG": self.nwg, "FF_KWG": self.kwg, "FF_MI": self.mi,
                 "FF_WM": self.wm, "FF_WN": self.wn, "FF_SK": self.sk, "FF_VW": self.vw,
                 "FF_LDS": self.lds, "FF_GM": self.gm, "FF_SG": self.sg, "FF_PD": self.pd,
@@ -166,7 +167,9 @@ MAX_SPLIT_LDS_BYTES = 160 * 1024
 
 def legal_split(v: Variant) -> bool:
     """Constraints of the split-precision kernel (csrc/sgemm_split.hip)."""
-    if v.mi not in (16, 32) or v.sk != 1 or v.sg not in SPLITS or v.lds not in (1, 2) or v.vw != 4 or v.pd != 1:
+    if v.mi not in (16, 32) or v.sk != 1 or v.sg not in SPLITS or v.lds not in (1, 2) or v.vw != 4:
+        return False
+    if v.pd not in (1, 2) or (v.pd == 2 and v.lds != 2):
         return False
     if v.mwg % (v.wm * v.mi) or v.nwg % (v.wn * v.mi) or v.kwg % v.mk:
         return False
@@ -394,18 +397,26 @@ SPLIT_K_SHAPES = [
 
 
 # Pre-split shapes (LDS mode 2: pieces formed once per call, copied to LDS).
-# (MWG, NWG, KWG, MI, WM, WN, SG)
 PRESPLIT_SHAPES = [
-    (128, 128, 32, 32, 2, 2, 1),
-    (128, 128, 64, 32, 2, 2, 1),
-    (256, 128, 32, 32, 4, 2, 1),
-    (128, 256, 32, 32, 2, 4, 1),
-    (256, 256, 32, 32, 4, 2, 1),
-    (64, 64, 64, 32, 2, 2, 1),
-    (64, 64, 64, 32, 2, 2, 8),
-    (128, 128, 32, 32, 2, 2, 4),
-    (128, 128, 64, 16, 4, 4, 1),
-    (32, 32, 64, 32, 1, 1, 8),
+    # (MWG, NWG, KWG, MI, WM, WN, SG, PD)
+    (128, 128, 32, 32, 2, 2, 1, 1),
+    (128, 128, 64, 32, 2, 2, 1, 1),
+    (256, 128, 32, 32, 4, 2, 1, 1),
+    (128, 256, 32, 32, 2, 4, 1, 1),
+    (256, 256, 32, 32, 4, 2, 1, 1),
+    (64, 64, 64, 32, 2, 2, 1, 1),
+    (64, 64, 64, 32, 2, 2, 8, 1),
+    (128, 128, 32, 32, 2, 2, 4, 1),
+    (128, 128, 64, 16, 4, 4, 1, 1),
+    (32, 32, 64, 32, 1, 1, 8, 1),
+    (128, 128, 32, 32, 2, 2, 1, 2),
+    (128, 128, 64, 32, 2, 2, 1, 2),
+    (256, 128, 32, 32, 4, 2, 1, 2),
+    (128, 256, 32, 32, 2, 4, 1, 2),
+    (256, 256, 32, 32, 4, 2, 1, 2),
+    (64, 64, 64, 32, 2, 2, 8, 2),
+    (128, 128, 32, 32, 2, 2, 4, 2),
+    (128, 128, 16, 32, 2, 2, 1, 2),
 ]
 
 
@@ -423,8 +434,8 @@ def split_family(precs=(1, 2, 3)):
             if legal(v):
                 out.append(v)
     for prec in precs:
-        for (mwg, nwg, kwg, mi, wm, wn, sg) in PRESPLIT_SHAPES:
-            v = Variant(mwg, nwg, kwg, mi, wm, wn, 1, 4, 2, 8, sg, prec)
+        for (mwg, nwg, kwg, mi, wm, wn, sg, pd) in PRESPLIT_SHAPES:
+            v = Variant(mwg, nwg, kwg, mi, wm, wn, 1, 4, 2, 8, sg, prec, pd)
             if legal(v):
                 out.append(v)
     return out
