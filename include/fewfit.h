@@ -54,7 +54,7 @@ extern "C" {
 #define FF_ERR_ARCH (-103)     /* set or code object built for another GPU */
 #define FF_ERR_HIP (-104)      /* a HIP runtime call failed */
 #define FF_ERR_IO (-105)       /* file missing or unreadable */
-#define FF_ERR_TOO_LARGE (-106)/* M, N or K above INT32_MAX */
+#define FF_ERR_TOO_LARGE (-106)/* M, N or K above INT32_MAX, or pieces beyond the workspace */
 #define FF_ERR_ARG (-107)      /* other invalid argument (tuning ABI) */
 
 /* Precision forms: how the FP32 product is formed (accumulation and the

@@ -599,13 +599,12 @@ FF_EXPORT int ptune_assign(int nv, int ns, const double* t, int k, const int* ka
 namespace {
 
 // L1 distance over log2 sizes (sizes below 1 count as 1).
-// L1 distances over log2 sizes (sizes below 1 count as 1).  train_lg, when
-// given, holds the training shapes' log2 sizes already computed.
+// L1 distances over log2 sizes (sizes below 1 count as 1) into d[0..ntrain).
+// train_lg, when given, holds the training shapes' log2 sizes already computed.
 void shape_distances(int ntrain, const int64_t* train_mnk, const double* train_lg, int64_t M, int64_t N, int64_t K,
-                     std::vector<double>& d)
+                     double* d)
 {
     const double q[3] = {ptune_log2_size(M), ptune_log2_size(N), ptune_log2_size(K)};
-    d.resize(ntrain);
     for (int i = 0; i < ntrain; ++i) {
         double t[3];
         for (int c = 0; c < 3; ++c) t[c] = train_lg ? train_lg[3 * i + c] : ptune_log2_size(train_mnk[3 * i + c]);
@@ -618,8 +617,8 @@ void shape_distances(int ntrain, const int64_t* train_mnk, const double* train_l
 FF_EXPORT int ptune_nearest(int ntrain, const int64_t* train_mnk, int64_t M, int64_t N, int64_t K)
 {
     if (ntrain < 1 || train_mnk == nullptr) return FF_ERR_ARG;
-    std::vector<double> d;
-    shape_distances(ntrain, train_mnk, nullptr, M, N, K, d);
+    std::vector<double> d(ntrain);
+    shape_distances(ntrain, train_mnk, nullptr, M, N, K, d.data());
     int best = 0;
     for (int i = 1; i < ntrain; ++i)
         if (d[i] < d[best]) best = i;
@@ -637,9 +636,17 @@ int ptune_dispatch_lw(int ntrain, const int64_t* train_mnk, const double* train_
                       const double* cost, const double* lw_train, const double* lw_query, int64_t M, int64_t N,
                       int64_t K)
 {
-    std::vector<double> d;
+    // Distances on the stack for the usual small training sets (this runs on
+    // every dispatched sgemm call).
+    double dsmall[64];
+    std::vector<double> dbig;
+    double* d = dsmall;
+    if (ntrain > 64) {
+        dbig.resize(ntrain);
+        d = dbig.data();
+    }
     shape_distances(ntrain, train_mnk, train_lg, M, N, K, d);
-    const double dmin = *std::min_element(d.begin(), d.end());
+    const double dmin = *std::min_element(d, d + ntrain);
     int bj = -1;
     double bs = kInf;
     for (int j = 0; j < k; ++j) {

@@ -113,3 +113,22 @@ def test_fp16_scale_follows_the_data(split_loaded):
         C1, _ = run_gemm(vid, A, B, None, 1.0, 0.0)
         C2, _ = run_gemm(vid, A * np.float32(2.0 ** 20), B * np.float32(2.0 ** -30), None, 1.0, 0.0)
         assert np.array_equal(C1 * np.float32(2.0 ** -10), C2), name
+
+
+def test_presplit_workspace_limit(split_loaded):
+    # A pre-split call whose pieces exceed the 1 GiB pieces workspace is
+    # refused before any launch: bf16x6 keeps 3 pieces per value, and
+    # 2 B * 3 * (Mp + Np) * Kp = 1.6e9 bytes for 16384 x 16384 x 8192.
+    vid = next(v for v, name, form in split_loaded if form == "bf16x6" and name.endswith("_l2"))
+    M = N = 16384
+    K = 8192
+    A = torch.empty(M, K, device="cuda")
+    B = torch.empty(K, N, device="cuda")
+    C = torch.full((M, N), 7.0, device="cuda")   # full size; never written: the call fails first
+    rc = abi.lib().sgemm_variant(vid, M, N, K, 1.0, A.data_ptr(), K, B.data_ptr(), N, 0.0,
+                                 C.data_ptr(), N, None)
+    assert rc == abi.FF_ERR_TOO_LARGE, (rc, abi.last_error())
+    assert "pieces" in abi.last_error()
+    torch.cuda.synchronize()
+    assert bool(torch.all(C == 7.0))
+
