@@ -1,0 +1,97 @@
+"""The vendor library's FP32 GEMM beside the k-variant set, on the 27-shape grid.
+
+Times torch's FP32 matrix product on the device (rocBLAS / hipBLASLt
+underneath; gfx950 has no reduced-precision FP32 MFMA, so it is a true FP32
+SGEMM) and this library's dispatched ``sgemm`` with the same protocol as
+``bench.py``: seeded uniform operands resident in HBM, per shape a loop of
+back-to-back calls bracketed by HIP events, the median of several trials.
+Context for the results, not part of the measured path.
+
+    python -m paper_2507_15277_amd.vendor_compare [--k 4] [--out vendor.json]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+
+import numpy as np
+
+from . import abi, datagen, tuned
+
+TARGET_MS = 1.0
+
+
+def _time_loop(fn, reps, trials=5):
+    import torch
+
+    fn()
+    torch.cuda.synchronize()
+    out = []
+    for _ in range(trials):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        out.append(e0.elapsed_time(e1) / reps)
+    return float(np.median(out))
+
+
+def run(k=4, log=print):
+    import torch
+
+    torch.backends.cuda.matmul.allow_tf32 = False
+    assert abi.variant_set_load(tuned.set_path(k)) == k
+    L = abi.lib()
+    stream = torch.cuda.current_stream()
+    h = stream.cuda_stream
+    rows = []
+    for (M, N, K) in datagen.grid27():
+        A, B, _ = datagen.gemm_operands(3, M, N, K)
+        dA, dB = torch.from_numpy(A).cuda(), torch.from_numpy(B).cuda()
+        dC = torch.empty(M, N, device="cuda")
+        dT = torch.empty(M, N, device="cuda")
+        pa, pb, pc = dA.data_ptr(), dB.data_ptr(), dC.data_ptr()
+
+        def ours():
+            rc = L.sgemm(M, N, K, 1.0, pa, K, pb, N, 0.0, pc, N, h)
+            if rc:
+                raise RuntimeError(abi.last_error())
+
+        def vendor():
+            torch.mm(dA, dB, out=dT)
+
+        t1 = _time_loop(vendor, 3, trials=1)
+        reps = max(1, min(1000, int(round(TARGET_MS / max(t1, 1e-4)))))
+        ms_v = _time_loop(vendor, reps)
+        ms_o = _time_loop(ours, reps)
+        fl = 2.0 * M * N * K
+        diff = float((dC - dT).abs().max())
+        rows.append({"M": M, "N": N, "K": K, "tflops_set": fl / ms_o / 1e9, "tflops_vendor": fl / ms_v / 1e9,
+                     "variant": abi.variant_select(M, N, K), "max_abs_diff": diff})
+        log(f"[vendor] {M}x{N}x{K}: set {fl / ms_o / 1e9:7.1f} TFLOP/s, vendor {fl / ms_v / 1e9:7.1f} TFLOP/s "
+            f"(x{ms_v / ms_o:.2f}), max |diff| {diff:.2e}")
+    gm = lambda key: math.exp(sum(math.log(r[key]) for r in rows) / len(rows))  # noqa: E731
+    rep = {"k": k, "shapes": rows, "geomean_tflops_set": gm("tflops_set"), "geomean_tflops_vendor": gm("tflops_vendor"),
+           "geomean_speedup": math.exp(sum(math.log(r["tflops_set"] / r["tflops_vendor"]) for r in rows) / len(rows)),
+           "vendor": f"torch {torch.__version__} torch.mm (FP32)"}
+    log(f"[vendor] geomean: set {rep['geomean_tflops_set']:.1f} TFLOP/s, vendor {rep['geomean_tflops_vendor']:.1f} "
+        f"TFLOP/s, speedup x{rep['geomean_speedup']:.2f}")
+    return rep
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
+    ap.add_argument("--k", type=int, default=4)
+    ap.add_argument("--out", default=None)
+    args = ap.parse_args(argv)
+    rep = run(args.k, log=lambda s: print(s, flush=True))
+    if args.out:
+        with open(args.out, "w") as f:
+            json.dump(rep, f, indent=1)
+
+
+if __name__ == "__main__":
+    main()
