@@ -417,6 +417,14 @@ PRESPLIT_SHAPES = [
     (64, 64, 64, 32, 2, 2, 8, 2),
     (128, 128, 32, 32, 2, 2, 4, 2),
     (128, 128, 16, 32, 2, 2, 1, 2),
+    # Eight waves (two per SIMD) and K-step 16, for the three-piece form's LDS budget.
+    (128, 128, 32, 32, 4, 2, 1, 1),
+    (128, 128, 32, 32, 4, 2, 1, 2),
+    (128, 128, 16, 32, 4, 2, 1, 2),
+    (256, 128, 16, 32, 4, 2, 1, 1),
+    (256, 128, 16, 32, 4, 2, 1, 2),
+    (128, 256, 16, 32, 2, 4, 1, 1),
+    (64, 64, 64, 32, 2, 2, 4, 2),
 ]
 
 
