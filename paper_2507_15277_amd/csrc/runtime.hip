@@ -479,10 +479,11 @@ int launch_variant(const Variant& v, int64_t M, int64_t N, int64_t K, float alph
         int vecA = (K % 4 == 0 && lda % 4 == 0 && aligned_for(A, 4)) ? 1 : 0;
         void* aa[] = {&Mi, &Ki, (void*)&A, &la, &vecA, (void*)&prescale, (void*)&PA, &Mp, &Kp, &pa_plane};
         void* ab[] = {&Ki, &Ni, (void*)&B, &lb, (void*)&prescale, (void*)&PB, &Np, &Kp, &pb_plane};
-        const int64_t ia = (int64_t)Mp * (Kp / 8), ib = (int64_t)Np * (Kp / 8);
+        const int64_t ia = (int64_t)Mp * (Kp / 8);
+        const int64_t gb = (int64_t)((Np + 63) / 64) * (Kp / 64);     // 64 x 64 tiles of B
         e = hipModuleLaunchKernel(v.fpa, (unsigned)((ia + 255) / 256), 1, 1, 256, 1, 1, 0, s, aa, nullptr);
         if (e == hipSuccess)
-            e = hipModuleLaunchKernel(v.fpb, (unsigned)((ib + 255) / 256), 1, 1, 256, 1, 1, 0, s, ab, nullptr);
+            e = hipModuleLaunchKernel(v.fpb, (unsigned)gb, 1, 1, 256, 1, 1, 0, s, ab, nullptr);
         if (e != hipSuccess) return hip_fail(e, ("launch split passes of " + v.name).c_str());
         void* ag[] = {&Mi, &Ni, &Kp, &alpha, (void*)&PA, &pa_plane, (void*)&PB, &pb_plane, &beta, (void*)&C, &lc,
                       (void*)&ws, &splits, &kper, (void*)&prescale};

@@ -559,22 +559,41 @@ FF_CAT(FF_NAME, _pa)(int M, int K, const float* __restrict__ A, long lda, int ve
     put_pieces(x, PREC == 3 ? prescale[0] : 1.0f, P + (long)m * Kp + k, plane);
 }
 
-// Split pass over B (K x N, row stride ldb), transposed: item (n, k8) writes
-// pieces of B[8 k8 .. 8 k8 + 7][n] to row n of the Np x Kp planes; zeros past
-// N and K.  Consecutive threads take consecutive n, so each load instruction
-// reads consecutive addresses.
+// Split pass over B (K x N, row stride ldb), transposed to row n of the
+// Np x Kp planes; zeros past N and K.  One block moves a 64 (k) x 64 (n)
+// tile through LDS: it reads rows of B with consecutive threads on
+// consecutive n, and writes with 8 consecutive threads covering 64
+// consecutive k of one n (128 contiguous bytes per piece plane).  Grid:
+// ceil(Np / 64) x (Kp / 64) blocks, n tiles fastest.
 extern "C" __global__ void __launch_bounds__(256)
 FF_CAT(FF_NAME, _pb)(int K, int N, const float* __restrict__ B, long ldb, const float* __restrict__ prescale,
                      short* __restrict__ P, int Np, int Kp, long plane)
 {
-    const long items = (long)Np * (Kp / 8);
-    const long idx = (long)blockIdx.x * 256 + threadIdx.x;
-    if (idx >= items) return;
-    const int n = (int)(idx % Np), k = (int)(idx / Np) * 8;
-    float x[8];
+    __shared__ float tile[64][65];
+    const int ntiles = (Np + 63) / 64;
+    const int n0 = (blockIdx.x % ntiles) * 64, k0 = (blockIdx.x / ntiles) * 64;
+    const int t = threadIdx.x;
+    {
+        const int nl = t & 63, kb = t >> 6;
+        const int n = n0 + nl;
 #pragma unroll
-    for (int e = 0; e < 8; ++e) x[e] = (n < N && k + e < K) ? B[(long)(k + e) * ldb + n] : 0.0f;
-    put_pieces(x, PREC == 3 ? prescale[1] : 1.0f, P + (long)n * Kp + k, plane);
+        for (int i = 0; i < 16; ++i) {
+            const int kl = kb + 4 * i, k = k0 + kl;
+            tile[kl][nl] = (n < N && k < K) ? B[(long)k * ldb + n] : 0.0f;
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+        const int item = t + 256 * j;
+        const int nl = item >> 3, kc = item & 7;
+        if (n0 + nl < Np) {
+            float x[8];
+#pragma unroll
+            for (int e = 0; e < 8; ++e) x[e] = tile[8 * kc + e][nl];
+            put_pieces(x, PREC == 3 ? prescale[1] : 1.0f, P + (long)(n0 + nl) * Kp + k0 + 8 * kc, plane);
+        }
+    }
 }
 
 // GEMM on the pieces (see body_pieces).
