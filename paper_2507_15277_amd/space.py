@@ -425,6 +425,11 @@ PRESPLIT_SHAPES = [
     (256, 128, 16, 32, 4, 2, 1, 2),
     (128, 256, 16, 32, 2, 4, 1, 1),
     (64, 64, 64, 32, 2, 2, 4, 2),
+    # Larger blocks per wave (128 x 64 or 64 x 128: fewer fragment reads per MFMA).
+    (256, 128, 16, 32, 2, 2, 1, 1),
+    (256, 128, 32, 32, 2, 2, 1, 1),
+    (128, 256, 16, 32, 2, 2, 1, 1),
+    (256, 128, 16, 32, 2, 2, 1, 2),
 ]
 
 
@@ -435,14 +440,16 @@ def split_family(precs=(1, 2, 3)):
             v = Variant(mwg, nwg, kwg, mi, wm, wn, 1, 4, 1, 8, 1, prec)
             if legal(v):
                 out.append(v)
-    # Appended after all forms' plain shapes, so earlier ids stay put.
-    for prec in precs:
-        for (mwg, nwg, kwg, mi, wm, wn, sg) in SPLIT_K_SHAPES:
+    # Later lists follow, shape by shape with the forms inside, so a shape
+    # appended to a list adds ids at the end and earlier ids keep their
+    # variants (tables and set files refer to variants by id).
+    for (mwg, nwg, kwg, mi, wm, wn, sg) in SPLIT_K_SHAPES:
+        for prec in precs:
             v = Variant(mwg, nwg, kwg, mi, wm, wn, 1, 4, 1, 8, sg, prec)
             if legal(v):
                 out.append(v)
-    for prec in precs:
-        for (mwg, nwg, kwg, mi, wm, wn, sg, pd) in PRESPLIT_SHAPES:
+    for (mwg, nwg, kwg, mi, wm, wn, sg, pd) in PRESPLIT_SHAPES:
+        for prec in precs:
             v = Variant(mwg, nwg, kwg, mi, wm, wn, 1, 4, 2, 8, sg, prec, pd)
             if legal(v):
                 out.append(v)

@@ -125,13 +125,15 @@ def operands(cfg, M, N, K, beta, data):
     return datagen.gemm_operands(cfg, M, N, K, beta=beta)
 
 
-def load_rows(path, khash=None):
+def load_rows(path, khash=None, directory=VARIANT_DIR):
     """Complete rows of a table file (a truncated last line is skipped).
     ``khash``: a build hash or a set of them; rows of other builds are
-    dropped."""
+    dropped.  Rows whose variant id names another variant in the current
+    manifest (ids move when the family changes) are dropped too."""
     rows = []
     if not os.path.exists(path):
         return rows
+    names = dict(read_manifest(directory)) if os.path.exists(os.path.join(directory, "manifest.txt")) else None
     with open(path) as f:
         for line in f:
             line = line.strip()
@@ -140,6 +142,8 @@ def load_rows(path, khash=None):
             try:
                 r = json.loads(line)
             except json.JSONDecodeError:
+                continue
+            if names is not None and names.get(r.get("variant")) != r.get("name"):
                 continue
             if khash is None or r.get("build") in ({khash} if isinstance(khash, str) else khash):
                 rows.append(r)
