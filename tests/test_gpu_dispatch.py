@@ -84,3 +84,60 @@ def test_sgemm_through_set(cus, shape):
     Cref, S, T = oracle.ref_gemm(A, B)
     tol = oracle.gemm_tolerance(K, 1.0, 0.0, S, T, None)
     assert np.all(np.abs(C.astype(np.float64) - Cref) <= tol), shape
+
+
+def _variant_id(name):
+    for line in open(os.path.join(tuned.VARIANT_DIR, "manifest.txt")):
+        f = line.split()
+        if not line.startswith("#") and f[1] == name:
+            return int(f[0])
+    raise KeyError(name)
+
+
+def test_dispatch_path_graph_replays(cus):
+    # The calls a user would capture: a K-split FP32 variant (GEMM, then the
+    # fixed-order reduction) and a pre-split form (two split passes, GEMM,
+    # reduction), captured once and replayed three times with eager work in
+    # between.  Every replay must reproduce the eager result bit for bit.
+    abi.variant_manifest_load(tuned.VARIANT_DIR)
+    fp32_split = next(int(l.split()[0]) for l in open(os.path.join(tuned.VARIANT_DIR, "manifest.txt"))
+                      if not l.startswith("#") and int(l.split()[12]) > 1 and int(l.split()[13]) == 0)
+    presplit = next(int(l.split()[0]) for l in open(os.path.join(tuned.VARIANT_DIR, "manifest.txt"))
+                    if not l.startswith("#") and int(l.split()[13]) == 2 and int(l.split()[10]) == 2
+                    and int(l.split()[12]) > 1)
+    M, N, K = 192, 160, 1000
+    A, B, C0 = datagen.gemm_operands(51, M, N, K, beta=0.5)
+    dA, dB = torch.from_numpy(A).cuda(), torch.from_numpy(B).cuda()
+    C1 = torch.from_numpy(C0).cuda()
+    C2 = torch.from_numpy(C0).cuda()
+    start1, start2 = C1.clone(), C2.clone()
+
+    def calls(stream):
+        abi.sgemm_variant(fp32_split, M, N, K, 1.25, dA, K, dB, N, 0.5, C1, N, stream)
+        abi.sgemm_variant(presplit, M, N, K, 1.25, dA, K, dB, N, 0.5, C2, N, stream)
+
+    calls(torch.cuda.current_stream())
+    torch.cuda.synchronize()
+    eager1, eager2 = C1.clone(), C2.clone()
+    Cref, S, T = oracle.ref_gemm(A, B, 1.25, 0.5, C0)
+    tol = oracle.gemm_tolerance(K, 1.25, 0.5, S, T, C0)
+    assert np.all(np.abs(eager1.cpu().numpy().astype(np.float64) - Cref) <= tol)
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    C1.copy_(start1)
+    C2.copy_(start2)
+    with torch.cuda.stream(side):
+        calls(side)                                      # warm the side stream
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        calls(torch.cuda.current_stream())
+    for r in range(3):
+        C1.copy_(start1)                                 # eager work between replays
+        C2.copy_(start2)
+        torch.cuda.synchronize()
+        graph.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(C1, eager1), f"replay {r}: K-split FP32 result differs"
+        assert torch.equal(C2, eager2), f"replay {r}: pre-split result differs"
