@@ -334,10 +334,27 @@ int ptune_kmeans(int nv, int ns, const double *t, int nsel, const int *shapes, i
  * thresholds halfway between consecutive distinct values; ties to the lower
  * leaf, feature and threshold).  Each leaf's mean vector contributes its best
  * variant as in ptune_kmeans.  Writes the sorted set (returns its size) and
- * each shape's leaf.
+ * each shape's leaf; when node_feat, node_thr and node_child are given
+ * (2k - 1 entries, node_child 2 per node), the tree as ptune_tree_route
+ * reads it, and when leaf_variant is given (k entries), each leaf's variant.
  */
 int ptune_tree(int nv, int ns, const double *t, int nsel, const int *shapes, int nfeat,
-               const double *features, int k, int *kappa_out, int *leaf_out);
+               const double *features, int k, int *kappa_out, int *leaf_out,
+               int *node_feat, double *node_thr, int *node_child, int *leaf_variant);
+
+/*
+ * The tree of Sec. IV-C-3 estimates the performance vector of any
+ * environment, so it also routes an unseen input to a leaf: the leaf of
+ * feature vector x[0..nfeat) in the tree ptune_tree wrote (node_feat,
+ * node_thr, node_child over nnodes = 2 * leaves - 1 nodes; node 0 the root;
+ * an internal node n sends x[node_feat[n]] <= node_thr[n] to node
+ * node_child[2n], else to node_child[2n + 1]; a leaf node has node_feat -1
+ * and its leaf index in node_child[2n]).  With ptune_tree's leaf_variant
+ * (the variant each leaf contributed), an unseen input gets its leaf's
+ * variant.  Returns the leaf index, or FF_ERR_ARG for a malformed tree.
+ */
+int ptune_tree_route(int nnodes, const int *node_feat, const double *node_thr,
+                     const int *node_child, int nfeat, const double *x);
 
 /*
  * For each of the nsel shapes, the member of kappa with the lowest time

@@ -271,10 +271,10 @@ def performance_vectors(times, shapes):
     return pts
 
 
-def _pick_distinct(vectors, k, nv):
+def _pick_each(vectors, k, nv):
     """Best variant (largest component, lowest index on ties) of each
-    representative vector; a variant already taken is replaced by the
-    vector's next best.  Returns the sorted set."""
+    representative vector, in order; a variant already taken is replaced by
+    the vector's next best; at most k."""
     chosen = []
     for vec in vectors:
         order = sorted(range(nv), key=lambda v: (-vec[v], v))
@@ -282,7 +282,12 @@ def _pick_distinct(vectors, k, nv):
             if v not in chosen:
                 chosen.append(v)
                 break
-    return tuple(sorted(chosen[:k]))
+    return chosen[:k]
+
+
+def _pick_distinct(vectors, k, nv):
+    """The sorted set of ``_pick_each``."""
+    return tuple(sorted(_pick_each(vectors, k, nv)))
 
 
 def kmeans_select(times, k, shapes, init, max_iter=100):
@@ -314,14 +319,14 @@ def kmeans_select(times, k, shapes, init, max_iter=100):
 
 # --- Sec. IV-C-3: decision tree with |kappa| leaves ----------------------------
 
-def tree_select(times, k, shapes, features):
-    """Regression tree from environment features to performance vectors,
-    grown best first to k leaves: repeatedly split the leaf whose best split
-    lowers the summed squared error of the vectors most (thresholds halfway
-    between consecutive distinct feature values; ties to the lower leaf,
-    feature, threshold); each leaf's representative is the mean vector of
-    its environments and contributes its best variant.
-    Returns (kappa, leaf index of each environment)."""
+def tree_model(times, k, shapes, features):
+    """The tree of ``tree_select`` as a model: (kappa, leaf of each
+    environment, nodes, leaf variants).  ``nodes[n]`` is (feature, threshold,
+    left node, right node) for an internal node and (-1, 0.0, leaf index, -1)
+    for a leaf; node 0 is the root and a split turns a leaf node into an
+    internal node whose children are appended, left first.  ``leaf
+    variants[l]`` is the variant leaf l contributed (its mean vector's best,
+    or its next best if an earlier leaf took it)."""
     pts = performance_vectors(times, shapes)
     nv = len(times)
 
@@ -346,6 +351,8 @@ def tree_select(times, k, shapes, features):
         return best
 
     leaves = [list(range(len(pts)))]
+    leaf_node = [0]
+    nodes = [None]
     while len(leaves) < k:
         cands = []
         for li, idx in enumerate(leaves):
@@ -354,11 +361,40 @@ def tree_select(times, k, shapes, features):
                 cands.append((bs[0], li, bs))
         if not cands:
             break
-        gain, li, bs = max(cands, key=lambda c: (c[0], -c[1]))
-        leaves[li:li + 1] = [bs[3], bs[4]]
+        _, li, (gain, f, thr, left, right) = max(cands, key=lambda c: (c[0], -c[1]))
+        n, a, b = leaf_node[li], len(nodes), len(nodes) + 1
+        nodes[n] = (f, thr, a, b)
+        nodes += [None, None]
+        leaves[li:li + 1] = [left, right]
+        leaf_node[li:li + 1] = [a, b]
+    for li, n in enumerate(leaf_node):
+        nodes[n] = (-1, 0.0, li, -1)
     reps = [[sum(pts[i][v] for i in idx) / len(idx) for v in range(nv)] for idx in leaves]
     leaf_of = [0] * len(pts)
     for li, idx in enumerate(leaves):
         for i in idx:
             leaf_of[i] = li
-    return _pick_distinct(reps, k, nv), leaf_of
+    each = _pick_each(reps, k, nv)
+    return tuple(sorted(each)), leaf_of, nodes, each
+
+
+def tree_route(nodes, x):
+    """Leaf index of feature vector x: from the root, x[f] <= threshold goes
+    to the left child."""
+    n = 0
+    while nodes[n][0] >= 0:
+        f, thr, left, right = nodes[n]
+        n = left if x[f] <= thr else right
+    return nodes[n][2]
+
+
+def tree_select(times, k, shapes, features):
+    """Regression tree from environment features to performance vectors,
+    grown best first to k leaves: repeatedly split the leaf whose best split
+    lowers the summed squared error of the vectors most (thresholds halfway
+    between consecutive distinct feature values; ties to the lower leaf,
+    feature, threshold); each leaf's representative is the mean vector of
+    its environments and contributes its best variant.
+    Returns (kappa, leaf index of each environment)."""
+    kappa, leaf_of, _, _ = tree_model(times, k, shapes, features)
+    return kappa, leaf_of

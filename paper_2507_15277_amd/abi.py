@@ -30,7 +30,8 @@ EXPORTS = ("sgemm", "sgemm_form", "variant_set_load", "variant_select", "variant
            "variant_manifest_load", "variant_count", "variant_info", "sgemm_variant",
            "sgemm_time", "screen_reference", "screen_compare", "ptune_postprocess",
            "ptune_cost", "ptune_select", "ptune_assign", "ptune_nearest", "ptune_dispatch",
-           "ptune_select_total", "ptune_kmeans", "ptune_tree", "sgemm_grouped_plan", "sgemm_grouped")
+           "ptune_select_total", "ptune_kmeans", "ptune_tree", "ptune_tree_route", "sgemm_grouped_plan",
+           "sgemm_grouped")
 
 
 class FewfitError(RuntimeError):
@@ -75,7 +76,8 @@ def lib():
         L.sgemm_grouped.argtypes = [i32, i32, vp, vp, i32, f32, f32, i32, vp]
         L.ptune_select_total.argtypes = [i32, i32, vp, i32, vp, vp, i32, i32, vp, vp, vp]
         L.ptune_kmeans.argtypes = [i32, i32, vp, i32, vp, i32, vp, i32, vp, vp, vp]
-        L.ptune_tree.argtypes = [i32, i32, vp, i32, vp, i32, vp, i32, vp, vp]
+        L.ptune_tree.argtypes = [i32, i32, vp, i32, vp, i32, vp, i32, vp, vp, vp, vp, vp, vp]
+        L.ptune_tree_route.argtypes = [i32, vp, vp, vp, i32, vp]
         for name in EXPORTS:
             if name != "fewfit_last_error":
                 getattr(L, name).restype = i32
@@ -329,7 +331,9 @@ def ptune_kmeans(t, k, shapes, init, max_iter=100):
     return tuple(int(x) for x in kap[:n]), [int(a) for a in asg], it.value
 
 
-def ptune_tree(t, k, shapes, features):
+def ptune_tree(t, k, shapes, features, model=False):
+    """(kappa, leaf of each shape); with model=True also the tree
+    (node_feat, node_thr, node_child) and each leaf's variant."""
     import numpy as np
     t = _table(t)
     nv, ns = t.shape
@@ -338,6 +342,27 @@ def ptune_tree(t, k, shapes, features):
     kap = np.empty(k, np.int32)
     n_pts = ns if s is None else nsel
     leaf = np.empty(n_pts, np.int32)
+    nf = np.full(2 * k - 1, -2, np.int32)
+    nt = np.zeros(2 * k - 1, np.float64)
+    nc = np.full(2 * (2 * k - 1), -2, np.int32)
+    lv = np.full(k, -1, np.int32)
     n = _check(lib().ptune_tree(nv, ns, t.ctypes.data, nsel, None if s is None else s.ctypes.data, f.shape[1],
-                                f.ctypes.data, k, kap.ctypes.data, leaf.ctypes.data))
-    return tuple(int(x) for x in kap[:n]), [int(x) for x in leaf]
+                                f.ctypes.data, k, kap.ctypes.data, leaf.ctypes.data, nf.ctypes.data,
+                                nt.ctypes.data, nc.ctypes.data, lv.ctypes.data))
+    out = (tuple(int(x) for x in kap[:n]), [int(x) for x in leaf])
+    if not model:
+        return out
+    nleaves = int(leaf.max()) + 1 if leaf.size else 1
+    nn = 2 * nleaves - 1
+    return out + (nf[:nn].copy(), nt[:nn].copy(), nc[:2 * nn].copy(), [int(x) for x in lv[:nleaves]])
+
+
+def ptune_tree_route(node_feat, node_thr, node_child, x):
+    """Leaf index of feature vector x in a tree written by ptune_tree."""
+    import numpy as np
+    nf = np.ascontiguousarray(node_feat, dtype=np.int32)
+    nt = np.ascontiguousarray(node_thr, dtype=np.float64)
+    nc = np.ascontiguousarray(node_child, dtype=np.int32)
+    xv = np.ascontiguousarray(x, dtype=np.float64)
+    return _check(lib().ptune_tree_route(nf.size, nf.ctypes.data, nt.ctypes.data, nc.ctypes.data, xv.size,
+                                         xv.ctypes.data))

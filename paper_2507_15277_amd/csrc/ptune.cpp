@@ -399,7 +399,10 @@ std::vector<std::vector<double>> perf_vectors(int nv, int ns, const double* t, c
 
 // The best variant of each representative vector; a variant already taken
 // is replaced by that vector's next best.  Sorted, at most k.
-std::vector<int> pick_distinct(const std::vector<std::vector<double>>& reps, int k, int nv)
+// Each representative's variant (largest component, lowest id on ties; a
+// variant already taken goes to the representative's next best), in
+// representative order, until k are chosen.
+std::vector<int> pick_each(const std::vector<std::vector<double>>& reps, int k, int nv)
 {
     std::vector<int> chosen;
     for (const auto& vec : reps) {
@@ -413,6 +416,12 @@ std::vector<int> pick_distinct(const std::vector<std::vector<double>>& reps, int
             }
         if ((int)chosen.size() == k) break;
     }
+    return chosen;
+}
+
+std::vector<int> pick_distinct(const std::vector<std::vector<double>>& reps, int k, int nv)
+{
+    std::vector<int> chosen = pick_each(reps, k, nv);
     std::sort(chosen.begin(), chosen.end());
     return chosen;
 }
@@ -498,6 +507,8 @@ double leaf_sse(const std::vector<std::vector<double>>& pts, const std::vector<i
 struct Split {
     bool ok = false;
     double gain = 0.0;
+    int f = -1;          // feature and threshold: x[f] <= thr goes left
+    double thr = 0.0;
     std::vector<int> left, right;
 };
 
@@ -519,6 +530,8 @@ Split best_split(const std::vector<std::vector<double>>& pts, const std::vector<
             if (!b.ok || gain > b.gain + 1e-12) {
                 b.ok = true;
                 b.gain = gain;
+                b.f = f;
+                b.thr = thr;
                 b.left = l;
                 b.right = r;
             }
@@ -530,7 +543,8 @@ Split best_split(const std::vector<std::vector<double>>& pts, const std::vector<
 }  // namespace
 
 FF_EXPORT int ptune_tree(int nv, int ns, const double* t, int nsel, const int* shapes, int nfeat,
-                         const double* features, int k, int* kappa_out, int* leaf_out)
+                         const double* features, int k, int* kappa_out, int* leaf_out, int* node_feat,
+                         double* node_thr, int* node_child, int* leaf_variant)
 {
     std::vector<int> sel;
     if (nv <= 0 || ns <= 0 || t == nullptr || k < 1 || nfeat < 1 || features == nullptr || kappa_out == nullptr ||
@@ -540,6 +554,11 @@ FF_EXPORT int ptune_tree(int nv, int ns, const double* t, int nsel, const int* s
     const int np = (int)pts.size();
     std::vector<std::vector<int>> leaves(1);
     for (int i = 0; i < np; ++i) leaves[0].push_back(i);
+    // The tree: node 0 is the root; a split turns its leaf node into an
+    // internal node with two new leaf nodes (left first).
+    struct Node { int feat = -1; double thr = 0.0; int left = -1, right = -1; };
+    std::vector<Node> nodes(1);
+    std::vector<int> leaf_node(1, 0);
     while ((int)leaves.size() < k) {
         int bl = -1;
         Split bs;
@@ -551,8 +570,16 @@ FF_EXPORT int ptune_tree(int nv, int ns, const double* t, int nsel, const int* s
             }
         }
         if (bl < 0) break;
+        const int n = leaf_node[bl], a = (int)nodes.size(), b = a + 1;
+        nodes.resize(nodes.size() + 2);
+        nodes[n].feat = bs.f;
+        nodes[n].thr = bs.thr;
+        nodes[n].left = a;
+        nodes[n].right = b;
         leaves[bl] = bs.left;
         leaves.insert(leaves.begin() + bl + 1, bs.right);
+        leaf_node[bl] = a;
+        leaf_node.insert(leaf_node.begin() + bl + 1, b);
     }
     std::vector<std::vector<double>> reps;
     for (const auto& idx : leaves) {
@@ -562,12 +589,44 @@ FF_EXPORT int ptune_tree(int nv, int ns, const double* t, int nsel, const int* s
         for (int v = 0; v < nv; ++v) mean[v] /= (double)idx.size();
         reps.push_back(mean);
     }
-    const std::vector<int> kap = pick_distinct(reps, k, nv);
+    const std::vector<int> each = pick_each(reps, k, nv);
+    std::vector<int> kap = each;
+    std::sort(kap.begin(), kap.end());
     for (size_t i = 0; i < kap.size(); ++i) kappa_out[i] = kap[i];
     if (leaf_out)
         for (size_t li = 0; li < leaves.size(); ++li)
             for (int i : leaves[li]) leaf_out[i] = (int)li;
+    if (node_feat && node_thr && node_child) {
+        std::vector<int> leaf_of_node(nodes.size(), -1);
+        for (size_t li = 0; li < leaf_node.size(); ++li) leaf_of_node[leaf_node[li]] = (int)li;
+        for (size_t n = 0; n < nodes.size(); ++n) {
+            node_feat[n] = nodes[n].feat;
+            node_thr[n] = nodes[n].thr;
+            node_child[2 * n] = nodes[n].feat >= 0 ? nodes[n].left : leaf_of_node[n];
+            node_child[2 * n + 1] = nodes[n].feat >= 0 ? nodes[n].right : -1;
+        }
+    }
+    if (leaf_variant)
+        for (size_t li = 0; li < leaves.size(); ++li) leaf_variant[li] = li < each.size() ? each[li] : -1;
     return (int)kap.size();
+}
+
+FF_EXPORT int ptune_tree_route(int nnodes, const int* node_feat, const double* node_thr, const int* node_child,
+                               int nfeat, const double* x)
+{
+    if (nnodes < 1 || node_feat == nullptr || node_thr == nullptr || node_child == nullptr || nfeat < 1 ||
+        x == nullptr)
+        return FF_ERR_ARG;
+    int n = 0;
+    for (int step = 0; step < nnodes; ++step) {
+        const int f = node_feat[n];
+        if (f < 0) return node_child[2 * n];
+        if (f >= nfeat) return FF_ERR_ARG;
+        const int next = x[f] <= node_thr[n] ? node_child[2 * n] : node_child[2 * n + 1];
+        if (next <= n || next >= nnodes) return FF_ERR_ARG;   // children always follow their parent
+        n = next;
+    }
+    return FF_ERR_ARG;
 }
 
 FF_EXPORT int ptune_assign(int nv, int ns, const double* t, int k, const int* kappa, int nsel, const int* shapes,
@@ -598,7 +657,6 @@ FF_EXPORT int ptune_assign(int nv, int ns, const double* t, int k, const int* ka
 
 namespace {
 
-// L1 distance over log2 sizes (sizes below 1 count as 1).
 // L1 distances over log2 sizes (sizes below 1 count as 1) into d[0..ntrain).
 // train_lg, when given, holds the training shapes' log2 sizes already computed.
 void shape_distances(int ntrain, const int64_t* train_mnk, const double* train_lg, int64_t M, int64_t N, int64_t K,

@@ -232,15 +232,24 @@ def selector_comparison(t, shapes, train_idx, runs=30, log=print):
                          "heldout_realised_mean": float(np.mean(fr_ho)), "heldout_realised_ci95": ci(fr_ho),
                          "seconds_mean": float(np.mean(secs)), "runs": runs}
         t0 = time.perf_counter()
-        kt, _ = abi.ptune_tree(t, k, train_idx, feats)
+        kt, _, nf, nt, nc, lv = abi.ptune_tree(t, k, train_idx, feats, model=True)
         dt = time.perf_counter() - t0
+        # The tree as its own runtime classifier: an unseen shape goes down
+        # the splits (log2 M, N, K) to a leaf and runs that leaf's variant.
+        routed = [lv[abi.ptune_tree_route(nf, nt, nc, [math.log2(x) for x in shapes[j]])]
+                  for j in held_idx]
+        best, _, _, _, _ = abi.ptune_postprocess(t)
         rec["decision_tree"] = {"kappa": list(kt), "train_frac": 1.0 / abi.ptune_cost(t, kt, train_idx),
                                 "heldout_realised": evaluate(t, shapes, train_idx, kt)["frac_heldout_realised"],
+                                "heldout_routed": geomean(best[j] / t[v, j] for j, v in zip(held_idx, routed)),
                                 "seconds": dt}
         out[str(k)] = rec
         log(f"[selectors] k={k}: PortabilityTune {rec['portability_tune']['train_frac']:.4f}, "
             f"k-means {rec['kmeans']['train_frac_mean']:.4f} +- {rec['kmeans']['train_frac_ci95']:.4f}, "
-            f"tree {rec['decision_tree']['train_frac']:.4f} (training shapes)")
+            f"tree {rec['decision_tree']['train_frac']:.4f} (training shapes); held-out "
+            f"{rec['portability_tune']['heldout_realised']:.4f} / "
+            f"{rec['decision_tree']['heldout_realised']:.4f} (vote) / "
+            f"{rec['decision_tree']['heldout_routed']:.4f} (tree routes)")
     return out
 
 

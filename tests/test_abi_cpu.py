@@ -278,6 +278,14 @@ def test_tree_matches_oracle(seed):
         kap, leaf = abi.ptune_tree(t, k, shapes, feats)
         rk, rl = pr.tree_select(t.tolist(), k, shapes, feats)
         assert kap == rk and leaf == rl
+        # The tree itself and its routing of unseen points.
+        kap, leaf, nf, nt, nc, lv = abi.ptune_tree(t, k, shapes, feats, model=True)
+        mk, ml, nodes, each = pr.tree_model(t.tolist(), k, shapes, feats)
+        assert (kap, leaf, lv) == (mk, ml, each)
+        assert [(int(nf[n]), float(nt[n]), int(nc[2 * n]), int(nc[2 * n + 1])) for n in range(len(nodes))] == nodes
+        for q in datagen.grid27() + [(512, 4096, 4096), (100, 3000, 77)]:
+            x = [float(np.log2(v)) for v in q]
+            assert abi.ptune_tree_route(nf, nt, nc, x) == pr.tree_route(nodes, x), q
 
 
 def test_manifest_matches_family():

@@ -377,3 +377,39 @@ def test_tree_closed_forms():
     # k = 1: the root's mean vector (0.667, 0.667, 0.5): ties -> variant 0.
     kap, leaf = pr.tree_select(t, 1, list(range(6)), feats)
     assert kap == (0,) and leaf == [0] * 6
+
+
+def test_tree_model_routes_like_its_splits():
+    # One feature; variant 0 is best on features 8, 9, variant 1 on 10, 11,
+    # variant 2 on 12, 13.  The root's best splits, 9.5 and 11.5, lower the
+    # squared error equally (each isolates one identical pair), so the tie
+    # goes to the lower threshold, 9.5.  Then only the right leaf {10..13}
+    # gains from a split (at 11.5); its children are nodes 3 and 4.
+    t = [[1.0, 1.0, 3.0, 3.0, 3.0, 3.0],
+         [3.0, 3.0, 1.0, 1.0, 3.0, 3.0],
+         [3.0, 3.0, 3.0, 3.0, 1.0, 1.0]]
+    feats = [[8.0], [9.0], [10.0], [11.0], [12.0], [13.0]]
+    kap, leaf, nodes, each = pr.tree_model(t, 3, list(range(6)), feats)
+    assert kap == (0, 1, 2) and leaf == [0, 0, 1, 1, 2, 2] and each == [0, 1, 2]
+    assert nodes == [(0, 9.5, 1, 2), (-1, 0.0, 0, -1), (0, 11.5, 3, 4), (-1, 0.0, 1, -1), (-1, 0.0, 2, -1)]
+    assert pr.tree_route(nodes, [9.5]) == 0            # thresholds are inclusive on the left
+    assert pr.tree_route(nodes, [9.6]) == 1
+    assert pr.tree_route(nodes, [11.5]) == 1
+    assert pr.tree_route(nodes, [-3.0]) == 0 and pr.tree_route(nodes, [40.0]) == 2
+    # k = 1: one leaf; every point routes to it.
+    kap, leaf, nodes, each = pr.tree_model(t, 1, list(range(6)), feats)
+    assert nodes == [(-1, 0.0, 0, -1)] and pr.tree_route(nodes, [100.0]) == 0
+
+
+def test_tree_model_routes_training_points_to_their_leaves():
+    rng = np.random.default_rng(17)
+    for _ in range(10):
+        t = rng.uniform(1.0, 5.0, (6, 12)).tolist()
+        feats = rng.integers(0, 5, (12, 3)).astype(float).tolist()
+        for k in (1, 2, 3, 5):
+            kap, leaf, nodes, each = pr.tree_model(t, k, list(range(12)), feats)
+            assert len(nodes) == 2 * (max(leaf) + 1) - 1
+            assert sorted(each) == list(kap)
+            for i in range(12):
+                assert pr.tree_route(nodes, feats[i]) == leaf[i]
+
