@@ -340,7 +340,11 @@ ff_splitk_reduce(int64_t M, int64_t N, int splits, const float* __restrict__ P, 
 }
 
 // Scaled FP16 form, step 1: block maxima of |A| (blocks [0, nb)) and |B|
-// (blocks [nb, 2 nb)).
+// (blocks [nb, 2 nb)).  A matrix is cut into units of one row by kAbsCols
+// columns; block b takes units b, b + nb, ... of its matrix, and its threads
+// read each unit's columns in coalesced strides (no division per element).
+constexpr int kAbsCols = 2048;
+
 __global__ void __launch_bounds__(256)
 ff_absmax_blocks(int64_t M, int64_t K, const float* __restrict__ A, int64_t lda, int64_t N,
                  const float* __restrict__ B, int64_t ldb, int nb, float* __restrict__ out)
@@ -350,11 +354,16 @@ ff_absmax_blocks(int64_t M, int64_t K, const float* __restrict__ A, int64_t lda,
     const int blk = isA ? blockIdx.x : blockIdx.x - nb;
     const int64_t rows = isA ? M : K, cols = isA ? K : N, ld = isA ? lda : ldb;
     const float* X = isA ? A : B;
-    const int64_t total = rows * cols;
+    const int64_t chunks = (cols + kAbsCols - 1) / kAbsCols;
+    const int64_t units = rows * chunks;
     float m = 0.0f;
-    for (int64_t idx = (int64_t)blk * blockDim.x + threadIdx.x; idx < total; idx += (int64_t)nb * blockDim.x) {
-        const int64_t i = idx / cols, j = idx - i * cols;
-        m = fmaxf(m, fabsf(X[i * ld + j]));
+    for (int64_t u = blk; u < units; u += nb) {
+        const int64_t i = u / chunks;
+        const int64_t c0 = (u - i * chunks) * kAbsCols;
+        const int64_t c1 = min(cols, c0 + (int64_t)kAbsCols);
+        const float* row = X + i * ld;
+#pragma unroll 8
+        for (int64_t j = c0 + threadIdx.x; j < c1; j += 256) m = fmaxf(m, fabsf(row[j]));
     }
     red[threadIdx.x] = m;
     __syncthreads();
@@ -366,15 +375,29 @@ ff_absmax_blocks(int64_t M, int64_t K, const float* __restrict__ A, int64_t lda,
 }
 
 // Step 2: exponents e with max * 2^e in [2^14, 2^15) (0 for an all-zero
-// matrix); writes {2^eA, 2^eB, 2^-(eA+eB)} after the block maxima.
-__global__ void __launch_bounds__(64) ff_fp16_prescale(int nb, float* __restrict__ buf)
+// matrix); writes {2^eA, 2^eB, 2^-(eA+eB)} after the block maxima.  One
+// work-group of 256 threads reduces the block maxima.
+__global__ void __launch_bounds__(256) ff_fp16_prescale(int nb, float* __restrict__ buf)
 {
-    if (threadIdx.x != 0) return;
+    __shared__ float ra[256], rb[256];
     float ma = 0.0f, mb = 0.0f;
-    for (int i = 0; i < nb; ++i) {
+    for (int i = threadIdx.x; i < nb; i += 256) {
         ma = fmaxf(ma, buf[i]);
         mb = fmaxf(mb, buf[nb + i]);
     }
+    ra[threadIdx.x] = ma;
+    rb[threadIdx.x] = mb;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) {
+            ra[threadIdx.x] = fmaxf(ra[threadIdx.x], ra[threadIdx.x + w]);
+            rb[threadIdx.x] = fmaxf(rb[threadIdx.x], rb[threadIdx.x + w]);
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x != 0) return;
+    ma = ra[0];
+    mb = rb[0];
     int ea = 0, eb = 0;
     if (ma > 0.0f) { int E; frexpf(ma, &E); ea = 15 - E; }
     if (mb > 0.0f) { int E; frexpf(mb, &E); eb = 15 - E; }
@@ -446,10 +469,12 @@ int launch_variant(const Variant& v, int64_t M, int64_t N, int64_t K, float alph
         if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices || g_ws[dev].scale == nullptr)
             return fail(FF_ERR_HIP, "fp16 form: no scale buffer on this device");
         float* buf = g_ws[dev].scale;
-        const int64_t most = std::max(M * K, K * N);
-        const int nbk = (int)std::min<int64_t>(kMaxBlocks, (most + 255) / 256);
+        // One block per row unit (a row, or kAbsCols columns of it), at
+        // most kMaxBlocks blocks per matrix.
+        const int64_t units = std::max(M * ((K + kAbsCols - 1) / kAbsCols), K * ((N + kAbsCols - 1) / kAbsCols));
+        const int nbk = (int)std::max<int64_t>(1, std::min<int64_t>(kMaxBlocks, units));
         hipLaunchKernelGGL(ff_absmax_blocks, dim3(2 * nbk), dim3(256), 0, s, M, K, A, lda, N, B, ldb, nbk, buf);
-        hipLaunchKernelGGL(ff_fp16_prescale, dim3(1), dim3(64), 0, s, nbk, buf);
+        hipLaunchKernelGGL(ff_fp16_prescale, dim3(1), dim3(256), 0, s, nbk, buf);
         hipError_t e0 = hipGetLastError();
         if (e0 != hipSuccess) return hip_fail(e0, "launch fp16 prescale");
         prescale = buf + 2 * kMaxBlocks;

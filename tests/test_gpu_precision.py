@@ -115,6 +115,31 @@ def test_fp16_scale_follows_the_data(split_loaded):
         assert np.array_equal(C1 * np.float32(2.0 ** -10), C2), name
 
 
+@pytest.mark.parametrize("shape,lds", [((5, 4100, 2500), (0, 0, 0)), ((2100, 3, 7), (1, 1, 1)),
+                                       ((300, 300, 300), (3, 5, 2))])
+def test_fp16_scale_finds_the_largest_entry(split_loaded, shape, lds):
+    # The largest |A| and |B| entries sit in the last row unit and last
+    # column of each matrix (long rows span several units of the block-maxima
+    # pass).  A scale taken from a smaller maximum would push them past the
+    # FP16 range and the result to infinity.
+    M, N, K = shape
+    A = datagen.lognormal((44, M, N, K, 0), M, K)
+    B = datagen.lognormal((44, M, N, K, 1), K, N)
+    A[M - 1, K - 1] = np.float32(1e4) * np.max(np.abs(A))
+    B[K - 1, N - 1] = np.float32(-1e4) * np.max(np.abs(B))
+    Cs, Ts = pr.split_form_gemm(A, B, "fp16s", 1.0, 0.0, None)
+    tol = pr.accumulation_tolerance(K, "fp16s", 1.0, 0.0, Ts, Cs, None)
+    fails = []
+    for vid, name, form in split_loaded:
+        if form != "fp16s":
+            continue
+        C, guard = run_gemm(vid, A, B, None, 1.0, 0.0, K + lds[0], N + lds[1], N + lds[2])
+        bad = ~(np.abs(C.astype(np.float64) - Cs) <= tol)
+        if bad.any() or not guard:
+            fails.append(f"{name}: {int(bad.sum())} elements off, guard {guard}")
+    assert not fails, "\n".join(fails[:10])
+
+
 def test_presplit_workspace_limit(split_loaded):
     # A pre-split call whose pieces exceed the 1 GiB pieces workspace is
     # refused before any launch: bf16x6 keeps 3 pieces per value, and
