@@ -339,6 +339,44 @@ ff_splitk_reduce(int64_t M, int64_t N, int splits, const float* __restrict__ P, 
     }
 }
 
+// Maximum of a non-negative float over the 64 lanes of a wave, by DPP
+// row shifts and row broadcasts: within each row of 16 lanes the maximum
+// collects in lane 15 (shifts by 1, 2, 4, 8; lanes shifted in from outside
+// the row read 0, the identity for non-negative values), row_bcast:15 folds
+// row 0 into row 1 and row 2 into row 3, and row_bcast:31 folds lane 31
+// into rows 2 and 3, leaving the wave's maximum in lane 63, which is read
+// back as a wave-uniform value.  fmaxf ignores a NaN operand, as the
+// per-lane loop does.
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ float dpp_max(float v)
+{
+    const int x = __float_as_int(v);
+    const int y = __builtin_amdgcn_update_dpp(x, x, CTRL, ROW_MASK, 0xf, true);
+    return fmaxf(v, __int_as_float(y));
+}
+
+__device__ __forceinline__ float wave_max(float v)
+{
+    v = dpp_max<0x111, 0xf>(v);   // row_shr:1
+    v = dpp_max<0x112, 0xf>(v);   // row_shr:2
+    v = dpp_max<0x114, 0xf>(v);   // row_shr:4
+    v = dpp_max<0x118, 0xf>(v);   // row_shr:8
+    v = dpp_max<0x142, 0xa>(v);   // row_bcast:15 into rows 1 and 3
+    v = dpp_max<0x143, 0xc>(v);   // row_bcast:31 into rows 2 and 3
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 63));
+}
+
+// Maximum over a 256-thread work-group: one wave maximum per wave, then
+// the four through LDS.  Every thread returns the result.
+__device__ __forceinline__ float block_max256(float v)
+{
+    __shared__ float part[4];
+    v = wave_max(v);
+    if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = v;
+    __syncthreads();
+    return fmaxf(fmaxf(part[0], part[1]), fmaxf(part[2], part[3]));
+}
+
 // Scaled FP16 form, step 1: block maxima of |A| (blocks [0, nb)) and |B|
 // (blocks [nb, 2 nb)).  A matrix is cut into units of one row by kAbsCols
 // columns; block b takes units b, b + nb, ... of its matrix, and its threads
@@ -349,7 +387,6 @@ __global__ void __launch_bounds__(256)
 ff_absmax_blocks(int64_t M, int64_t K, const float* __restrict__ A, int64_t lda, int64_t N,
                  const float* __restrict__ B, int64_t ldb, int nb, float* __restrict__ out)
 {
-    __shared__ float red[256];
     const bool isA = (int)blockIdx.x < nb;
     const int blk = isA ? blockIdx.x : blockIdx.x - nb;
     const int64_t rows = isA ? M : K, cols = isA ? K : N, ld = isA ? lda : ldb;
@@ -365,13 +402,8 @@ ff_absmax_blocks(int64_t M, int64_t K, const float* __restrict__ A, int64_t lda,
 #pragma unroll 8
         for (int64_t j = c0 + threadIdx.x; j < c1; j += 256) m = fmaxf(m, fabsf(row[j]));
     }
-    red[threadIdx.x] = m;
-    __syncthreads();
-    for (int w = 128; w > 0; w >>= 1) {
-        if ((int)threadIdx.x < w) red[threadIdx.x] = fmaxf(red[threadIdx.x], red[threadIdx.x + w]);
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) out[blockIdx.x] = red[0];
+    m = block_max256(m);
+    if (threadIdx.x == 0) out[blockIdx.x] = m;
 }
 
 // Step 2: exponents e with max * 2^e in [2^14, 2^15) (0 for an all-zero
@@ -379,25 +411,15 @@ ff_absmax_blocks(int64_t M, int64_t K, const float* __restrict__ A, int64_t lda,
 // work-group of 256 threads reduces the block maxima.
 __global__ void __launch_bounds__(256) ff_fp16_prescale(int nb, float* __restrict__ buf)
 {
-    __shared__ float ra[256], rb[256];
     float ma = 0.0f, mb = 0.0f;
     for (int i = threadIdx.x; i < nb; i += 256) {
         ma = fmaxf(ma, buf[i]);
         mb = fmaxf(mb, buf[nb + i]);
     }
-    ra[threadIdx.x] = ma;
-    rb[threadIdx.x] = mb;
-    __syncthreads();
-    for (int w = 128; w > 0; w >>= 1) {
-        if ((int)threadIdx.x < w) {
-            ra[threadIdx.x] = fmaxf(ra[threadIdx.x], ra[threadIdx.x + w]);
-            rb[threadIdx.x] = fmaxf(rb[threadIdx.x], rb[threadIdx.x + w]);
-        }
-        __syncthreads();
-    }
+    ma = block_max256(ma);
+    __syncthreads();                      // the partials are reused
+    mb = block_max256(mb);
     if (threadIdx.x != 0) return;
-    ma = ra[0];
-    mb = rb[0];
     int ea = 0, eb = 0;
     if (ma > 0.0f) { int E; frexpf(ma, &E); ea = 15 - E; }
     if (mb > 0.0f) { int E; frexpf(mb, &E); eb = 15 - E; }

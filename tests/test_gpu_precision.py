@@ -140,6 +140,24 @@ def test_fp16_scale_finds_the_largest_entry(split_loaded, shape, lds):
     assert not fails, "\n".join(fails[:10])
 
 
+def test_fp16_scale_max_at_every_lane_position(split_loaded):
+    # The block maxima reduce across the lanes of each wave and across the
+    # waves of a block: put the one large entry of A (then of B) at columns
+    # that land in each row of 16 lanes, each wave, and the second stride.
+    vid, name, _ = next(x for x in split_loaded if x[2] == "fp16s")
+    M, N, K = 4, 40, 300
+    for col in (0, 5, 15, 16, 31, 32, 47, 48, 63, 64, 130, 200, 255, 256, 299):
+        for which in ("A", "B"):
+            A = datagen.lognormal((45, col, 0), M, K)
+            B = datagen.lognormal((45, col, 1), K, N)
+            if which == "A":
+                A[M - 1, col] = np.float32(3e4) * np.max(np.abs(A))
+            else:
+                B[K - 1, col % N] = np.float32(3e4) * np.max(np.abs(B))
+            C, _ = run_gemm(vid, A, B, None, 1.0, 0.0)
+            _check_form(C, A, B, "fp16s", label=f"{name} large {which} entry at column {col}")
+
+
 def test_presplit_workspace_limit(split_loaded):
     # A pre-split call whose pieces exceed the 1 GiB pieces workspace is
     # refused before any launch: bf16x6 keeps 3 pieces per value, and
