@@ -114,3 +114,56 @@ def test_split_forms_full_size_through_set(form, shape):
     lhs = np.abs(C.astype(np.float64) @ x - sc * exact)
     bound = 4.0 * len(pr.PAIRS[form]) * K * U * sc * absb
     assert (lhs <= bound).all(), (form, shape, float(np.max(lhs / bound)))
+
+
+def test_fp32_output_past_2_31_elements(k4_set):
+    # C of 65,543 x 65,543 floats (4.3e9 elements, 17 GB): every row, tile
+    # and element offset must be formed in 64 bits.  K = 5, through the set.
+    M = N = 65543
+    K = 5
+    A = datagen.uniform((60, 0), M, K)
+    B = datagen.uniform((60, 1), K, N)
+    dA, dB = torch.from_numpy(A).cuda(), torch.from_numpy(B).cuda()
+    dC = torch.full((M, N), float("nan"), device="cuda")
+    abi.sgemm(M, N, K, 1.0, dA, K, dB, N, 0.0, dC, N)
+    torch.cuda.synchronize()
+    rng = np.random.default_rng([61])
+    rows, cols = _sample_idx(rng, M), _sample_idx(rng, N)
+    Cref, S, T = oracle.ref_gemm(np.ascontiguousarray(A[rows]), B)
+    tol = oracle.gemm_tolerance(K, 1.0, 0.0, S, T, None)
+    got = dC[torch.from_numpy(rows).cuda()].cpu().numpy().astype(np.float64)
+    assert ((np.abs(got - Cref) <= tol).all()), float(np.max(np.abs(got - Cref) / tol))
+    Cref, S, T = oracle.ref_gemm(A, np.ascontiguousarray(B[:, cols]))
+    tol = oracle.gemm_tolerance(K, 1.0, 0.0, S, T, None)
+    got = dC[:, torch.from_numpy(cols).cuda()].cpu().numpy().astype(np.float64)
+    assert ((np.abs(got - Cref) <= tol).all()), float(np.max(np.abs(got - Cref) / tol))
+    # The whole result: C x against A (B x) in FP64, 4,096 rows at a time.
+    x = rng.uniform(-1.0, 1.0, N)
+    dx = torch.from_numpy(x).cuda()
+    cx = np.concatenate([(dC[r:r + 4096].double() @ dx).cpu().numpy() for r in range(0, M, 4096)])
+    A64, B64 = A.astype(np.float64), B.astype(np.float64)
+    lhs = np.abs(cx - A64 @ (B64 @ x))
+    bound = 4.0 * K * U * (np.abs(A64) @ (np.abs(B64) @ np.abs(x)))
+    assert (lhs <= bound).all(), float(np.max(lhs / bound))
+    del dC
+
+
+def test_fp32_k_past_2_24_exact(k4_set):
+    # K = 2^24 + 3 (A and B 1 GiB each; the set sends this to a member that
+    # splits K over work-groups).  A has one 1 every 4,099 columns of a row
+    # and B holds integers in [-2, 2] (no short period along k), so every
+    # partial sum is an integer below 2^24 and the FP32 result is exact in
+    # any summation order: bit-equal to the FP64 oracle.
+    M = N = 16
+    K = (1 << 24) + 3
+    k = torch.arange(K, device="cuda")
+    dA = (k.unsqueeze(0) % 4099 == torch.arange(M, device="cuda").unsqueeze(1)).float().contiguous()
+    kk = (k * 40503 + (k >> 5)).unsqueeze(1)
+    dB = ((kk + torch.arange(N, device="cuda").unsqueeze(0) * 3) % 5 - 2).float().contiguous()
+    del kk
+    del k
+    dC = torch.full((M, N), float("nan"), device="cuda")
+    abi.sgemm(M, N, K, 1.0, dA, K, dB, N, 0.0, dC, N)
+    torch.cuda.synchronize()
+    Cref, _, _ = oracle.ref_gemm(dA.cpu().numpy(), dB.cpu().numpy())
+    assert np.array_equal(dC.cpu().numpy().astype(np.float64), Cref)
