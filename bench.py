@@ -15,7 +15,7 @@ table, timed live beside the dispatched one), the roofline of the dominant
 kernel, and the FP64 oracle on the host cores as a CPU baseline.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--k 4] [--no-cpu-baseline]
-                    [--form fp32|bf16x3|bf16x6|fp16s]
+                    [--form fp32|bf16x3|bf16x6|fp16s|fp16x3]
 
 ``--form`` other than fp32 runs the same protocol for a split-precision form
 (its own k-variant set, ``sgemm_form``) on the precision workload: the 27
@@ -38,8 +38,8 @@ sys.path.insert(0, ROOT)
 METRIC = "SGEMM TFLOP/s geomean over (M,N,K) grid; % of per-shape best with k variants"
 FP32_MFMA_PEAK_TFLOPS = 157.3     # MI355X dense FP32 matrix peak (256 CU x 2.4 GHz x 256 flop/clk)
 MFMA16_PEAK_TFLOPS = 2500.0       # MI355X dense bf16 / fp16 matrix peak
-FORMS = {"fp32": 0, "bf16x3": 1, "bf16x6": 2, "fp16s": 3}
-FORM_PRODUCTS = {"fp32": 1, "bf16x3": 3, "bf16x6": 6, "fp16s": 1}   # MFMA term products per GEMM
+FORMS = {"fp32": 0, "bf16x3": 1, "bf16x6": 2, "fp16s": 3, "fp16x3": 4}
+FORM_PRODUCTS = {"fp32": 1, "bf16x3": 3, "bf16x6": 6, "fp16s": 1, "fp16x3": 3}   # MFMA term products per GEMM
 TARGET_MS_PER_SHAPE = 1.0
 
 

@@ -63,6 +63,7 @@ extern "C" {
 #define FF_FORM_BF16X3 1  /* split-bf16, 3 products: hi*hi + hi*lo + lo*hi */
 #define FF_FORM_BF16X6 2  /* split-bf16 in 3 pieces, 6 products */
 #define FF_FORM_FP16S 3   /* per-matrix power-of-two scaled fp16, 1 product */
+#define FF_FORM_FP16X3 4  /* the same scaled fp16 in 2 pieces, 3 products */
 
 /* ---------------------------------------------------------------------
  * Hot path
@@ -121,10 +122,12 @@ int variant_set_load(const char *path);
  * piece products in FP32 (not a paper method: an MI355X form of the same
  * operation).  Per-element error, as a multiple of |alpha|(|A||B|): about
  * 3.1*2^-16 (bf16x3), 4.2*2^-24 (bf16x6), 2.1*2^-11 (fp16s, for operands
- * within 2^25 of each matrix's largest magnitude), plus FP32 accumulation.
- * The fp16s form first reduces max|A| and max|B| on the device into the
- * per-device workspace (calls on one device must not overlap in time) and
- * needs finite inputs.  Pre-split variants (LDS mode 2) first form the
+ * within 2^25 of each matrix's largest magnitude), 3.1*2^-22 (fp16x3, for
+ * operands within 2^18 of each matrix's largest magnitude; smaller ones
+ * lose bits of their low piece to FP16 underflow), plus FP32 accumulation.
+ * The fp16s and fp16x3 forms first reduce max|A| and max|B| on the device
+ * into the per-device workspace (calls on one device must not overlap in
+ * time) and need finite inputs.  Pre-split variants (LDS mode 2) first form the
  * pieces of A and B into a 1 GiB per-device pieces workspace (allocated
  * when such a variant is loaded; calls on one device must not overlap in
  * time) and return FF_ERR_TOO_LARGE when 2 * T * (Mp + Np) * Kp bytes

@@ -9,6 +9,9 @@ operands with FP32 accumulation:
   the product keeps the six term products of total order <= 2.
 * fp16s: x * 2^e rounded to FP16, e per matrix with max|x| * 2^e in
   [2^14, 2^15); one product, scaled back by 2^-(ea + eb).
+* fp16x3: the same scaled value s = x * 2^e in two FP16 pieces,
+  hi = fp16(s), lo = fp16(s - hi); the product keeps lo_a hi_b + hi_a lo_b
+  + hi_a hi_b, scaled back by 2^-(ea + eb).
 
 Here every piece is formed exactly as defined (round to nearest, ties to
 even), each kept term product is summed in FP64 with the plain GEMM oracle
@@ -24,13 +27,14 @@ import numpy as np
 
 from . import ref_gemm, U32
 
-FORMS = {"bf16x3": 1, "bf16x6": 2, "fp16s": 3}
+FORMS = {"bf16x3": 1, "bf16x6": 2, "fp16s": 3, "fp16x3": 4}
 PAIRS = {
     "bf16x3": [(1, 0), (0, 1), (0, 0)],
     "bf16x6": [(2, 0), (0, 2), (1, 1), (1, 0), (0, 1), (0, 0)],
     "fp16s": [(0, 0)],
+    "fp16x3": [(1, 0), (0, 1), (0, 0)],
 }
-TERMS = {"bf16x3": 2, "bf16x6": 3, "fp16s": 1}
+TERMS = {"bf16x3": 2, "bf16x6": 3, "fp16s": 1, "fp16x3": 2}
 
 
 def bf16_rne(x):
@@ -70,12 +74,29 @@ def split_fp16(x):
     return scaled.astype(np.float16).astype(np.float32), e
 
 
+def split_fp16_pieces(x, terms):
+    """([hi, lo, ...], e): s = x * 2^e (e as in split_fp16), hi = fp16(s) and
+    each later piece the FP16 rounding of the residual left so far; pieces
+    widened to FP32.  The residuals are exact in FP32."""
+    x = np.asarray(x, dtype=np.float32)
+    e = fp16_exponent(float(np.max(np.abs(x))) if x.size else 0.0)
+    r = (x.astype(np.float64) * 2.0 ** e).astype(np.float32)
+    out = []
+    for _ in range(terms):
+        p = r.astype(np.float16).astype(np.float32)
+        out.append(p)
+        r = (r - p).astype(np.float32)
+    return out, e
+
+
 def pieces(x, form):
     """The 16-bit pieces of an FP32 matrix for `form` (as FP32 arrays) and the
     power-of-two exponent applied (0 for the BF16 forms)."""
     if form == "fp16s":
         p, e = split_fp16(x)
         return [p], e
+    if form == "fp16x3":
+        return split_fp16_pieces(x, 2)
     return split_bf16(x, TERMS[form]), 0
 
 
@@ -119,9 +140,15 @@ def accumulation_tolerance(K, form, alpha, beta, Tsplit, Csplit=None, C0=None):
 def truncation_bound(form):
     """Per-product relative error of dropping the residuals and the omitted
     term products, as a multiple of |a||b| (derived from |x - hi| <= 2^-8|x|
-    for round-to-nearest bf16 and |x - fp16(x)| <= 2^-11|x| for normal fp16)."""
+    for round-to-nearest bf16 and |x - fp16(x)| <= 2^-11|x| for normal fp16).
+    fp16x3: with d = s - hi - lo, |lo| <= 2^-11 |s| and |d| <= 2^-22 |s|
+    while the residual s - hi is an FP16 normal or |s| >= 2^-3 (entries
+    within 2^18 of the matrix's largest magnitude); the dropped
+    hi_a d_b + d_a hi_b + lo_a lo_b + smaller come to 3.01 * 2^-22 |a||b|."""
     if form == "bf16x3":
         return 3.1 * 2.0 ** -16
     if form == "bf16x6":
         return 4.2 * 2.0 ** -24
+    if form == "fp16x3":
+        return 3.1 * 2.0 ** -22
     return 2.1 * 2.0 ** -11

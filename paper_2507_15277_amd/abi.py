@@ -23,7 +23,7 @@ FF_ERR_A, FF_ERR_LDA, FF_ERR_B, FF_ERR_LDB, FF_ERR_C, FF_ERR_LDC = -5, -6, -7, -
 FF_ERR_NO_SET, FF_ERR_VARIANT, FF_ERR_PARSE = -100, -101, -102
 FF_ERR_ARCH, FF_ERR_HIP, FF_ERR_IO, FF_ERR_TOO_LARGE, FF_ERR_ARG = -103, -104, -105, -106, -107
 FF_FORM_FP32, FF_FORM_BF16X3, FF_FORM_BF16X6, FF_FORM_FP16S = 0, 1, 2, 3
-FORM_NAMES = ("fp32", "bf16x3", "bf16x6", "fp16s")
+FORM_NAMES = ("fp32", "bf16x3", "bf16x6", "fp16s", "fp16x3")
 
 EXPORTS = ("sgemm", "sgemm_form", "variant_set_load", "variant_select", "variant_select_form",
            "fewfit_last_error",

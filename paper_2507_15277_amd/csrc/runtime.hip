@@ -57,7 +57,8 @@ struct Variant {
     int id = -1;
     std::string name;
     int mwg = 0, nwg = 0, kwg = 0, mi = 0, wm = 0, wn = 0, sk = 0, vw = 0, lds = 0, gm = 0, sg = 0;
-    int prec = 0;  // 0 FP32 MFMA; 1 bf16x3, 2 bf16x6, 3 scaled fp16 (16-bit MFMA, FP32 accumulation)
+    int prec = 0;  // 0 FP32 MFMA; 1 bf16x3, 2 bf16x6, 3 scaled fp16, 4 scaled fp16 in two pieces
+                   // (16-bit MFMA, FP32 accumulation)
     int pd = 1;    // prefetch depth (compiled into the kernel; not a launch parameter)
     hipModule_t mod = nullptr;
     hipFunction_t fvec = nullptr;  // VW-wide loads
@@ -68,7 +69,8 @@ struct Variant {
     hipFunction_t fpa = nullptr;   // pre-split forms (LDS mode 2): pieces of A
     hipFunction_t fpb = nullptr;   // pre-split forms: pieces of B, transposed
     bool presplit() const { return prec > 0 && lds == 2; }
-    int terms() const { return prec == 1 ? 2 : (prec == 2 ? 3 : 1); }
+    int terms() const { return prec == 2 ? 3 : (prec == 3 || prec == 0 ? 1 : 2); }
+    bool scaled() const { return prec >= 3; }   // per-matrix power-of-two prescale
     int threads() const { return 64 * wm * wn * sk; }
 };
 
@@ -81,7 +83,7 @@ bool parse_descriptor(std::istringstream& is, Variant& v)
     if (v.pd < 1 || v.pd > 2) return false;
     if (v.id < 0 || v.mwg <= 0 || v.nwg <= 0 || v.kwg <= 0 || (v.mi != 16 && v.mi != 32) || v.wm <= 0 ||
         v.wn <= 0 || v.sk <= 0 || (v.vw != 1 && v.vw != 2 && v.vw != 4) || v.lds < 0 || v.lds > 2 || (v.lds == 2 && v.vw != 4) ||
-        v.gm <= 0 || v.sg < 1 || v.sg > 64 || v.prec < 0 || v.prec > 3 || v.threads() > 1024)
+        v.gm <= 0 || v.sg < 1 || v.sg > 64 || v.prec < 0 || v.prec > 4 || v.threads() > 1024)
         return false;
     if (v.prec > 0 && (v.sk != 1 || v.lds < 1)) return false;
     for (char c : v.name)
@@ -104,7 +106,7 @@ struct VarSet {
     std::vector<double> train_lg;                // log2 sizes of the training shapes
 };
 
-constexpr int kForms = 4;
+constexpr int kForms = 5;
 constexpr int kMaxMembers = 64;  // variants in one set
 std::mutex g_mu;
 std::map<int, std::shared_ptr<Variant>> g_variants;
@@ -117,7 +119,7 @@ constexpr size_t kWsBytes = size_t(128) << 20;
 constexpr int kMaxDevices = 16;
 struct Workspace {
     float* ws = nullptr;
-    float* scale = nullptr;  // FP16 form: block maxima of |A| and |B|, then {2^eA, 2^eB, 2^-(eA+eB)}
+    float* scale = nullptr;  // FP16 forms: block maxima of |A| and |B|, then {2^eA, 2^eB, 2^-(eA+eB)}
     short* pieces = nullptr; // pre-split forms: 16-bit pieces of A and B
 };
 // Pieces of the pre-split forms: TERMS planes of A (Mp x Kp) and of B
@@ -219,7 +221,7 @@ int register_variant(const Variant& d, const std::string& dir)
     auto v = std::make_shared<Variant>(d);
     int rc = load_code_object(*v, dir + "/" + d.name + ".co");
     if (rc != FF_OK) return rc;
-    if (d.sg > 1 || d.prec == 3) {
+    if (d.sg > 1 || d.scaled()) {
         rc = ensure_workspace();
         if (rc != FF_OK) return rc;
     }
@@ -377,7 +379,7 @@ __device__ __forceinline__ float block_max256(float v)
     return fmaxf(fmaxf(part[0], part[1]), fmaxf(part[2], part[3]));
 }
 
-// Scaled FP16 form, step 1: block maxima of |A| (blocks [0, nb)) and |B|
+// Scaled FP16 forms, step 1: block maxima of |A| (blocks [0, nb)) and |B|
 // (blocks [nb, 2 nb)).  A matrix is cut into units of one row by kAbsCols
 // columns; block b takes units b, b + nb, ... of its matrix, and its threads
 // read each unit's columns in coalesced strides (no division per element).
@@ -486,7 +488,7 @@ int launch_variant(const Variant& v, int64_t M, int64_t N, int64_t K, float alph
                             aligned_for(A, w) && aligned_for(B, w));
     hipFunction_t f = vec ? v.fvec : v.fsca;
     const float* prescale = nullptr;
-    if (v.prec == 3) {
+    if (v.scaled()) {
         int dev = 0;
         if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices || g_ws[dev].scale == nullptr)
             return fail(FF_ERR_HIP, "fp16 form: no scale buffer on this device");
@@ -774,7 +776,7 @@ static int wave_table(VarSet& set)
 //   fewfit-set 1
 //   arch <gfx name>
 //   codedir <dir>          code objects, relative to the set file's directory
-//   form <name>            optional: fp32 (default), bf16x3, bf16x6 or fp16s;
+//   form <name>            optional: fp32 (default), bf16x3, bf16x6, fp16s or fp16x3;
 //                          every member must be of that form
 //   variant <descriptor>   k lines, descriptor as in the manifest
 //   rule <M> <N> <K> <id> <c_1> ... <c_k>
@@ -815,7 +817,7 @@ FF_EXPORT int variant_set_load(const char* path)
             if (!(is >> codedir)) return fail(FF_ERR_PARSE, "%s:%d: codedir needs a value", path, lineno);
         } else if (key == "form") {
             std::string f;
-            static const char* names[kForms] = {"fp32", "bf16x3", "bf16x6", "fp16s"};
+            static const char* names[kForms] = {"fp32", "bf16x3", "bf16x6", "fp16s", "fp16x3"};
             if (!(is >> f)) return fail(FF_ERR_PARSE, "%s:%d: form needs a value", path, lineno);
             form = -1;
             for (int i = 0; i < kForms; ++i)

@@ -14,6 +14,12 @@
 //   FF_PREC 3 (fp16s):  x * 2^e rounded to FP16, with e per matrix such that
 //                       max |x| * 2^e lies in [2^14, 2^15); one product,
 //                       unscaled exactly by 2^-(eA+eB) in FP32
+//   FF_PREC 4 (fp16x3): the same scaled value s = x * 2^e split into two FP16
+//                       pieces, hi = fp16(s), lo = fp16(s - hi), so
+//                       s = hi + lo + O(2^-22 s); A*B ~ lo_A hi_B + hi_A lo_B
+//                       + hi_A hi_B (11-bit pieces: the dropped terms are
+//                       2^-22 relative, against bf16x3's 2^-16), unscaled as
+//                       in fp16s
 //
 // Residuals x - hi and x - hi - mid are exact in FP32, and every term
 // product is exact in the FP32 accumulator's input, so the only roundings
@@ -85,7 +91,8 @@ constexpr int MWG = FF_MWG, NWG = FF_NWG, KWG = FF_KWG, MI = FF_MI;
 constexpr int WM = FF_WM, WN = FF_WN, PREC = FF_PREC, GM = FF_GM, SG = FF_SG;
 constexpr bool PRESPLIT = FF_LDS == 2;
 constexpr int NS = PRESPLIT ? FF_PD + 1 : 2;            // LDS stages (pre-split: PD slabs in flight)
-constexpr int TERMS = PREC == 1 ? 2 : (PREC == 2 ? 3 : 1);
+constexpr int TERMS = PREC == 2 ? 3 : (PREC == 3 ? 1 : 2);
+constexpr bool SCALED = PREC >= 3;       // FP16 pieces of the power-of-two scaled operands
 constexpr int KB = 8 * (64 / MI);        // MFMA k depth: 16 (MI 32) or 32 (MI 16)
 constexpr int WTM = MWG / WM, WTN = NWG / WN;
 constexpr int RM = WTM / MI, RN = WTN / MI;
@@ -107,7 +114,7 @@ constexpr int DPS = (NWI + NWAVE - 1) / NWAVE;           // copies per wave per 
 constexpr int LDS_ELEMS = NS * STAGE + (PRESPLIT ? 512 : 0);
 constexpr int KPAD = 64;                                 // pre-split pieces: K padded to this
 
-static_assert(PREC >= 1 && PREC <= 3, "precision form");
+static_assert(PREC >= 1 && PREC <= 4, "precision form");
 static_assert(MI == 32 || MI == 16, "MFMA block edge");
 static_assert(MWG % (WM * MI) == 0 && NWG % (WN * MI) == 0, "tile must split into MFMA blocks");
 static_assert(KWG % KB == 0, "slab depth must be a multiple of the MFMA k");
@@ -132,7 +139,7 @@ typedef typename AccT<ACC>::T acc_t;
 // One MFMA on 8 16-bit values per lane, kept as raw 16-bit patterns.
 __device__ __forceinline__ f32x16 mfma16(i16x8 x, i16x8 y, f32x16 c)
 {
-    if constexpr (PREC == 3)
+    if constexpr (SCALED)
         return __builtin_amdgcn_mfma_f32_32x32x16_f16(__builtin_bit_cast(f16x8, x), __builtin_bit_cast(f16x8, y),
                                                       c, 0, 0, 0);
     else
@@ -141,7 +148,7 @@ __device__ __forceinline__ f32x16 mfma16(i16x8 x, i16x8 y, f32x16 c)
 }
 __device__ __forceinline__ f32x4 mfma16(i16x8 x, i16x8 y, f32x4 c)
 {
-    if constexpr (PREC == 3)
+    if constexpr (SCALED)
         return __builtin_amdgcn_mfma_f32_16x16x32_f16(__builtin_bit_cast(f16x8, x), __builtin_bit_cast(f16x8, y),
                                                       c, 0, 0, 0);
     else
@@ -155,9 +162,14 @@ __device__ __forceinline__ void split8(const float (&x)[8], float scale, i16x8 (
 {
 #pragma unroll
     for (int e = 0; e < 8; ++e) {
-        if constexpr (PREC == 3) {
-            const _Float16 h = (_Float16)(x[e] * scale);
-            out[0][e] = __builtin_bit_cast(short, h);
+        if constexpr (SCALED) {
+            float r = x[e] * scale;             // exact: a power of two
+#pragma unroll
+            for (int t = 0; t < TERMS; ++t) {
+                const _Float16 h = (_Float16)r;
+                out[t][e] = __builtin_bit_cast(short, h);
+                r -= (float)h;                  // exact: the residual fits in FP32
+            }
         } else {
             float r = x[e];
 #pragma unroll
@@ -196,7 +208,7 @@ struct Pair { int a, b; };
 __device__ constexpr Pair kPairs3[3] = {{1, 0}, {0, 1}, {0, 0}};
 __device__ constexpr Pair kPairs6[6] = {{2, 0}, {0, 2}, {1, 1}, {1, 0}, {0, 1}, {0, 0}};
 __device__ constexpr Pair kPairs1[1] = {{0, 0}};
-constexpr int NPAIRS = PREC == 1 ? 3 : (PREC == 2 ? 6 : 1);
+constexpr int NPAIRS = PREC == 2 ? 6 : (PREC == 3 ? 1 : 3);
 
 // The MFMAs of one LDS slab: every kept term product of the lane's A rows
 // and B columns, smallest first.
@@ -222,7 +234,7 @@ __device__ __forceinline__ void mma_slab(const short* sA, const short* sB, int a
         if (s + 1 < S) fragments(s + 1, (s + 1) & 1);
 #pragma unroll
         for (int p = 0; p < NPAIRS; ++p) {
-            const Pair pr = PREC == 1 ? kPairs3[p] : (PREC == 2 ? kPairs6[p] : kPairs1[p]);
+            const Pair pr = PREC == 2 ? kPairs6[p] : (PREC == 3 ? kPairs1[p] : kPairs3[p]);
 #pragma unroll
             for (int i = 0; i < RM; ++i)
 #pragma unroll
@@ -296,7 +308,7 @@ __device__ __forceinline__ void body(int M, int N, int K, float alpha, const flo
     const int lr = lane % MI, lh = lane / MI;
 
     float sa = 1.0f, sb = 1.0f, unscale = 1.0f;
-    if constexpr (PREC == 3) {
+    if constexpr (SCALED) {
         sa = prescale[0];
         sb = prescale[1];
         unscale = prescale[2];
@@ -438,7 +450,7 @@ __device__ __forceinline__ void body_pieces(int M, int N, int Kp, float alpha, c
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
     const int wm = wid / WN, wn = wid % WN;
     const int lr = lane % MI, lh = lane / MI;
-    const float unscale = (PREC == 3) ? prescale[2] : 1.0f;
+    const float unscale = SCALED ? prescale[2] : 1.0f;
 
     acc_t acc[RM][RN];
 #pragma unroll
@@ -556,7 +568,7 @@ FF_CAT(FF_NAME, _pa)(int M, int K, const float* __restrict__ A, long lda, int ve
 #pragma unroll
         for (int e = 0; e < 8; ++e) x[e] = (m < M && k + e < K) ? p[e] : 0.0f;
     }
-    put_pieces(x, PREC == 3 ? prescale[0] : 1.0f, P + (long)m * Kp + k, plane);
+    put_pieces(x, SCALED ? prescale[0] : 1.0f, P + (long)m * Kp + k, plane);
 }
 
 // Split pass over B (K x N, row stride ldb), transposed to row n of the
@@ -591,7 +603,7 @@ FF_CAT(FF_NAME, _pb)(int K, int N, const float* __restrict__ B, long ldb, const 
             float x[8];
 #pragma unroll
             for (int e = 0; e < 8; ++e) x[e] = tile[8 * kc + e][nl];
-            put_pieces(x, PREC == 3 ? prescale[1] : 1.0f, P + (long)(n0 + nl) * Kp + k0 + 8 * kc, plane);
+            put_pieces(x, SCALED ? prescale[1] : 1.0f, P + (long)(n0 + nl) * Kp + k0 + 8 * kc, plane);
         }
     }
 }

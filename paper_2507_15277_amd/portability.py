@@ -148,7 +148,7 @@ def precision_report(rows, variants, write_sets=False, log=print):
     train_idx = [shapes.index(s) for s in train]
     out = {"forms": {}, "per_shape": []}
     best = {}
-    for p in range(4):
+    for p in range(len(abi.FORM_NAMES)):
         tp = np.where((prec == p)[:, None], t, np.inf)
         if not np.isfinite(tp).any(axis=0).all():
             continue

@@ -46,7 +46,7 @@ class Variant:
     lds: int
     gm: int = 8
     sg: int = 1
-    prec: int = 0   # 0 FP32 MFMA; 1 bf16x3, 2 bf16x6, 3 scaled fp16 (csrc/sgemm_split.hip)
+    prec: int = 0   # 0 FP32 MFMA; 1 bf16x3, 2 bf16x6, 3 scaled fp16, 4 scaled fp16 in two pieces (csrc/sgemm_split.hip)
     pd: int = 1     # prefetch depth in slabs (LDS-staged FP32 variants)
 
     @property
@@ -57,7 +57,7 @@ class Variant:
 
     @property
     def terms(self):
-        return {0: 1, 1: 2, 2: 3, 3: 1}[self.prec]
+        return {0: 1, 1: 2, 2: 3, 3: 1, 4: 2}[self.prec]
 
     @property
     def source(self):
@@ -161,7 +161,7 @@ class Variant:
         return asdict(self)
 
 
-PREC_NAMES = {0: "fp32", 1: "bf16x3", 2: "bf16x6", 3: "fp16s"}
+PREC_NAMES = {0: "fp32", 1: "bf16x3", 2: "bf16x6", 3: "fp16s", 4: "fp16x3"}
 MAX_SPLIT_LDS_BYTES = 160 * 1024
 
 
@@ -458,5 +458,7 @@ def split_family(precs=(1, 2, 3)):
 
 def full_family():
     """Everything that is compiled: the FP32 family, then the split forms
-    (appended, so FP32 variant ids do not depend on the split family)."""
-    return family() + split_family()
+    (appended, so FP32 variant ids do not depend on the split family), then
+    the two-piece scaled FP16 form, added last so that earlier ids keep
+    their variants."""
+    return family() + split_family() + split_family(precs=(4,))

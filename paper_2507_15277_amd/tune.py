@@ -46,10 +46,12 @@ CFG_SQUARE, CFG_GRID, CFG_PRECISION = 2, 3, 5
 # and its number of term products.  Round-to-nearest bf16 keeps 8 bits
 # (|x - hi| <= 2^-8 |x|), fp16 keeps 11; the dropped terms of bf16x3 are
 # hi*d + d*hi + lo*lo + smaller (3.03 * 2^-16), those of bf16x6 mid*lo +
-# lo*mid + hi*d + d*hi + smaller (4.03 * 2^-24), and fp16s rounds both
-# operands once (2 * 2^-11).
-FORM_TRUNCATION = {1: 3.1 * 2.0 ** -16, 2: 4.2 * 2.0 ** -24, 3: 2.1 * 2.0 ** -11}
-FORM_PRODUCTS = {0: 1, 1: 3, 2: 6, 3: 1}
+# lo*mid + hi*d + d*hi + smaller (4.03 * 2^-24), fp16s rounds both
+# operands once (2 * 2^-11), and fp16x3 drops hi*d + d*hi + lo*lo + smaller
+# of its 11-bit pieces (3.01 * 2^-22, for entries within 2^18 of the
+# matrix's largest magnitude).
+FORM_TRUNCATION = {1: 3.1 * 2.0 ** -16, 2: 4.2 * 2.0 ** -24, 3: 2.1 * 2.0 ** -11, 4: 3.1 * 2.0 ** -22}
+FORM_PRODUCTS = {0: 1, 1: 3, 2: 6, 3: 1, 4: 3}
 
 
 def _sha(path):

@@ -74,8 +74,9 @@ def test_null_operands_allowed_when_not_read(L):
 def test_form_arguments(L):
     assert L.sgemm_form(7, 4, 4, 4, 1.0, 8, 4, 8, 4, 0.0, 8, 4, None) == abi.FF_ERR_ARG
     assert L.sgemm_form(-1, 4, 4, 4, 1.0, 8, 4, 8, 4, 0.0, 8, 4, None) == abi.FF_ERR_ARG
-    assert L.variant_select_form(4, 1, 1, 1) == abi.FF_ERR_ARG
+    assert L.variant_select_form(5, 1, 1, 1) == abi.FF_ERR_ARG
     assert L.variant_select_form(2, 1, 1, 1) == abi.FF_ERR_NO_SET
+    assert L.variant_select_form(4, 1, 1, 1) == abi.FF_ERR_NO_SET
     assert L.sgemm_form(1, -1, 4, 4, 1.0, 8, 4, 8, 4, 0.0, 8, 4, None) == abi.FF_ERR_M
 
 

@@ -73,7 +73,7 @@ def test_fp32_full_size_through_set(k4_set, shape):
     assert (lhs <= bound).all(), (shape, float(np.max(lhs / bound)))
 
 
-@pytest.mark.parametrize("form", ["bf16x3", "bf16x6", "fp16s"])
+@pytest.mark.parametrize("form", ["bf16x3", "bf16x6", "fp16s", "fp16x3"])
 @pytest.mark.parametrize("shape", [(4096, 4096, 4096), (256, 4096, 1024), (4096, 256, 256), (1024, 1024, 1024)],
                          ids=lambda s: "x".join(map(str, s)))
 def test_split_forms_full_size_through_set(form, shape):

@@ -40,7 +40,7 @@ def loaded():
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
     n = abi.variant_manifest_load(VARIANT_DIR)
-    assert n == sum(len(_manifest(p)) for p in range(4))
+    assert n == sum(len(_manifest(p)) for p in range(len(abi.FORM_NAMES)))
     return _manifest(0)
 
 

@@ -67,7 +67,49 @@ def test_closed_form_one_plus_eps():
     assert C6[0, 0] == (1.0 + 2.0 ** -10) * (1.0 + 2.0 ** -12)
 
 
-@pytest.mark.parametrize("form", ["bf16x3", "bf16x6", "fp16s"])
+def test_fp16_two_pieces_match_numpy():
+    # hi and lo are numpy's float16 roundings of the scaled value and of the
+    # residual; the residual left after lo is within 2^-22 of the scaled
+    # value (lognormal entries span 16 binades, inside the 2^18 range).
+    A = datagen.lognormal((11, 0), 50, 40)
+    (hi, lo), e = pr.split_fp16_pieces(A, 2)
+    s = A * np.float32(2.0 ** e)
+    assert 2.0 ** 14 <= float(np.max(np.abs(s))) < 2.0 ** 15
+    assert np.array_equal(hi, s.astype(np.float16).astype(np.float32))
+    assert np.array_equal(lo, (s - hi).astype(np.float16).astype(np.float32))
+    d = s.astype(np.float64) - hi - lo
+    assert np.all(np.abs(d) <= 2.0 ** -22 * np.abs(s))
+    assert np.any(np.abs(d) > 2.0 ** -26 * np.abs(s))     # something is dropped
+    # The one-piece split is the fp16s piece.
+    (p1,), e1 = pr.split_fp16_pieces(A, 1)
+    p, ep = pr.split_fp16(A)
+    assert e1 == ep and np.array_equal(p1, p)
+
+
+def test_fp16x3_closed_form():
+    # A = 1 + 2^-12, B = 1 + 2^-13, K = 1: both scale by 2^14; hi = 2^14
+    # (the FP16 spacing there is 16), lo = 4 and 2; the form keeps
+    # hi*hi + hi*lo + lo*hi = 2^28 + 6 * 2^14 and drops lo*lo = 8, so
+    # C = 1 + 2^-12 + 2^-13 (the exact product adds 2^-25).
+    A = np.array([[1.0 + 2.0 ** -12]], np.float32)
+    B = np.array([[1.0 + 2.0 ** -13]], np.float32)
+    (ha, la), ea = pr.split_fp16_pieces(A, 2)
+    assert ea == 14 and ha[0, 0] == 2.0 ** 14 and la[0, 0] == 4.0
+    C, _ = pr.split_form_gemm(A, B, "fp16x3")
+    assert C[0, 0] == 1.0 + 2.0 ** -12 + 2.0 ** -13
+
+
+def test_fp16x3_exact_on_fp16_inputs():
+    # Small integers scale to FP16 values exactly: lo = 0 and the form is
+    # the exact product.
+    A = datagen.integers((12, 0), 20, 33, -100, 100)
+    B = datagen.integers((12, 1), 33, 17, -100, 100)
+    _, S, _ = oracle.ref_gemm(A, B)
+    C, _ = pr.split_form_gemm(A, B, "fp16x3")
+    assert np.array_equal(C, S)
+
+
+@pytest.mark.parametrize("form", ["bf16x3", "bf16x6", "fp16s", "fp16x3"])
 def test_truncation_bound_holds_and_is_not_vacuous(form):
     M, N, K = 24, 20, 300
     A = datagen.lognormal((8, 0), M, K)
