@@ -78,6 +78,7 @@ def tflops(shape, ms):
 # Compute units of the device the table was measured on (MI355X); the
 # runtime queries the device it runs on.
 DEVICE_CUS = 256
+SO_EDGES = (1.0, 1.05, 1.1, 1.25, 1.5)   # S/O histogram bin edges (last bin open)
 _VARIANTS = {}
 
 
@@ -114,9 +115,16 @@ def evaluate(t, shapes, train_idx, kappa, extra=()):
         realised[j] = dispatch(train, kappa, costs, *s)
     frac = lambda idx, pick: geomean(best[j] / t[pick(j), j] for j in idx)  # noqa: E731
     in_set = lambda j: min(kappa, key=lambda v: (t[v, j], v))  # noqa: E731
+    # Per-shape slowdown of the dispatched member over the per-shape best
+    # (the paper's S/O, Sec. V-E), over all shapes, as a histogram.
+    so = [float(t[realised[j], j] / best[j]) for j in range(len(shapes))]
+    edges = SO_EDGES + (math.inf,)
+    hist = [sum(1 for x in so if lo <= x < hi) for lo, hi in zip(edges[:-1], edges[1:])]
     return {
         "kappa": list(kappa),
         "winners": winners,
+        "so_max": max(so),
+        "so_hist": {"edges": list(SO_EDGES), "counts": hist},
         "costs": costs.tolist(),
         "frac_heldout_realised": frac(held_idx, lambda j: realised[j]),
         "frac_heldout_inset": frac(held_idx, in_set),
