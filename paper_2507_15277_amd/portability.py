@@ -66,7 +66,10 @@ def matrix(rows, shapes, beta=0.0, nv=None, data="uniform", field="ms"):
 
 
 def geomean(xs):
+    """Geometric mean; NaN for an empty sequence (e.g. no held-out shapes)."""
     xs = list(xs)
+    if not xs:
+        return math.nan
     return math.exp(sum(math.log(x) for x in xs) / len(xs))
 
 

@@ -9,7 +9,7 @@ import numpy as np
 import pytest
 
 from oracle import ptune_ref as pr
-from paper_2507_15277_amd import abi, space
+from paper_2507_15277_amd import abi, datagen, space
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 HEADER = os.path.join(ROOT, "include", "fewfit.h")
@@ -316,3 +316,25 @@ def test_committed_sets_match_manifest():
         assert members, fn
         for m in members:
             assert man[int(m[0])] == m, (fn, m)
+
+
+def test_evaluate_slowdown_histogram():
+    # portability.evaluate on a random table over the real family: the S/O
+    # histogram counts every shape once, its maximum is the largest ratio of
+    # the dispatched member's time to the per-shape best, and a set holding
+    # every shape's winner, dispatched on its own training shapes, is at 1.
+    from paper_2507_15277_amd import portability
+    nv = len(portability.read_variants())
+    shapes = datagen.grid27()
+    rng = np.random.default_rng(77)
+    t = np.exp(rng.normal(0, 0.5, (nv, len(shapes))))
+    train, _ = datagen.checkerboard_split(shapes)
+    train_idx = [shapes.index(s) for s in train]
+    kap, _, _ = abi.ptune_select(t, 4, shapes=train_idx, method=-1)
+    ev = portability.evaluate(t, shapes, train_idx, kap)
+    assert sum(ev["so_hist"]["counts"]) == len(shapes)
+    so = [r["frac"] for r in ev["per_shape"]]
+    assert ev["so_max"] == pytest.approx(1.0 / min(so))
+    winners = sorted({int(np.argmin(t[:, j])) for j in range(len(shapes))})
+    ev_all = portability.evaluate(t, shapes, list(range(len(shapes))), tuple(winners))
+    assert ev_all["so_max"] == pytest.approx(1.0) and ev_all["so_hist"]["counts"][0] == len(shapes)
