@@ -456,9 +456,24 @@ def split_family(precs=(1, 2, 3)):
     return out
 
 
+# FP32 variants added after the split forms (ids after theirs, so earlier
+# ids keep their variants): eight-wave K splits of 16-wide tiles (SK 8,
+# outside the sampled space's SK range), for small M and N with long K.
+EXTRA_FP32 = [
+    Variant(16, 16, 128, 16, 1, 1, 8, 4, 0),
+    Variant(16, 16, 256, 16, 1, 1, 8, 4, 0),
+    Variant(16, 16, 128, 16, 1, 1, 8, 4, 2),
+    Variant(16, 16, 256, 16, 1, 1, 8, 4, 2),
+    Variant(16, 32, 128, 16, 1, 1, 8, 4, 2),
+    Variant(32, 16, 128, 16, 1, 1, 8, 4, 2),
+    Variant(16, 16, 128, 16, 1, 1, 8, 4, 1, pd=2),
+    Variant(16, 16, 256, 16, 1, 1, 8, 4, 1),
+]
+
+
 def full_family():
     """Everything that is compiled: the FP32 family, then the split forms
     (appended, so FP32 variant ids do not depend on the split family), then
-    the two-piece scaled FP16 form, added last so that earlier ids keep
-    their variants."""
-    return family() + split_family() + split_family(precs=(4,))
+    the two-piece scaled FP16 form and the later FP32 additions, each added
+    last so that earlier ids keep their variants."""
+    return family() + split_family() + split_family(precs=(4,)) + [v for v in EXTRA_FP32 if legal(v)]
