@@ -457,8 +457,8 @@ def split_family(precs=(1, 2, 3)):
 
 
 # FP32 variants added after the split forms (ids after theirs, so earlier
-# ids keep their variants): eight-wave K splits of 16-wide tiles (SK 8,
-# outside the sampled space's SK range), for small M and N with long K.
+# ids keep their variants): eight-wave K splits of 16- and 32-wide tiles
+# (SK 8, outside the sampled space's SK range), for small M and N with long K.
 EXTRA_FP32 = [
     Variant(16, 16, 128, 16, 1, 1, 8, 4, 0),
     Variant(16, 16, 256, 16, 1, 1, 8, 4, 0),
@@ -468,6 +468,9 @@ EXTRA_FP32 = [
     Variant(32, 16, 128, 16, 1, 1, 8, 4, 2),
     Variant(16, 16, 128, 16, 1, 1, 8, 4, 1, pd=2),
     Variant(16, 16, 256, 16, 1, 1, 8, 4, 1),
+    Variant(32, 32, 128, 16, 1, 1, 8, 4, 2),
+    Variant(32, 32, 128, 32, 1, 1, 8, 4, 2),
+    Variant(32, 32, 256, 32, 1, 1, 8, 4, 2),
 ]
 
 
