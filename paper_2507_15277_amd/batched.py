@@ -122,17 +122,62 @@ def time_it(fn, reps=5, warmup=2):
     return e0.elapsed_time(e1) / reps
 
 
+SCREEN_PER_BUCKET = 6      # problems of each bucket checked against the FP64 reference
+
+
+def screen_refs(batch, idx):
+    """FP64 reference and elementwise bound (the FP32 GEMM bound) of a few
+    problems of a bucket, on the device: the first, the last, the largest
+    and evenly spaced ones between."""
+    import torch
+
+    pick = sorted({idx[0], idx[-1], max(idx, key=lambda i: np.prod(batch.shapes[i]))}
+                  | set(idx[:: max(1, len(idx) // (SCREEN_PER_BUCKET - 3))]))[:SCREEN_PER_BUCKET]
+    refs = []
+    for i in pick:
+        M, N, K = batch.shapes[i]
+        ref = torch.empty(M * N, dtype=torch.float64, device="cuda")
+        tol = torch.empty(M * N, dtype=torch.float64, device="cuda")
+        abi.screen_reference(M, N, K, 1.0, batch.A.data_ptr() + 4 * batch.off["A"][i], K,
+                             batch.B.data_ptr() + 4 * batch.off["B"][i], N, 0.0, None, N, ref, tol)
+        refs.append((i, ref, tol))
+    return refs
+
+
+def screen_ok(batch, refs):
+    """True when every screened problem's C meets its bound (Sec. V-C: a
+    variant that gives wrong results is dropped)."""
+    for i, ref, tol in refs:
+        M, N, _ = batch.shapes[i]
+        nbad, _ = abi.screen_compare(M, N, batch.C.data_ptr() + 4 * batch.off["C"][i], N, ref, tol)
+        if nbad:
+            return False
+    return True
+
+
 def tune_buckets(batch, bucket_of, nb, candidates, log=print):
-    """Fastest grouped variant per bucket: {bucket: (vid, ms)}."""
+    """Fastest grouped variant per bucket among those whose results pass the
+    screen: {bucket: (vid, ms)}."""
     best = {}
     for b in range(nb):
         idx = [i for i in range(len(batch.shapes)) if bucket_of[i] == b]
         if not idx:
             continue
+        refs = screen_refs(batch, idx)
         res = []
+        dropped = 0
         for vid in candidates:
             plan = GroupedPlan(batch, idx, vid)
+            batch.C.fill_(float("nan"))
+            plan.launch()
+            if not screen_ok(batch, refs):
+                dropped += 1
+                continue
             res.append((time_it(plan.launch, reps=3, warmup=1), vid))
+        if not res:
+            raise RuntimeError(f"bucket {b}: no candidate passed the screen")
+        if dropped:
+            log(f"[batched] bucket {b}: {dropped} candidates dropped by the screen")
         res.sort()
         best[b] = (res[0][1], res[0][0])
         log(f"[batched] bucket {b}: {len(idx)} problems, best variant {res[0][1]} "
@@ -142,7 +187,9 @@ def tune_buckets(batch, bucket_of, nb, candidates, log=print):
 
 def run(count=2000, nb=4, seed=0, log=print, bucket_variants=None):
     """Tune the bucket variants (or take ``bucket_variants``, one id per
-    bucket), then time per-problem launches, grouped launches and the graph."""
+    bucket), check the grouped launches on a few problems per bucket against
+    the FP64 reference, then time per-problem launches, grouped launches and
+    the graph."""
     import torch
 
     abi.variant_manifest_load(tuned.VARIANT_DIR)
@@ -172,6 +219,12 @@ def run(count=2000, nb=4, seed=0, log=print, bucket_variants=None):
                               batch.B.data_ptr() + 4 * o["B"][i], N, 0.0, batch.C.data_ptr() + 4 * o["C"][i], N,
                               stream)
 
+    # The grouped launches' results on the screened problems of every bucket.
+    refs = [r for b in sorted(best) for r in screen_refs(batch, [i for i in range(count) if bucket_of[i] == b])]
+    batch.C.fill_(float("nan"))
+    grouped()
+    if not screen_ok(batch, refs):
+        raise RuntimeError("grouped launches fail the screen")
     ms_single = time_it(per_problem, reps=3, warmup=1)
     ms_grouped = time_it(grouped, reps=10, warmup=2)
     graph = torch.cuda.CUDAGraph()
@@ -193,7 +246,8 @@ def run(count=2000, nb=4, seed=0, log=print, bucket_variants=None):
                                for b, (v, ms) in best.items()},
            "ms_per_problem_launches": ms_single, "ms_grouped": ms_grouped, "ms_grouped_graph": ms_graph,
            "tflops_per_problem_launches": tf(ms_single), "tflops_grouped": tf(ms_grouped),
-           "tflops_grouped_graph": tf(ms_graph), "bucket_tuning_seconds": tune_s}
+           "tflops_grouped_graph": tf(ms_graph), "bucket_tuning_seconds": tune_s,
+           "screened_problems": len(refs)}
     log(f"[batched] {count} GEMMs, {rep['gflop']:.1f} GFLOP: per-problem launches {ms_single:.3f} ms "
         f"({tf(ms_single):.1f} TFLOP/s), grouped {ms_grouped:.3f} ms ({tf(ms_grouped):.1f}), "
         f"grouped in a graph {ms_graph:.3f} ms ({tf(ms_graph):.1f})")
