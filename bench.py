@@ -78,9 +78,10 @@ def cpu_baseline(shapes, budget_s=15.0):
                        f"{t_total:.1f} s total; FP64 triple loop with |A||B|, OpenMP over rows")}
 
 
-def measured_traffic(kernel, k, khash):
+def measured_traffic(kernel, k, khash, shapes):
     """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
-    summary of this workload, or None if there is none for this kernel source."""
+    summary of this workload, or None if there is none for this kernel source
+    and the same shapes (the counters average over the kernel's launch mix)."""
     path = os.path.join(ROOT, "profiles", f"{kernel}__grid27_k{k}.md")
     if not os.path.exists(path):
         return None
@@ -91,6 +92,9 @@ def measured_traffic(kernel, k, khash):
                 key, _, val = line.partition(":")
                 vals[key.strip().strip("`- ")] = val.strip().strip("`")
     if vals.get("kernel_build") != khash or "traffic_bytes_per_launch" not in vals:
+        return None
+    served = [x.strip() for x in next((v for key, v in vals.items() if key.startswith("shapes served")), "").split(",")]
+    if served != list(shapes):
         return None
     return float(vals["traffic_bytes_per_launch"])
 
@@ -228,7 +232,9 @@ def main():
         achieved = fl / tm / 1e9
         roofline = {"bound": "mfma", "achieved": achieved, "peak": FP32_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s",
                     "frac": achieved / FP32_MFMA_PEAK_TFLOPS,
-                    "traffic": measured_traffic(dom_name, args.k, kernel_hash())}
+                    "traffic": measured_traffic(dom_name, args.k, kernel_hash(),
+                                                ["x".join(map(str, s)) for j, s in enumerate(shapes)
+                                                 if picks[j] == dom])}
     else:
         # MFMA work the form issues: its term products, each 2MNK on 16-bit MFMA.
         achieved = FORM_PRODUCTS[form] * fl / tm / 1e9
