@@ -69,7 +69,14 @@ struct Variant {
     hipFunction_t fpa = nullptr;   // pre-split forms (LDS mode 2): pieces of A
     hipFunction_t fpb = nullptr;   // pre-split forms: pieces of B, transposed
     bool presplit() const { return prec > 0 && lds == 2; }
-    int terms() const { return prec == 2 ? 3 : (prec == 3 || prec == 0 ? 1 : 2); }
+    int terms() const   // 16-bit pieces per value: bf16x3 2, bf16x6 3, fp16s 1, fp16x3 2
+    {
+        switch (prec) {
+            case 1: case 4: return 2;
+            case 2: return 3;
+            default: return 1;
+        }
+    }
     bool scaled() const { return prec >= 3; }   // per-matrix power-of-two prescale
     int threads() const { return 64 * wm * wn * sk; }
 };
