@@ -163,6 +163,20 @@ def test_fp16_scale_max_at_every_lane_position(split_loaded):
             _check_form(C, A, B, "fp16s", label=f"{name} large {which} entry at column {col}")
 
 
+def test_scaled_forms_zero_operand(split_loaded):
+    # An all-zero A: the scale exponent is 0 for it (nothing to scale) and
+    # every scaled-form variant writes exact zeros (beta = 0, C poisoned
+    # with NaN beforehand).
+    M, N, K = 40, 72, 96
+    A = np.zeros((M, K), np.float32)
+    B = datagen.lognormal((46, 1), K, N)
+    for vid, name, form in split_loaded:
+        if form not in SCALED:
+            continue
+        C, guard = run_gemm(vid, A, B, np.full((M, N), np.nan, np.float32), 1.0, 0.0)
+        assert guard and np.array_equal(C, np.zeros((M, N), np.float32)), name
+
+
 def test_presplit_workspace_limit(split_loaded):
     # A pre-split call whose pieces exceed the 1 GiB pieces workspace is
     # refused before any launch: bf16x6 keeps 3 pieces per value, and
