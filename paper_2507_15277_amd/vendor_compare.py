@@ -4,7 +4,8 @@ Times torch's FP32 matrix product on the device (rocBLAS / hipBLASLt
 underneath; gfx950 has no reduced-precision FP32 MFMA, so it is a true FP32
 SGEMM) and this library's dispatched ``sgemm`` with the same protocol as
 ``bench.py``: seeded uniform operands resident in HBM, per shape a loop of
-back-to-back calls bracketed by HIP events, the median of several trials.
+back-to-back calls bracketed by HIP events, the median of six trials per
+side, interleaved with the order alternating.
 Context for the results, not part of the measured path.
 
     python -m paper_2507_15277_amd.vendor_compare [--k 4] [--out vendor.json]
@@ -65,8 +66,14 @@ def run(k=4, log=print):
 
         t1 = _time_loop(vendor, 3, trials=1)
         reps = max(1, min(1000, int(round(TARGET_MS / max(t1, 1e-4)))))
-        ms_v = _time_loop(vendor, reps)
-        ms_o = _time_loop(ours, reps)
+        # Interleaved trials, the order alternating, so that neither side
+        # always runs right after the other's heavy loop (clock and power
+        # state); the median of each.
+        tv, to = [], []
+        for t in range(6):
+            for which in ((vendor, ours) if t % 2 == 0 else (ours, vendor)):
+                (tv if which is vendor else to).append(_time_loop(which, reps, trials=1))
+        ms_v, ms_o = float(np.median(tv)), float(np.median(to))
         fl = 2.0 * M * N * K
         diff = float((dC - dT).abs().max())
         rows.append({"M": M, "N": N, "K": K, "tflops_set": fl / ms_o / 1e9, "tflops_vendor": fl / ms_v / 1e9,
