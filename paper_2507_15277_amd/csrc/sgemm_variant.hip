@@ -328,8 +328,15 @@ __device__ __forceinline__ void dma_slabs(int M, int N, int K, const float* __re
 // One work-group computes tile (tm, tn) of C over slabs [kt0, kt1) of K
 // (split `part` of `splits` when the K range is split over work-groups).
 // Every wave reaches every barrier and no wave returns early, so the
-// grouped kernel can call this once per tile in a loop.
-template <int V>
+// grouped kernel can call this once per tile in a loop.  EDGE false: the
+// tile and its slabs lie inside the matrices, so no load needs a per-element
+// bounds test or select.  Only the prefetch of a slab past the last one
+// (issued unconditionally by the two-deep loop and never staged) is sent to
+// the safe address, by one uniform test of the slab index.
+// Variants with an unmasked copy of the tile loop for interior tiles.
+template <int V> constexpr bool kUnmasked = USE_LDS && !(DMA && V == 4);
+
+template <int V, bool EDGE = true>
 __device__ __forceinline__ void tile_gemm(int M, int N, int K, float alpha,
                                           const float* __restrict__ A, long lda,
                                           const float* __restrict__ B, long ldb,
@@ -380,7 +387,7 @@ __device__ __forceinline__ void tile_gemm(int M, int N, int K, float alpha,
                 if (NVA % NT == 0 || v < NVA) {
                     const int row = v / AVEC_ROW, kk = (v % AVEC_ROW) * V;
                     const int m = m0 + row, k = kb + kk;
-                    oka[rbuf][i] = (m < M) && (k < K);
+                    oka[rbuf][i] = EDGE ? ((m < M) && (k < K)) : (kt < kt1);
                     ra[rbuf][i] = load_raw<V>(A + (long)m * lda + k, oka[rbuf][i], A);
                 }
             }
@@ -390,7 +397,7 @@ __device__ __forceinline__ void tile_gemm(int M, int N, int K, float alpha,
                 if (NVB % NT == 0 || v < NVB) {
                     const int row = v / BVEC_ROW, nn = (v % BVEC_ROW) * V;
                     const int k = kb + row, n = n0 + nn;
-                    okb[rbuf][i] = (k < K) && (n < N);
+                    okb[rbuf][i] = EDGE ? ((k < K) && (n < N)) : (kt < kt1);
                     rb[rbuf][i] = load_raw<V>(B + (long)k * ldb + n, okb[rbuf][i], B);
                 }
             }
@@ -403,7 +410,7 @@ __device__ __forceinline__ void tile_gemm(int M, int N, int K, float alpha,
                 const int v = tid + i * NT;
                 if (NVA % NT == 0 || v < NVA) {
                     const int row = v / AVEC_ROW, kk = (v % AVEC_ROW) * V;
-                    *reinterpret_cast<vt*>(sA + row * LDA_S + kk) = zsel<V>(ra[rbuf][i], oka[rbuf][i]);
+                    *reinterpret_cast<vt*>(sA + row * LDA_S + kk) = EDGE ? zsel<V>(ra[rbuf][i], oka[rbuf][i]) : ra[rbuf][i];
                 }
             }
 #pragma unroll
@@ -411,7 +418,7 @@ __device__ __forceinline__ void tile_gemm(int M, int N, int K, float alpha,
                 const int v = tid + i * NT;
                 if (NVB % NT == 0 || v < NVB) {
                     const int row = v / BVEC_ROW, nn = (v % BVEC_ROW) * V;
-                    *reinterpret_cast<vt*>(sB + row * LDB_S + nn) = zsel<V>(rb[rbuf][i], okb[rbuf][i]);
+                    *reinterpret_cast<vt*>(sB + row * LDB_S + nn) = EDGE ? zsel<V>(rb[rbuf][i], okb[rbuf][i]) : rb[rbuf][i];
                 }
             }
         };
@@ -660,7 +667,17 @@ __device__ __forceinline__ void gemm_body(int M, int N, int K, float alpha,
     // This work-group's slabs [kt0, kt1): all of K unless the tile is split.
     const int kt0 = (SG > 1) ? part * kper : 0;
     const int kt1 = (SG > 1) ? min(nkt, kt0 + kper) : nkt;
-    tile_gemm<V>(M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, ws, splits, part, kt0, kt1, tm, tn, smem);
+    // Interior tiles (the usual case) of the register-staged variants run
+    // without per-element masking.  The load-to-LDS path clamps addresses
+    // instead; the direct-load path measured slower without its selects.
+    if constexpr (kUnmasked<V>) {
+        if ((tm + 1) * MWG <= M && (tn + 1) * NWG <= N && kt1 * KWG <= K) {
+            tile_gemm<V, false>(M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, ws, splits, part, kt0, kt1, tm, tn,
+                                smem);
+            return;
+        }
+    }
+    tile_gemm<V, true>(M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, ws, splits, part, kt0, kt1, tm, tn, smem);
 }
 
 // One problem of a grouped launch (layout shared with the runtime).
@@ -692,8 +709,16 @@ __device__ __forceinline__ void grouped_body(const GemmDesc* __restrict__ d, con
         const int nbn = (p.N + NWG - 1) / NWG;
         const int tm = local / nbn, tn = local - tm * nbn;
         __syncthreads();   // the previous tile is done with LDS
-        tile_gemm<V>(p.M, p.N, p.K, alpha, p.A, p.lda, p.B, p.ldb, beta, p.C, p.ldc, nullptr, 1, 0, 0,
-                     (p.K + KWG - 1) / KWG, tm, tn, smem);
+        const int nkt = (p.K + KWG - 1) / KWG;
+        if constexpr (kUnmasked<V>) {
+            if ((tm + 1) * MWG <= p.M && (tn + 1) * NWG <= p.N && nkt * KWG <= p.K) {
+                tile_gemm<V, false>(p.M, p.N, p.K, alpha, p.A, p.lda, p.B, p.ldb, beta, p.C, p.ldc, nullptr, 1, 0, 0,
+                                    nkt, tm, tn, smem);
+                continue;
+            }
+        }
+        tile_gemm<V, true>(p.M, p.N, p.K, alpha, p.A, p.lda, p.B, p.ldb, beta, p.C, p.ldc, nullptr, 1, 0, 0,
+                           nkt, tm, tn, smem);
     }
 }
 

@@ -1,0 +1,74 @@
+"""CPU model of the register-staged kernels' global loads on interior tiles.
+
+Interior tiles (the tile and its slabs inside the matrices) run the
+register-staged loop without per-element masks.  The two-deep prefetch loop
+still issues the loads of one slab past the tile's last (they are never
+staged), so those must go to the safe base address.  This test restates the
+loads' index arithmetic and the PD = 1 / PD = 2 call sequences of
+csrc/sgemm_variant.hip and checks that every dereferenced element lies inside
+A (M x lda) and B (K x ldb) for every register-staged variant of the family,
+on the last interior tile and on the first and last K split.
+"""
+import numpy as np
+import pytest
+
+from paper_2507_15277_amd import space
+
+
+def _loads(v, M, N, K, lda, ldb, tm, tn, kt0, kt1):
+    V, KWG, NT = v.vw, v.kwg, v.threads
+    tid = np.arange(NT)
+
+    def gload(kt, out):
+        if not kt < kt1:           # past the last slab: the safe base address
+            return
+        for rows, vec_row, n_items, ld, base_r, base_c, name in (
+                (v.mwg, KWG // V, v.mwg * (KWG // V), lda, tm * v.mwg, kt * KWG, "A"),
+                (KWG, v.nwg // V, KWG * (v.nwg // V), ldb, kt * KWG, tn * v.nwg, "B")):
+            items = np.concatenate([tid + i * NT for i in range(-(-n_items // NT))])
+            items = items[items < n_items]
+            r = base_r + items // vec_row
+            c = base_c + (items % vec_row) * V
+            out[name] = max(out[name], int(np.max(r * ld + c + V - 1)))
+
+    out = {"A": -1, "B": -1}
+    if v.pd == 1:
+        gload(kt0, out)
+        for kt in range(kt0, kt1):
+            if kt + 1 < kt1:
+                gload(kt + 1, out)
+    else:
+        gload(kt0, out)
+        gload(kt0 + 1, out)
+        kt = kt0
+        while kt + 2 < kt1:
+            gload(kt + 2, out)
+            gload(kt + 3, out)
+            kt += 2
+    return out
+
+
+@pytest.mark.parametrize("shape", [(256, 256, 256), (512, 1024, 768)])
+def test_interior_loads_stay_inside(shape):
+    M, N, K = shape
+    staged = [v for v in space.full_family() if v.prec == 0 and v.lds == 1]
+    assert staged
+    checked = 0
+    for v in staged:
+        nbm, nbn = M // v.mwg, N // v.nwg
+        if K % v.kwg or nbm == 0 or nbn == 0:
+            continue
+        nkt = K // v.kwg
+        splits = 1
+        if v.sg > 1:
+            sp = min(v.sg, nkt, space.WORKSPACE_BYTES // (M * N * 4))
+            if sp >= 2:
+                splits = -(-nkt // -(-nkt // sp))
+        per = -(-nkt // splits)
+        for part in {0, splits - 1}:
+            kt0, kt1 = part * per, min(nkt, part * per + per)
+            out = _loads(v, M, N, K, K, N, nbm - 1, nbn - 1, kt0, kt1)
+            assert out["A"] <= (M - 1) * K + K - 1, (v.name, shape, part)
+            assert out["B"] <= (K - 1) * N + N - 1, (v.name, shape, part)
+            checked += 1
+    assert checked > 100
