@@ -458,7 +458,10 @@ def split_family(precs=(1, 2, 3)):
 
 # FP32 variants added after the split forms (ids after theirs, so earlier
 # ids keep their variants): eight-wave K splits of 16- and 32-wide tiles
-# (SK 8, outside the sampled space's SK range), for small M and N with long K.
+# (SK 8, outside the sampled space's SK range), for small M and N with long K;
+# then 16x16-block versions of the winning tile shapes, where each wave holds
+# several independent accumulator blocks instead of one 32x32 chain whose
+# back-to-back MFMAs wait on each other.
 EXTRA_FP32 = [
     Variant(16, 16, 128, 16, 1, 1, 8, 4, 0),
     Variant(16, 16, 256, 16, 1, 1, 8, 4, 0),
@@ -471,6 +474,23 @@ EXTRA_FP32 = [
     Variant(32, 32, 128, 16, 1, 1, 8, 4, 2),
     Variant(32, 32, 128, 32, 1, 1, 8, 4, 2),
     Variant(32, 32, 256, 32, 1, 1, 8, 4, 2),
+    Variant(64, 64, 64, 16, 2, 2, 2, 4, 1, pd=2),
+    Variant(64, 64, 64, 16, 2, 2, 2, 4, 1),
+    Variant(64, 64, 32, 16, 2, 2, 1, 4, 1, pd=2),
+    Variant(64, 64, 32, 16, 2, 2, 2, 4, 1, pd=2),
+    Variant(64, 64, 64, 16, 2, 2, 1, 4, 1, pd=2),
+    Variant(64, 64, 16, 16, 2, 2, 1, 4, 1, pd=2),
+    Variant(32, 32, 64, 16, 1, 1, 4, 4, 1, pd=2),
+    Variant(32, 32, 32, 16, 1, 1, 4, 4, 1, pd=2),
+    Variant(32, 32, 64, 16, 1, 1, 2, 4, 1, pd=2),
+    Variant(64, 128, 32, 16, 2, 2, 2, 4, 1, pd=2),
+    Variant(128, 64, 32, 16, 2, 2, 2, 4, 1, pd=2),
+    Variant(128, 128, 32, 16, 2, 2, 2, 4, 1, pd=2),
+    Variant(128, 128, 32, 16, 2, 2, 1, 4, 1, pd=2),
+    Variant(128, 128, 32, 16, 2, 2, 1, 4, 2, pd=2),
+    Variant(128, 256, 16, 16, 2, 4, 1, 4, 1, pd=2),
+    Variant(128, 256, 16, 16, 2, 4, 1, 4, 1),
+    Variant(256, 256, 32, 16, 4, 2, 1, 4, 2),
 ]
 
 

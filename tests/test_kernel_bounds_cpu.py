@@ -6,8 +6,9 @@ still issues the loads of one slab past the tile's last (they are never
 staged), so those must go to the safe base address.  This test restates the
 loads' index arithmetic and the PD = 1 / PD = 2 call sequences of
 csrc/sgemm_variant.hip and checks that every dereferenced element lies inside
-A (M x lda) and B (K x ldb) for every register-staged variant of the family,
-on the last interior tile and on the first and last K split.
+A (M x lda) and B (K x ldb) for every register-staged kernel of the family
+(both load widths of LDS mode 1 and the scalar-load kernel of load-to-LDS
+variants), on the last interior tile and on the first and last K split.
 """
 import numpy as np
 import pytest
@@ -15,8 +16,9 @@ import pytest
 from paper_2507_15277_amd import space
 
 
-def _loads(v, M, N, K, lda, ldb, tm, tn, kt0, kt1):
-    V, KWG, NT = v.vw, v.kwg, v.threads
+def _loads(v, M, N, K, lda, ldb, tm, tn, kt0, kt1, V=None):
+    V = V or v.vw
+    KWG, NT = v.kwg, v.threads
     tid = np.arange(NT)
 
     def gload(kt, out):
@@ -48,13 +50,25 @@ def _loads(v, M, N, K, lda, ldb, tm, tn, kt0, kt1):
     return out
 
 
+def _staged_kernels():
+    """(variant, vector width) of every kernel that stages through registers:
+    both kernels of LDS mode 1, and the scalar-load kernel of LDS mode 2."""
+    out = []
+    for v in space.full_family():
+        if v.prec == 0 and v.lds == 1:
+            out += [(v, v.vw)] + ([(v, 1)] if v.vw != 1 else [])
+        elif v.prec == 0 and v.lds == 2:
+            out.append((v, 1))
+    return out
+
+
 @pytest.mark.parametrize("shape", [(256, 256, 256), (512, 1024, 768)])
 def test_interior_loads_stay_inside(shape):
     M, N, K = shape
-    staged = [v for v in space.full_family() if v.prec == 0 and v.lds == 1]
-    assert staged
+    staged = _staged_kernels()
+    assert any(vw == 1 for _, vw in staged) and any(v.lds == 2 for v, _ in staged)
     checked = 0
-    for v in staged:
+    for v, vw in staged:
         nbm, nbn = M // v.mwg, N // v.nwg
         if K % v.kwg or nbm == 0 or nbn == 0:
             continue
@@ -67,8 +81,8 @@ def test_interior_loads_stay_inside(shape):
         per = -(-nkt // splits)
         for part in {0, splits - 1}:
             kt0, kt1 = part * per, min(nkt, part * per + per)
-            out = _loads(v, M, N, K, K, N, nbm - 1, nbn - 1, kt0, kt1)
-            assert out["A"] <= (M - 1) * K + K - 1, (v.name, shape, part)
-            assert out["B"] <= (K - 1) * N + N - 1, (v.name, shape, part)
+            out = _loads(v, M, N, K, K, N, nbm - 1, nbn - 1, kt0, kt1, vw)
+            assert out["A"] <= (M - 1) * K + K - 1, (v.name, vw, shape, part)
+            assert out["B"] <= (K - 1) * N + N - 1, (v.name, vw, shape, part)
             checked += 1
     assert checked > 100
