@@ -104,6 +104,18 @@ constexpr int KG = KWG / SK;             // k per split group per slab
 constexpr int S = KG / MK;               // MFMA steps per split group per slab
 constexpr int ACC = MI * MI / 64;        // accumulator floats per lane per block
 constexpr int AV = (S % 4 == 0) ? 4 : ((S % 2 == 0) ? 2 : 1);  // A read width
+// LDS fragment order of 16x16 blocks.  The four lane groups of an MFMA read
+// B rows (their k) in the same instruction.  With each group owning S
+// consecutive k, the groups sit S rows apart; for S = 8 and more that is a
+// multiple of 32 words, so the 16 columns of two groups in one half-wave
+// share banks (the LDS bank-conflict counter shows it).  When a group has
+// more than one chunk of AV steps, the chunks of the four groups are
+// interleaved instead (group h, chunk q owns k = (q*4 + h)*AV + t): the
+// groups sit AV rows apart, 16 words modulo 32, in disjoint banks, and A
+// reads stay AV-wide vectors.  32x32 blocks (two lane groups, one per
+// half-wave) keep the contiguous order.
+constexpr bool KIL = (MI == 16) && (S > AV);
+constexpr int KQS = KIL ? (64 / MI) * AV : AV;    // k distance between a group's chunks
 
 // LDS rows are padded by 4 floats: the A row stride (KWG+4) is an odd
 // multiple of 4 floats for KWG in {8,16,32}, so 16-byte reads of 8
@@ -423,7 +435,8 @@ __device__ __forceinline__ void tile_gemm(int M, int N, int K, float alpha,
             }
         };
 
-        const int arow0 = (wm * WTM + lr) * LDA_S + kg0;
+        const int kq0 = KIL ? grp * KG + lh * AV : kg0;   // first k of the lane's chunk 0
+        const int arow0 = (wm * WTM + lr) * LDA_S + kq0;
         const int bcol0 = wn * WTN + lr;
         // One slab from LDS: the steps go in chunks of AV (one A vector read
         // per MFMA row block); the fragments of chunk q + 1 are read while
@@ -437,12 +450,12 @@ __device__ __forceinline__ void tile_gemm(int M, int N, int K, float alpha,
             auto fragments = [&](int q, int buf) {
 #pragma unroll
                 for (int i = 0; i < RM; ++i)
-                    av[buf][i] = *reinterpret_cast<const avt*>(sA + arow0 + i * MI * LDA_S + q * AV);
+                    av[buf][i] = *reinterpret_cast<const avt*>(sA + arow0 + i * MI * LDA_S + q * KQS);
 #pragma unroll
                 for (int t = 0; t < AV; ++t)
 #pragma unroll
                     for (int j = 0; j < RN; ++j)
-                        bv[buf][t][j] = sB[(kg0 + q * AV + t) * LDB_S + bcol0 + j * MI];
+                        bv[buf][t][j] = sB[(kq0 + q * KQS + t) * LDB_S + bcol0 + j * MI];
             };
             fragments(0, 0);
 #pragma unroll
