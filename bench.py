@@ -88,10 +88,45 @@ def cpu_baseline(shapes, budget_s=15.0, min_s=10.0):
     n_runs = sorted({len(runs[s]) for s in done})
     return {"value": geomean(float(np.median(runs[s])) for s in done) / 1e12, "unit": "TFLOP/s",
             "cores": oracle.threads(), "kind": "oracle",
+            "one_thread": cpu_one_thread(order),
             "sample": (f"{len(done)} of the 27 grid shapes, smallest flop count first "
                        f"({', '.join('x'.join(map(str, s)) for s in done)}), "
                        f"{n_runs[0] if n_runs[0] == n_runs[-1] else f'{n_runs[0]}-{n_runs[-1]}'} run(s) each (median per shape), "
                        f"{t_total:.1f} s total; FP64 triple loop with |A||B|, OpenMP over rows")}
+
+
+_ONE_THREAD = r"""
+import json, sys, time
+import oracle
+from paper_2507_15277_amd import datagen
+out, spent = [], 0.0
+for (M, N, K) in json.loads(sys.argv[1]):
+    A, B, _ = datagen.gemm_operands(3, M, N, K)
+    if out and spent + 2.0 * M * N * K / out[-1][1] > float(sys.argv[2]):
+        break
+    t0 = time.perf_counter()
+    oracle.ref_gemm(A, B)
+    dt = time.perf_counter() - t0
+    spent += dt
+    out.append(("x".join(map(str, (M, N, K))), 2.0 * M * N * K / dt))
+print(json.dumps({"threads": oracle.threads(), "rates": out, "seconds": spent}))
+"""
+
+
+def cpu_one_thread(order, budget_s=4.0):
+    """The oracle on one host thread (a child process with OMP_NUM_THREADS=1,
+    which touches no GPU) over the smallest shapes until `budget_s` is spent."""
+    import subprocess
+
+    env = dict(os.environ, OMP_NUM_THREADS="1", PYTHONPATH=ROOT)
+    p = subprocess.run([sys.executable, "-c", _ONE_THREAD, json.dumps([list(s) for s in order]), str(budget_s)],
+                       env=env, cwd=ROOT, capture_output=True, text=True, timeout=120)
+    if p.returncode != 0:
+        raise RuntimeError("one-thread oracle run failed: " + p.stderr[-2000:])
+    r = json.loads(p.stdout.strip().splitlines()[-1])
+    return {"value": geomean(x for _, x in r["rates"]) / 1e12, "unit": "TFLOP/s", "cores": r["threads"],
+            "sample": f"{len(r['rates'])} smallest grid shapes ({', '.join(s for s, _ in r['rates'])}), "
+                      f"one run each, {r['seconds']:.1f} s"}
 
 
 def measured_traffic(kernel, k, khash, shapes):
