@@ -266,16 +266,20 @@ def main():
         ms_best = np.array([t_table[best_ids[j], j] for j in range(len(shapes))])
         frac = frac_raw = geomean(min(b, d) / d for b, d in zip(ms_best, ms_shape))
 
-    # Dominant kernel: the set member with the most time in a step.
+    # Dominant kernel: the set member with the most time in a step, as the
+    # tuning table predicts it (launches x table time), so that members with
+    # near-equal shares do not swap from run to run; its rate is measured.
     # Algorithmic work per launch: 2MNK flops; bytes 4(MK + KN + MN) with
     # beta = 0 (A and B read once, C written once).
-    share = {}
+    share, predicted = {}, {}
     for j, (M, N, K) in enumerate(shapes):
         v = picks[j]
         fl, tm, by = share.get(v, (0.0, 0.0, 0.0))
         share[v] = (fl + reps[j] * 2.0 * M * N * K, tm + reps[j] * ms_shape[j],
                     by + reps[j] * 4.0 * (M * K + K * N + M * N))
-    dom = max(share, key=lambda v: share[v][1])
+        t_pred = float(t_table[v, j]) if np.isfinite(t_table[v, j]) else float(ms_shape[j])
+        predicted[v] = predicted.get(v, 0.0) + reps[j] * t_pred
+    dom = max(share, key=lambda v: predicted[v])
     fl, tm, by = share[dom]
     launches = sum(reps[j] for j in range(len(shapes)) if picks[j] == dom)
     dom_name = abi.variant_info(dom).split()[1]
