@@ -15,7 +15,11 @@ table, timed live beside the dispatched one), the roofline of the dominant
 kernel, and the FP64 oracle on the host cores as a CPU baseline.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--k 4] [--no-cpu-baseline]
-                    [--form fp32|bf16x3|bf16x6|fp16s|fp16x3]
+                    [--form fp32|bf16x3|bf16x6|fp16s|fp16x3] [--cold]
+
+``--cold`` times every call on its own after writing a 512 MB scrub buffer
+(more than the 256 MB memory-side cache and the L2s together), so operands
+come from HBM; the default is warm, back-to-back calls.
 
 ``--form`` other than fp32 runs the same protocol for a split-precision form
 (its own k-variant set, ``sgemm_form``) on the precision workload: the 27
@@ -164,6 +168,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--phase", choices=("all", "dispatch"), default="all",
                     help="dispatch: only the timed dispatch steps (for profiler runs)")
+    ap.add_argument("--cold", action="store_true",
+                    help="time each call alone after a 512 MB scrub write (operands from HBM)")
     ap.add_argument("--form", choices=tuple(FORMS), default="fp32",
                     help="precision form (fp32: the plain SGEMM metric)")
     args = ap.parse_args()
@@ -255,6 +261,42 @@ def main():
         wall = time.perf_counter() - t0
         return per / steps, wall
 
+    COLD_CALLS = 8
+    scrub = torch.empty(128 << 20, dtype=torch.float32, device="cuda") if args.cold else None
+
+    def timed_cold(vids, steps, warmup):
+        """Each call alone: a scrub write evicts the operands from the L2s and
+        the memory-side cache, then the call runs between two HIP events."""
+        ev = [[(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+               for _ in range(COLD_CALLS)] for _ in shapes]
+        per = np.zeros(len(shapes))
+        t0 = time.perf_counter()
+        for step in range(warmup + steps):
+            if step == warmup:
+                t0 = time.perf_counter()   # wall time of the timed steps (scrub writes included)
+            for j, (M, N, K) in enumerate(shapes):
+                pa, pb, pc = ptrs[j]
+                for c in range(COLD_CALLS):
+                    scrub.fill_(float(c))
+                    ev[j][c][0].record(stream)
+                    if vids is None and fid == 0:
+                        rc = L.sgemm(M, N, K, 1.0, pa, K, pb, N, 0.0, pc, N, h)
+                    elif vids is None:
+                        rc = L.sgemm_form(fid, M, N, K, 1.0, pa, K, pb, N, 0.0, pc, N, h)
+                    else:
+                        rc = L.sgemm_variant(vids[j], M, N, K, 1.0, pa, K, pb, N, 0.0, pc, N, h)
+                    ev[j][c][1].record(stream)
+                    if rc:
+                        raise RuntimeError("sgemm failed: " + abi.last_error())
+            torch.cuda.synchronize()
+            if step >= warmup:
+                per += [np.median([a.elapsed_time(b) for a, b in ev[j]]) for j in range(len(shapes))]
+        return per / steps, time.perf_counter() - t0
+
+    if args.cold:
+        timed = timed_cold                # noqa: F811 (the cold protocol replaces the warm one)
+        reps = [COLD_CALLS] * len(shapes)
+
     # Timed region: the dispatch path, exactly --steps steps.
     torch.cuda.synchronize()
     ms_shape, wall = timed(None, args.steps, args.warmup)
@@ -318,6 +360,7 @@ def main():
         "config": {"workload": f"{workload}, dispatched over a k={k_loaded} portability-tuned variant set",
                    "k": k_loaded, "set_file": os.path.relpath(set_file, ROOT),
                    "launches_per_shape_per_step": reps,
+                   "cache": "cold (512 MB scrub write before each call)" if args.cold else "warm",
                    "pct_of_best_uncapped": 100.0 * frac_raw,
                    "per_shape_tflops": {"x".join(map(str, s)): round(x, 3) for s, x in zip(shapes, tf)}},
         "roofline": roofline,
