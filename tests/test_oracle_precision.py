@@ -142,3 +142,139 @@ def test_lognormal_generator_range():
     # sigma = 2: about 0.56% of the magnitudes fall outside 2^[-8,8].
     frac = np.mean((a == np.float32(2.0 ** -8)) | (a == np.float32(2.0 ** 8)))
     assert 0.002 < frac < 0.01
+
+
+# ---------------------------------------------------------------------------
+# Pins of accumulation_tolerance, the pass bound of every split-form parity
+# test: an FP32 accumulation of the kept term products sits inside it, and
+# each factor of it (products per k, K, |alpha|, the epilogue term) is needed,
+# shown by a legal accumulation or a dropped term that lands between the
+# bound and a bound missing that factor.
+
+U = 2.0 ** -24
+
+
+def _fp32_accumulate(A, B, form, alpha=1.0, beta=0.0, C0=None):
+    """FP32 accumulation of the form's kept term products, k by k and pair by
+    pair (smallest first, as the kernels issue them), then the exact unscale
+    and an FP32 epilogue.  Products of 16-bit pieces are exact in FP32."""
+    pa, ea = pr.pieces(A, form)
+    pb, eb = pr.pieces(B, form)
+    M, K = A.shape
+    N = B.shape[1]
+    acc = np.zeros((M, N), np.float32)
+    for k in range(K):
+        for ta, tb in pr.PAIRS[form]:
+            prod = np.outer(pa[ta][:, k].astype(np.float64), pb[tb][k, :].astype(np.float64))
+            acc = (acc + prod.astype(np.float32)).astype(np.float32)
+    v = (acc.astype(np.float64) * 2.0 ** -(ea + eb)).astype(np.float32)
+    out = (np.float32(alpha) * v).astype(np.float32)
+    if beta != 0.0:
+        out = (out + (np.float32(beta) * C0.astype(np.float32)).astype(np.float32)).astype(np.float32)
+    return out.astype(np.float64)
+
+
+@pytest.mark.parametrize("form", ["bf16x3", "bf16x6", "fp16s", "fp16x3"])
+@pytest.mark.parametrize("K", [1, 7, 256, 1024])
+def test_accumulation_tolerance_holds_for_fp32_accumulation(form, K):
+    M, N = 6, 5
+    A = datagen.lognormal((13, K), M, K)
+    B = datagen.lognormal((14, K), K, N)
+    Cs, Ts = pr.split_form_gemm(A, B, form)
+    got = _fp32_accumulate(A, B, form)
+    tol = pr.accumulation_tolerance(K, form, 1.0, 0.0, Ts, Cs)
+    assert np.all(np.abs(got - Cs) <= tol)
+
+
+# K = 1 constructions: one kept term product (the smallest) is dropped, and
+# its size is set between the bound and 1.5x the bound, so the bound must be
+# violated; a bound with n^2 products, or without |alpha| in Tsplit, is not.
+#   bf16x3: a = 1 + 2^-20 (hi 1, lo 2^-20), b = 1: lo_a hi_b = 16u, bound 12u.
+#   bf16x6: a = 1 + 2^-10 + 2^-19 (hi 1, mid 2^-10, lo 2^-19), b = 1:
+#           lo_a hi_b = 32u, bound 24u.
+#   fp16x3: a = 1 + 2^-20 scales to 2^14 + 2^-6 (hi 2^14, lo 2^-6), b = 1
+#           (2^14): lo_a hi_b = 2^8, unscaled by 2^-28 to 16u, bound 12u.
+_CALIBRATED = {
+    "bf16x3": (1.0 + 2.0 ** -20, (1, 0), 16),
+    "bf16x6": (1.0 + 2.0 ** -10 + 2.0 ** -19, (2, 0), 32),
+    "fp16x3": (1.0 + 2.0 ** -20, (1, 0), 16),
+}
+
+
+@pytest.mark.parametrize("form", sorted(_CALIBRATED))
+@pytest.mark.parametrize("alpha", [1.0, 2.0 ** -40])
+def test_accumulation_tolerance_catches_a_dropped_term(form, alpha):
+    a, drop, units = _CALIBRATED[form]
+    A = np.array([[a]], np.float32)
+    B = np.array([[1.0]], np.float32)
+    pa, ea = pr.pieces(A, form)
+    pb, eb = pr.pieces(B, form)
+    dropped = float(pa[drop[0]][0, 0]) * float(pb[drop[1]][0, 0]) * 2.0 ** -(ea + eb)
+    assert dropped == units * U
+    Cs, Ts = pr.split_form_gemm(A, B, form, alpha=alpha)
+    tol = pr.accumulation_tolerance(1, form, alpha, 0.0, Ts, Cs)
+    n = len(pr.PAIRS[form])
+    assert Ts[0, 0] == pytest.approx(alpha * (1.0 + units * U + 2.0 ** -10 * (form == "bf16x6")), rel=1e-12)
+    # The sum with that product dropped is outside the bound, by less than
+    # the factor a bound with n^2 products would allow.
+    err = abs(alpha) * dropped
+    assert err > tol[0, 0]
+    assert err < n * tol[0, 0]
+    # The kept sum in FP32 is exact here, so inside.
+    assert abs(alpha * float(np.float32(1.0 + units * U + 2.0 ** -10 * (form == "bf16x6"))) - Cs[0, 0]) <= tol[0, 0]
+
+
+def test_accumulation_tolerance_one_piece_form_scales_with_K():
+    # fp16s: a = [1, 3 * 2^-22], b = [1, 1] (3 * 2^-22 scales by 2^14 to the
+    # FP16 value 3 * 2^-8, exact): dropping the second product loses 12u,
+    # above the K = 2 bound of 8u.
+    A = np.array([[1.0, 3.0 * 2.0 ** -22]], np.float32)
+    B = np.array([[1.0], [1.0]], np.float32)
+    Cs, Ts = pr.split_form_gemm(A, B, "fp16s")
+    assert Cs[0, 0] == 1.0 + 12 * U
+    tol = pr.accumulation_tolerance(2, "fp16s", 1.0, 0.0, Ts, Cs)
+    assert 12 * U > tol[0, 0] > 8 * U
+
+
+def test_accumulation_tolerance_needs_its_K_factor():
+    # A legal FP32 order reaches about K u: 1 followed by K - 1 products of
+    # 2^-24 (1 + 2^-7), each just above half an ulp of the running sum, so
+    # each addition rounds up by nearly half an ulp.  bf16x3 with bf16
+    # inputs keeps only hi * hi (lo = 0).
+    K = 64
+    a = np.full((1, K), 2.0 ** -12 * (1 + 2.0 ** -7), np.float32)
+    b = np.full((K, 1), 2.0 ** -12, np.float32)
+    a[0, 0] = 1.0
+    b[0, 0] = 1.0
+    Cs, Ts = pr.split_form_gemm(a, b, "bf16x3")
+    got = _fp32_accumulate(a, b, "bf16x3")
+    err = abs(got[0, 0] - Cs[0, 0])
+    assert err > 0.9 * (K - 1) * U            # close to (K - 1) u
+    tol = pr.accumulation_tolerance(K, "bf16x3", 1.0, 0.0, Ts, Cs)
+    assert err <= tol[0, 0]
+    # A bound without K (4 n u T) would reject this legal result.
+    assert err > 4 * 3 * U * Ts[0, 0]
+
+
+def test_accumulation_tolerance_epilogue_term():
+    # A = 0: Tsplit = 0 and the result is beta * C0 rounded in FP32; only the
+    # epilogue term admits that rounding.
+    M, N, K = 8, 9, 5
+    A = np.zeros((M, K), np.float32)
+    B = datagen.lognormal((15, 1), K, N)
+    C0 = datagen.lognormal((15, 2), M, N)
+    beta = float(np.float32(1.0 / 3.0))
+    for form in ("bf16x3", "fp16x3"):
+        Cs, Ts = pr.split_form_gemm(A, B, form, alpha=1.0, beta=beta, C0=C0)
+        assert np.all(Ts == 0.0)
+        got = _fp32_accumulate(A, B, form, 1.0, beta, C0)
+        err = np.abs(got - Cs)
+        assert np.any(err > 0.0)
+        tol = pr.accumulation_tolerance(K, form, 1.0, beta, Ts, Cs, C0)
+        assert np.all(err <= tol)
+    # alpha != 1 alone: the FP32 product alpha * acc rounds once more.
+    A = datagen.lognormal((16, 0), M, K)
+    alpha = float(np.float32(1.0 / 3.0))
+    Cs, Ts = pr.split_form_gemm(A, B, "fp16x3", alpha=alpha)
+    got = _fp32_accumulate(A, B, "fp16x3", alpha)
+    assert np.all(np.abs(got - Cs) <= pr.accumulation_tolerance(K, "fp16x3", alpha, 0.0, Ts, Cs))
