@@ -190,6 +190,17 @@ int sgemm_variant(int id, int64_t M, int64_t N, int64_t K, float alpha,
                   float beta, float *C, int64_t ldc, void *stream);
 
 /*
+ * Work-groups of the GEMM kernel launch that sgemm_variant() makes for
+ * variant `id` on (M, N, K) on the current device: the tiles of C times the
+ * split count of K over work-groups (as many splits as the variant's SG
+ * allows, no more than there are K slabs, every split non-empty, and no
+ * more M x N FP32 slices than fit the K-split workspace).  0 when M or N is
+ * 0.  These counts feed the dispatch's wave correction (variant_select()).
+ * Writes *groups; returns 0, FF_ERR_M/N/K, FF_ERR_VARIANT or FF_ERR_ARG.
+ */
+int variant_work_groups(int id, int64_t M, int64_t N, int64_t K, int64_t *groups);
+
+/*
  * Time variant `id` with HIP events on `stream`: `warmup` untimed launches,
  * then `trials` trials of `reps` back-to-back launches each, bracketed by
  * two events.  Writes the mean milliseconds per launch of each trial to

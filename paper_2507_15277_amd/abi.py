@@ -31,7 +31,7 @@ EXPORTS = ("sgemm", "sgemm_form", "variant_set_load", "variant_select", "variant
            "sgemm_time", "screen_reference", "screen_compare", "ptune_postprocess",
            "ptune_cost", "ptune_select", "ptune_assign", "ptune_nearest", "ptune_dispatch",
            "ptune_select_total", "ptune_kmeans", "ptune_tree", "ptune_tree_route", "sgemm_grouped_plan",
-           "sgemm_grouped")
+           "sgemm_grouped", "variant_work_groups")
 
 
 class FewfitError(RuntimeError):
@@ -57,6 +57,7 @@ def lib():
         L.variant_select_form.argtypes = [i32, i64, i64, i64]
         L.sgemm_variant.argtypes = [i32] + gemm_args
         L.sgemm_time.argtypes = [i32] + gemm_args + [i32, i32, i32, vp]
+        L.variant_work_groups.argtypes = [i32, i64, i64, i64, vp]
         L.variant_set_load.argtypes = [ctypes.c_char_p]
         L.variant_manifest_load.argtypes = [ctypes.c_char_p]
         L.variant_select.argtypes = [i64, i64, i64]
@@ -155,6 +156,12 @@ def variant_info(vid):
 def sgemm_variant(vid, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, stream=None):
     return _check(lib().sgemm_variant(vid, M, N, K, alpha, _ptr(A), lda, _ptr(B), ldb, beta,
                                       _ptr(C), ldc, _stream(stream)))
+
+
+def variant_work_groups(vid, M, N, K):
+    out = ctypes.c_int64(0)
+    _check(lib().variant_work_groups(vid, M, N, K, ctypes.byref(out)))
+    return out.value
 
 
 def sgemm_time(vid, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, stream=None,

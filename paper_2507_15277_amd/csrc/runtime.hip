@@ -126,7 +126,7 @@ constexpr size_t kWsBytes = size_t(128) << 20;
 constexpr int kMaxDevices = 16;
 struct Workspace {
     float* ws = nullptr;
-    float* scale = nullptr;  // FP16 forms: block maxima of |A| and |B|, then {2^eA, 2^eB, 2^-(eA+eB)}
+    float* scale = nullptr;  // FP16 forms: block maxima of |A| and |B|, then the exponents {eA, eB}
     short* pieces = nullptr; // pre-split forms: 16-bit pieces of A and B
 };
 // Pieces of the pre-split forms: TERMS planes of A (Mp x Kp) and of B
@@ -416,8 +416,9 @@ ff_absmax_blocks(int64_t M, int64_t K, const float* __restrict__ A, int64_t lda,
 }
 
 // Step 2: exponents e with max * 2^e in [2^14, 2^15) (0 for an all-zero
-// matrix); writes {2^eA, 2^eB, 2^-(eA+eB)} after the block maxima.  One
-// work-group of 256 threads reduces the block maxima.
+// matrix); writes the integers {eA, eB} after the block maxima (the GEMM
+// kernels scale by ldexp, so any exponent a finite FP32 maximum needs is
+// exact).  One work-group of 256 threads reduces the block maxima.
 __global__ void __launch_bounds__(256) ff_fp16_prescale(int nb, float* __restrict__ buf)
 {
     float ma = 0.0f, mb = 0.0f;
@@ -432,12 +433,9 @@ __global__ void __launch_bounds__(256) ff_fp16_prescale(int nb, float* __restric
     int ea = 0, eb = 0;
     if (ma > 0.0f) { int E; frexpf(ma, &E); ea = 15 - E; }
     if (mb > 0.0f) { int E; frexpf(mb, &E); eb = 15 - E; }
-    ea = max(-100, min(100, ea));
-    eb = max(-100, min(100, eb));
-    float* o = buf + 2 * kMaxBlocks;
-    o[0] = ldexpf(1.0f, ea);
-    o[1] = ldexpf(1.0f, eb);
-    o[2] = ldexpf(1.0f, -(ea + eb));
+    int* o = reinterpret_cast<int*>(buf + 2 * kMaxBlocks);
+    o[0] = ea;
+    o[1] = eb;
 }
 
 // The current device's K-split workspace, or nullptr if it has none.
@@ -958,6 +956,18 @@ FF_EXPORT int sgemm_variant(int id, int64_t M, int64_t N, int64_t K, float alpha
     auto v = find_variant(id);
     if (!v) return fail(FF_ERR_VARIANT, "variant %d not registered", id);
     return gemm_common(v.get(), 0, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, stream);
+}
+
+FF_EXPORT int variant_work_groups(int id, int64_t M, int64_t N, int64_t K, int64_t* groups)
+{
+    if (groups == nullptr) return fail(FF_ERR_ARG, "variant_work_groups: groups is NULL");
+    if (M < 0) return fail(FF_ERR_M, "variant_work_groups: M < 0");
+    if (N < 0) return fail(FF_ERR_N, "variant_work_groups: N < 0");
+    if (K < 0) return fail(FF_ERR_K, "variant_work_groups: K < 0");
+    auto v = find_variant(id);
+    if (!v) return fail(FF_ERR_VARIANT, "variant %d not registered", id);
+    *groups = launch_groups(*v, M, N, K, current_workspace() != nullptr);
+    return FF_OK;
 }
 
 FF_EXPORT int sgemm_time(int id, int64_t M, int64_t N, int64_t K, float alpha, const float* A, int64_t lda,

@@ -13,7 +13,8 @@
 //                       order <= 2 (lo hi, hi lo, mid mid, mid hi, hi mid, hi hi)
 //   FF_PREC 3 (fp16s):  x * 2^e rounded to FP16, with e per matrix such that
 //                       max |x| * 2^e lies in [2^14, 2^15); one product,
-//                       unscaled exactly by 2^-(eA+eB) in FP32
+//                       unscaled by 2^-(eA+eB) with one ldexp (a single
+//                       rounding, exact while the result is a normal FP32)
 //   FF_PREC 4 (fp16x3): the same scaled value s = x * 2^e split into two FP16
 //                       pieces, hi = fp16(s), lo = fp16(s - hi), so
 //                       s = hi + lo + O(2^-22 s); A*B ~ lo_A hi_B + hi_A lo_B
@@ -156,14 +157,15 @@ __device__ __forceinline__ f32x4 mfma16(i16x8 x, i16x8 y, f32x4 c)
                                                        __builtin_bit_cast(bf16x8, y), c, 0, 0, 0);
 }
 
-// Split 8 FP32 values into TERMS vectors of 8 16-bit patterns.  `scale` is
-// the power-of-two prescale of the FP16 form (1 otherwise).
-__device__ __forceinline__ void split8(const float (&x)[8], float scale, i16x8 (&out)[TERMS])
+// Split 8 FP32 values into TERMS vectors of 8 16-bit patterns.  `ex` is
+// the FP16 form's prescale exponent (unused otherwise): x * 2^ex by ldexp,
+// exact for any exponent while the result stays a normal FP32.
+__device__ __forceinline__ void split8(const float (&x)[8], int ex, i16x8 (&out)[TERMS])
 {
 #pragma unroll
     for (int e = 0; e < 8; ++e) {
         if constexpr (SCALED) {
-            float r = x[e] * scale;             // exact: a power of two
+            float r = __builtin_amdgcn_ldexpf(x[e], ex);
 #pragma unroll
             for (int t = 0; t < TERMS; ++t) {
                 const _Float16 h = (_Float16)r;
@@ -245,10 +247,11 @@ __device__ __forceinline__ void mma_slab(const short* sA, const short* sB, int a
 }
 
 // Epilogue as in the FP32 kernel; the FP16 form first removes its prescale
-// (a power of two, exact).  A split tile writes its raw partial to its slice
-// of the workspace (alpha 1, beta 0).
+// by ldexp with the exponent -(eA + eB) (one rounding, exact while the
+// result is a normal FP32).  A split tile writes its raw partial to its
+// slice of the workspace (alpha 1, beta 0).
 __device__ __forceinline__ void store_tile(const acc_t (&acc)[RM][RN], int M, int N, float alpha, float beta,
-                                           float* __restrict__ C, long ldc, float unscale, float* __restrict__ ws,
+                                           float* __restrict__ C, long ldc, int unscale, float* __restrict__ ws,
                                            int splits, int part, int m0, int n0, int wm, int wn, int lr, int lh)
 {
     if constexpr (SG > 1) {
@@ -273,7 +276,8 @@ __device__ __forceinline__ void store_tile(const acc_t (&acc)[RM][RN], int M, in
                 const int n = n0 + wn * WTN + j * MI + (MI == 32 ? 8 * g : 0) + 4 * lh;
                 f32x4 v;
 #pragma unroll
-                for (int c = 0; c < 4; ++c) v[c] = acc[i][j][4 * g + c] * unscale;
+                for (int c = 0; c < 4; ++c)
+                    v[c] = SCALED ? __builtin_amdgcn_ldexpf(acc[i][j][4 * g + c], unscale) : acc[i][j][4 * g + c];
                 if (cvec && n + 4 <= N) {
                     f32x4 o = alpha * v;
                     if (use_beta) o += beta * *reinterpret_cast<const f32x4*>(crow + n);
@@ -297,7 +301,7 @@ template <bool VEC>
 __device__ __forceinline__ void body(int M, int N, int K, float alpha, const float* __restrict__ A, long lda,
                                      const float* __restrict__ B, long ldb, float beta, float* __restrict__ C,
                                      long ldc, float* __restrict__ ws, int splits, int kper,
-                                     const float* __restrict__ prescale, short* smem)
+                                     const int* __restrict__ pexp, short* smem)
 {
     const int nbm = (M + MWG - 1) / MWG, nbn = (N + NWG - 1) / NWG;
     int tm, tn, part;
@@ -307,11 +311,11 @@ __device__ __forceinline__ void body(int M, int N, int K, float alpha, const flo
     const int wm = wid / WN, wn = wid % WN;
     const int lr = lane % MI, lh = lane / MI;
 
-    float sa = 1.0f, sb = 1.0f, unscale = 1.0f;
+    int sa = 0, sb = 0, unscale = 0;
     if constexpr (SCALED) {
-        sa = prescale[0];
-        sb = prescale[1];
-        unscale = prescale[2];
+        sa = pexp[0];
+        sb = pexp[1];
+        unscale = -(sa + sb);
     }
 
     acc_t acc[RM][RN];
@@ -441,7 +445,7 @@ typedef __attribute__((address_space(3))) void* lds_ptr;
 __device__ __forceinline__ void body_pieces(int M, int N, int Kp, float alpha, const short* __restrict__ PA,
                                             long pa_plane, const short* __restrict__ PB, long pb_plane,
                                             float beta, float* __restrict__ C, long ldc, float* __restrict__ ws,
-                                            int splits, int kper, const float* __restrict__ prescale, short* smem)
+                                            int splits, int kper, const int* __restrict__ pexp, short* smem)
 {
     const int nbm = (M + MWG - 1) / MWG, nbn = (N + NWG - 1) / NWG;
     int tm, tn, part;
@@ -450,7 +454,7 @@ __device__ __forceinline__ void body_pieces(int M, int N, int Kp, float alpha, c
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
     const int wm = wid / WN, wn = wid % WN;
     const int lr = lane % MI, lh = lane / MI;
-    const float unscale = SCALED ? prescale[2] : 1.0f;
+    const int unscale = SCALED ? -(pexp[0] + pexp[1]) : 0;
 
     acc_t acc[RM][RN];
 #pragma unroll
@@ -532,10 +536,10 @@ __device__ __forceinline__ void body_pieces(int M, int N, int Kp, float alpha, c
 
 // Pieces of one 8-value chunk of k.  `x` holds the FP32 values (0 past the
 // matrix), written as TERMS 16-byte vectors to planes of `plane` elements.
-__device__ __forceinline__ void put_pieces(const float (&x)[8], float scale, short* __restrict__ out, long plane)
+__device__ __forceinline__ void put_pieces(const float (&x)[8], int ex, short* __restrict__ out, long plane)
 {
     i16x8 t[TERMS];
-    split8(x, scale, t);
+    split8(x, ex, t);
 #pragma unroll
     for (int q = 0; q < TERMS; ++q) *reinterpret_cast<i16x8*>(out + q * plane) = t[q];
 }
@@ -548,7 +552,7 @@ __device__ __forceinline__ void put_pieces(const float (&x)[8], float scale, sho
 // vec: K and lda multiples of 4 and A 16-byte aligned (two vector loads).
 extern "C" __global__ void __launch_bounds__(256)
 FF_CAT(FF_NAME, _pa)(int M, int K, const float* __restrict__ A, long lda, int vec,
-                     const float* __restrict__ prescale, short* __restrict__ P, int Mp, int Kp, long plane)
+                     const int* __restrict__ pexp, short* __restrict__ P, int Mp, int Kp, long plane)
 {
     const long items = (long)Mp * (Kp / 8);
     const long idx = (long)blockIdx.x * 256 + threadIdx.x;
@@ -568,7 +572,7 @@ FF_CAT(FF_NAME, _pa)(int M, int K, const float* __restrict__ A, long lda, int ve
 #pragma unroll
         for (int e = 0; e < 8; ++e) x[e] = (m < M && k + e < K) ? p[e] : 0.0f;
     }
-    put_pieces(x, SCALED ? prescale[0] : 1.0f, P + (long)m * Kp + k, plane);
+    put_pieces(x, SCALED ? pexp[0] : 0, P + (long)m * Kp + k, plane);
 }
 
 // Split pass over B (K x N, row stride ldb), transposed to row n of the
@@ -578,7 +582,7 @@ FF_CAT(FF_NAME, _pa)(int M, int K, const float* __restrict__ A, long lda, int ve
 // consecutive k of one n (128 contiguous bytes per piece plane).  Grid:
 // ceil(Np / 64) x (Kp / 64) blocks, n tiles fastest.
 extern "C" __global__ void __launch_bounds__(256)
-FF_CAT(FF_NAME, _pb)(int K, int N, const float* __restrict__ B, long ldb, const float* __restrict__ prescale,
+FF_CAT(FF_NAME, _pb)(int K, int N, const float* __restrict__ B, long ldb, const int* __restrict__ pexp,
                      short* __restrict__ P, int Np, int Kp, long plane)
 {
     __shared__ float tile[64][65];
@@ -603,7 +607,7 @@ FF_CAT(FF_NAME, _pb)(int K, int N, const float* __restrict__ B, long ldb, const 
             float x[8];
 #pragma unroll
             for (int e = 0; e < 8; ++e) x[e] = tile[8 * kc + e][nl];
-            put_pieces(x, SCALED ? prescale[1] : 1.0f, P + (long)(n0 + nl) * Kp + k0 + 8 * kc, plane);
+            put_pieces(x, SCALED ? pexp[1] : 0, P + (long)(n0 + nl) * Kp + k0 + 8 * kc, plane);
         }
     }
 }
@@ -612,29 +616,29 @@ FF_CAT(FF_NAME, _pb)(int K, int N, const float* __restrict__ B, long ldb, const 
 extern "C" __global__ void __launch_bounds__(NT)
 FF_NAME(int M, int N, int Kp, float alpha, const short* __restrict__ PA, long pa_plane,
         const short* __restrict__ PB, long pb_plane, float beta, float* __restrict__ C, long ldc,
-        float* __restrict__ ws, int splits, int kper, const float* __restrict__ prescale)
+        float* __restrict__ ws, int splits, int kper, const int* __restrict__ pexp)
 {
     __shared__ __attribute__((aligned(16))) short smem[LDS_ELEMS];
-    body_pieces(M, N, Kp, alpha, PA, pa_plane, PB, pb_plane, beta, C, ldc, ws, splits, kper, prescale, smem);
+    body_pieces(M, N, Kp, alpha, PA, pa_plane, PB, pb_plane, beta, C, ldc, ws, splits, kper, pexp, smem);
 }
 #else
-// Same argument list as the FP32 variants; `prescale` (FP16 form only)
-// points to {2^eA, 2^eB, 2^-(eA+eB)}.
+// Same argument list as the FP32 variants; `pexp` (FP16 form only) points
+// to the per-matrix exponents {eA, eB}.
 extern "C" __global__ void __launch_bounds__(NT)
 FF_NAME(int M, int N, int K, float alpha, const float* __restrict__ A, long lda, const float* __restrict__ B,
         long ldb, float beta, float* __restrict__ C, long ldc, float* __restrict__ ws, int splits, int kper,
-        const float* __restrict__ prescale)
+        const int* __restrict__ pexp)
 {
     __shared__ __attribute__((aligned(16))) short smem[LDS_ELEMS];
-    body<true>(M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, ws, splits, kper, prescale, smem);
+    body<true>(M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, ws, splits, kper, pexp, smem);
 }
 
 extern "C" __global__ void __launch_bounds__(NT)
 FF_CAT(FF_NAME, _v1)(int M, int N, int K, float alpha, const float* __restrict__ A, long lda,
                      const float* __restrict__ B, long ldb, float beta, float* __restrict__ C, long ldc,
-                     float* __restrict__ ws, int splits, int kper, const float* __restrict__ prescale)
+                     float* __restrict__ ws, int splits, int kper, const int* __restrict__ pexp)
 {
     __shared__ __attribute__((aligned(16))) short smem[LDS_ELEMS];
-    body<false>(M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, ws, splits, kper, prescale, smem);
+    body<false>(M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, ws, splits, kper, pexp, smem);
 }
 #endif

@@ -5,7 +5,10 @@ against the FP64 oracle.
 The runtime tabulates the wave correction from the device it runs on; the
 oracle is given the same inputs: the set file's training shapes and member
 log-slowdowns, work-group counts of each member's launch (tiles times K
-splits, ``space.Variant.work_groups``), and the device's compute-unit count.
+splits) as the runtime itself reports them (``variant_work_groups``), and
+the device's compute-unit count.  Those counts are checked against
+hand-worked values here and against ``space.Variant.work_groups``, whose
+own hand-worked cases run on the CPU.
 """
 import os
 
@@ -64,14 +67,36 @@ def test_select_matches_oracle_rule(cus, fname):
     path = os.path.join(SETS_DIR, fname)
     form, members, variants, train, cost = _parse(path)
     assert abi.variant_set_load(path) == len(members)
-    gt = [[variants[v].work_groups(*s) for v in members] for s in train]
+    gt = [[abi.variant_work_groups(v, *s) for v in members] for s in train]
+    assert gt == [[variants[v].work_groups(*s) for v in members] for s in train], fname
     for q in _queries():
-        gq = [variants[v].work_groups(*q) for v in members]
+        gq = [abi.variant_work_groups(v, *q) for v in members]
+        assert gq == [variants[v].work_groups(*q) for v in members], (fname, q)
         want = pr.dispatch(train, members, cost, *q, gt, gq, cus)
         assert abi.variant_select_form(form, *q) == want, (fname, q)
     # Every training shape gets its own rule winner.
     for s, row in zip(train, cost):
         assert abi.variant_select_form(form, *s) == members[int(np.argmin(row))], (fname, s)
+
+
+# Hand-worked work-group counts of manifest variants, as the runtime must
+# report them: (variant name, shape, count, how it arises).
+HAND_GROUPS = [
+    ("sgemm_m64n128k32_i16_w2x2_s2_v4_l1_d2", (4096, 4096, 4096), 64 * 32, "64 x 32 tiles"),
+    ("sgemm_m64n64k64_i32_w2x2_s2_v4_l1_d2", (300, 500, 700), 5 * 8, "ceil(300/64) x ceil(500/64)"),
+    ("sgemm_m32n32k32_i32_w1x1_s4_v4_l1_p4", (256, 256, 4096), 64 * 4, "64 tiles x 4 splits of 32 slabs"),
+    ("sgemm_m64n64k64_i32_w2x2_s2_v4_l2_p8", (256, 256, 640), 16 * 5, "10 slabs: 5 non-empty splits of 2"),
+    ("sgemm_m128n128k16_i32_w2x2_s1_v4_l1_p4", (4096, 2048, 4096), 32 * 16 * 4, "4 slices of 32 MiB fit"),
+    ("sgemm_m128n128k16_i32_w2x2_s1_v4_l1_p4", (8192, 8192, 1024), 64 * 64, "a 256 MiB slice does not fit"),
+    ("sgemm_m128n128k16_i32_w2x2_s1_v4_l1_p2", (4096, 4096, 1024), 32 * 32 * 2, "2 slices of 64 MiB fit"),
+    ("sgemm_m64n64k16_i32_w2x2_s1_v4_l1_p4", (0, 64, 64), 0, "empty"),
+]
+
+
+def test_runtime_work_groups_hand_cases(cus):
+    abi.variant_manifest_load(tuned.VARIANT_DIR)
+    for name, shape, want, why in HAND_GROUPS:
+        assert abi.variant_work_groups(_variant_id(name), *shape) == want, (name, shape, why)
 
 
 @pytest.mark.parametrize("shape", [(256, 1024, 1024), (1024, 1024, 1024), (300, 500, 700), (4096, 256, 1024)])

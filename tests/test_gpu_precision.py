@@ -163,6 +163,33 @@ def test_fp16_scale_max_at_every_lane_position(split_loaded):
             _check_form(C, A, B, "fp16s", label=f"{name} large {which} entry at column {col}")
 
 
+@pytest.mark.parametrize("ea,eb", [(-62, -62), (-100, 100), (60, -60)])
+def test_scaled_forms_extreme_magnitudes(split_loaded, ea, eb):
+    # Operands far from 1 (uniform entries times 2^ea and 2^eb, exact in
+    # FP32): the scale exponents reach 77 + 77 (an unscale factor of 2^-154,
+    # below FP32's range as one number, while every element of C is a normal
+    # FP32: the tiny operands are taken positive, so no element cancels) and
+    # 115 (beyond 100), and every scaled variant must still give the oracle's
+    # form value, whose exponent rule has no clamp.
+    M, N, K = 72, 136, 264
+    A = datagen.uniform((42, ea + 200, 0), M, K) * np.float32(2.0 ** ea)
+    B = datagen.uniform((42, eb + 200, 1), K, N) * np.float32(2.0 ** eb)
+    if ea < 0 and eb < 0:
+        A, B = np.abs(A), np.abs(B)
+    fails = []
+    for vid, name, form in split_loaded:
+        if form not in SCALED:
+            continue
+        C, guard = run_gemm(vid, A, B, np.full((M, N), np.nan, np.float32), 1.0, 0.0)
+        try:
+            assert np.isfinite(C).all() and np.any(C != 0), f"{name}: zero or non-finite result"
+            _check_form(C, A, B, form, label=name)
+            assert guard, f"{name}: wrote outside C"
+        except AssertionError as e:
+            fails.append(str(e))
+    assert not fails, "\n".join(fails[:10])
+
+
 def test_scaled_forms_zero_operand(split_loaded):
     # An all-zero A: the scale exponent is 0 for it (nothing to scale) and
     # every scaled-form variant writes exact zeros (beta = 0, C poisoned
