@@ -313,39 +313,44 @@ def main():
         ms_best = np.array([t_table[best_ids[j], j] for j in range(len(shapes))])
         frac = frac_raw = geomean(min(b, d) / d for b, d in zip(ms_best, ms_shape))
 
-    # Dominant kernel: the set member with the most time in a step, as the
-    # tuning table predicts it (launches x table time), so that members with
-    # near-equal shares do not swap from run to run; its rate is measured.
-    # Algorithmic work per launch: 2MNK flops; bytes 4(MK + KN + MN) with
-    # beta = 0 (A and B read once, C written once).
-    share, predicted = {}, {}
+    # Per member of the set: its launches in a step, their algorithmic work
+    # (2MNK flops; bytes 4(MK + KN + MN) with beta = 0, A and B read once and
+    # C written once) and their HIP-event time measured in the timed region
+    # above.  The dominant kernel is the member with the most measured time
+    # in a step; every member with at least 10% of the step is reported too.
+    share = {}
     for j, (M, N, K) in enumerate(shapes):
         v = picks[j]
-        fl, tm, by = share.get(v, (0.0, 0.0, 0.0))
+        fl, tm, by, n = share.get(v, (0.0, 0.0, 0.0, 0))
         share[v] = (fl + reps[j] * 2.0 * M * N * K, tm + reps[j] * ms_shape[j],
-                    by + reps[j] * 4.0 * (M * K + K * N + M * N))
-        t_pred = float(t_table[v, j]) if np.isfinite(t_table[v, j]) else float(ms_shape[j])
-        predicted[v] = predicted.get(v, 0.0) + reps[j] * t_pred
-    dom = max(share, key=lambda v: predicted[v])
-    fl, tm, by = share[dom]
-    launches = sum(reps[j] for j in range(len(shapes)) if picks[j] == dom)
-    dom_name = abi.variant_info(dom).split()[1]
-    if fid == 0:
-        achieved = fl / tm / 1e9
-        roofline = {"bound": "mfma", "achieved": achieved, "peak": FP32_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s",
-                    "frac": achieved / FP32_MFMA_PEAK_TFLOPS,
-                    "traffic": measured_traffic(dom_name, args.k, kernel_hash(),
-                                                ["x".join(map(str, s)) for j, s in enumerate(shapes)
-                                                 if picks[j] == dom])}
-    else:
-        # MFMA work the form issues: its term products, each 2MNK on 16-bit MFMA.
-        achieved = FORM_PRODUCTS[form] * fl / tm / 1e9
-        roofline = {"bound": "mfma", "achieved": achieved, "peak": MFMA16_PEAK_TFLOPS, "unit": "TFLOP/s",
-                    "frac": achieved / MFMA16_PEAK_TFLOPS, "traffic": None,
-                    "fp32_equivalent_tflops": fl / tm / 1e9, "mfma_products": FORM_PRODUCTS[form]}
-    roofline.update({"kernel": dom_name, "launches_per_step": launches, "flop_per_launch": fl / launches,
-                     "algorithmic_bytes_per_launch": by / launches, "ms_per_launch": tm / launches,
-                     "shapes": ["x".join(map(str, s)) for j, s in enumerate(shapes) if picks[j] == dom]})
+                    by + reps[j] * 4.0 * (M * K + K * N + M * N), n + reps[j])
+    step_ms = sum(tm for _, tm, _, _ in share.values())
+
+    def member_roofline(v):
+        fl, tm, by, launches = share[v]
+        name = abi.variant_info(v).split()[1]
+        served = ["x".join(map(str, s)) for j, s in enumerate(shapes) if picks[j] == v]
+        if fid == 0:
+            achieved = fl / tm / 1e9
+            r = {"bound": "mfma", "achieved": achieved, "peak": FP32_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s",
+                 "frac": achieved / FP32_MFMA_PEAK_TFLOPS,
+                 "traffic": measured_traffic(name, args.k, kernel_hash(), served)}
+        else:
+            # MFMA work the form issues: its term products, each 2MNK on 16-bit MFMA.
+            achieved = FORM_PRODUCTS[form] * fl / tm / 1e9
+            r = {"bound": "mfma", "achieved": achieved, "peak": MFMA16_PEAK_TFLOPS, "unit": "TFLOP/s",
+                 "frac": achieved / MFMA16_PEAK_TFLOPS, "traffic": None,
+                 "fp32_equivalent_tflops": fl / tm / 1e9, "mfma_products": FORM_PRODUCTS[form]}
+        r.update({"kernel": name, "share_of_step": tm / step_ms, "launches_per_step": launches,
+                  "flop_per_launch": fl / launches, "algorithmic_bytes_per_launch": by / launches,
+                  "ms_per_launch": tm / launches, "shapes": served})
+        return r
+
+    dom = max(share, key=lambda v: share[v][1])
+    roofline = member_roofline(dom)
+    roofline["members_over_10pct"] = [
+        {key: val for key, val in member_roofline(v).items() if key != "shapes"}
+        for v in sorted(share, key=lambda v: -share[v][1]) if share[v][1] >= 0.1 * step_ms]
 
     metric = METRIC if fid == 0 else METRIC.replace("SGEMM", f"SGEMM ({form} form)", 1)
     workload = ("27-shape grid {256,1024,4096}^3 FP32 SGEMM, alpha=1 beta=0" if fid == 0 else

@@ -131,3 +131,82 @@ def test_plan_rejects_bad_problems(loaded):
     d[1] = (16, 16, 16, 3, 4, 4, 4, 4, 4, 0)     # lda < K
     with pytest.raises(abi.FewfitError):
         abi.sgemm_grouped_plan(loaded[0], d)
+
+
+def _committed_bucket_variants():
+    """Variant ids of the committed batched run's bucket variants."""
+    import json
+    rep = json.load(open(os.path.join(os.path.dirname(tuned.VARIANT_DIR), "data", "mi355x_batched.json")))
+    names = [rep["bucket_variants"][str(b)]["name"] for b in range(rep["buckets"])]
+    ids = {l.split()[1]: int(l.split()[0]) for l in open(os.path.join(tuned.VARIANT_DIR, "manifest.txt"))
+           if not l.startswith("#")}
+    return rep["count"], [ids[n] for n in names]
+
+
+def test_full_batch_2000_against_oracle(loaded):
+    # The batched workload at full size: 2,000 problems with M, N, K
+    # log-uniform on [16, 1024] (multiples of 16), host operands from the
+    # seeded generator, one grouped launch per size bucket with the committed
+    # bucket variants, then the same launches replayed from a HIP graph.
+    # Every problem is checked against the oracle on sampled rows and
+    # columns, and over its whole result through C x against A (B x).
+    count, bucket_vids = _committed_bucket_variants()
+    assert count == 2000
+    shapes = batched.batch_shapes(count, 0)
+    ops = [(datagen.uniform((62, i, 0), M, K), datagen.uniform((62, i, 1), K, N))
+           for i, (M, N, K) in enumerate(shapes)]
+    batch = batched.Batch(shapes, host_ops=ops)
+    bucket_of = batched.buckets_of(shapes, len(bucket_vids))
+    plans = [batched.GroupedPlan(batch, [i for i in range(count) if bucket_of[i] == b], vid)
+             for b, vid in enumerate(bucket_vids)]
+    assert sum(p.count for p in plans) == count
+    # The largest bucket's tiles outnumber its resident work-groups, so each
+    # work-group walks several tiles of the persistent loop.
+    assert plans[-1].total > 2 * torch.cuda.get_device_properties(0).multi_processor_count
+    batch.C.fill_(float("nan"))
+    for p in plans:
+        p.launch()
+    torch.cuda.synchronize()
+    eager = batch.C.clone()
+
+    rng = np.random.default_rng([63])
+    fails = []
+    U = 2.0 ** -24
+    for i, (A, B) in enumerate(ops):
+        M, K = A.shape
+        N = B.shape[1]
+        C = eager[batch.off["C"][i]:batch.off["C"][i] + M * N].view(M, N).cpu().numpy()
+        if not np.isfinite(C).all():
+            fails.append(f"problem {i} {M}x{N}x{K}: non-finite")
+            continue
+        rows = np.unique(np.r_[0, M - 1, rng.integers(0, M, 6)])
+        cols = np.unique(np.r_[0, N - 1, rng.integers(0, N, 6)])
+        _, S, T = oracle.ref_gemm(np.ascontiguousarray(A[rows]), np.ascontiguousarray(B[:, cols]))
+        if not np.all(np.abs(C[np.ix_(rows, cols)] - S) <= 4 * K * U * T):
+            fails.append(f"problem {i} {M}x{N}x{K}: sampled entries")
+        x = rng.uniform(-1.0, 1.0, N)
+        A64, B64 = A.astype(np.float64), B.astype(np.float64)
+        lhs = np.abs(C.astype(np.float64) @ x - A64 @ (B64 @ x))
+        if not np.all(lhs <= 4 * K * U * (np.abs(A64) @ (np.abs(B64) @ np.abs(x)))):
+            fails.append(f"problem {i} {M}x{N}x{K}: C x")
+    assert not fails, fails[:10]
+
+    # One capture of the four launches, replayed after the result is cleared:
+    # bit-equal to the eager launches.
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        for p in plans:
+            p.launch(stream=side)
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        for p in plans:
+            p.launch(stream=torch.cuda.current_stream())
+    for r in range(2):
+        batch.C.fill_(float("nan"))
+        torch.cuda.synchronize()
+        graph.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(batch.C, eager), f"graph replay {r} differs from the eager launches"

@@ -73,9 +73,37 @@ def test_fp32_full_size_through_set(k4_set, shape):
     assert (lhs <= bound).all(), (shape, float(np.max(lhs / bound)))
 
 
+@pytest.mark.parametrize("n", datagen.SQUARE_SIZES)
+def test_fp32_squares_beta_half_through_set(k4_set, n):
+    # The square sweep at beta = 0.5 (C0 uniform on [-1, 1)), through sgemm()
+    # and the k = 4 set, on the tuner's seeded inputs: sampled outputs against
+    # the oracle, and C x against A (B x) + 0.5 C0 x over the whole result.
+    M = N = K = n
+    A, B, C0 = datagen.gemm_operands(2, M, N, K, beta=0.5)
+    dA, dB = torch.from_numpy(A).cuda(), torch.from_numpy(B).cuda()
+    dC = torch.from_numpy(C0).cuda()
+    abi.sgemm(M, N, K, 1.0, dA, K, dB, N, 0.5, dC, N)
+    torch.cuda.synchronize()
+    C = dC.cpu().numpy()
+    assert np.isfinite(C).all(), n
+    rng = np.random.default_rng([11, n])
+    rows, cols = _sample_idx(rng, M), _sample_idx(rng, N)
+    C0s = np.ascontiguousarray(C0[np.ix_(rows, cols)])
+    Cref, S, T = oracle.ref_gemm(np.ascontiguousarray(A[rows]), np.ascontiguousarray(B[:, cols]), 1.0, 0.5, C0s)
+    tol = oracle.gemm_tolerance(K, 1.0, 0.5, S, T, C0s)
+    err = np.abs(C[np.ix_(rows, cols)].astype(np.float64) - Cref)
+    assert (err <= tol).all(), (n, float(np.max(err / tol)))
+    # The elementwise bound summed against |x|; |A B| <= |A||B| covers the
+    # epilogue's 2u|alpha A B| term.
+    x = rng.uniform(-1.0, 1.0, N)
+    A64, B64, C064 = A.astype(np.float64), B.astype(np.float64), C0.astype(np.float64)
+    lhs = np.abs(C.astype(np.float64) @ x - (A64 @ (B64 @ x) + 0.5 * (C064 @ x)))
+    bound = (4.0 * K + 2.0) * U * (np.abs(A64) @ (np.abs(B64) @ np.abs(x))) + 2.0 * U * 0.5 * (np.abs(C064) @ np.abs(x))
+    assert (lhs <= bound).all(), (n, float(np.max(lhs / bound)))
+
+
 @pytest.mark.parametrize("form", ["bf16x3", "bf16x6", "fp16s", "fp16x3"])
-@pytest.mark.parametrize("shape", [(4096, 4096, 4096), (256, 4096, 1024), (4096, 256, 256), (1024, 1024, 1024)],
-                         ids=lambda s: "x".join(map(str, s)))
+@pytest.mark.parametrize("shape", datagen.grid27(), ids=lambda s: "x".join(map(str, s)))
 def test_split_forms_full_size_through_set(form, shape):
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
@@ -148,22 +176,49 @@ def test_fp32_output_past_2_31_elements(k4_set):
     del dC
 
 
-def test_fp32_k_past_2_24_exact(k4_set):
-    # K = 2^24 + 3 (A and B 1 GiB each; the set sends this to a member that
-    # splits K over work-groups).  A has one 1 every 4,099 columns of a row
-    # and B holds integers in [-2, 2] (no short period along k), so every
-    # partial sum is an integer below 2^24 and the FP32 result is exact in
-    # any summation order: bit-equal to the FP64 oracle.
-    M = N = 16
-    K = (1 << 24) + 3
+def _k_past_2_24_operands(M, N, K):
+    # A has one 1 every 4,099 columns of a row and B holds integers in
+    # [-2, 2] (no short period along k), so every partial sum is an integer
+    # below 2^24 and the FP32 result is exact in any summation order:
+    # bit-equal to the FP64 oracle.
     k = torch.arange(K, device="cuda")
     dA = (k.unsqueeze(0) % 4099 == torch.arange(M, device="cuda").unsqueeze(1)).float().contiguous()
     kk = (k * 40503 + (k >> 5)).unsqueeze(1)
     dB = ((kk + torch.arange(N, device="cuda").unsqueeze(0) * 3) % 5 - 2).float().contiguous()
-    del kk
-    del k
+    return dA, dB
+
+
+def test_fp32_k_past_2_24_exact(k4_set):
+    # K = 2^24 + 3 (A and B 1 GiB each) through the set, as a user would call
+    # it.  The set's rule sends 16 x 16 x K to an unsplit member, one
+    # work-group walking all of K.
+    M = N = 16
+    K = (1 << 24) + 3
+    dA, dB = _k_past_2_24_operands(M, N, K)
     dC = torch.full((M, N), float("nan"), device="cuda")
     abi.sgemm(M, N, K, 1.0, dA, K, dB, N, 0.0, dC, N)
+    torch.cuda.synchronize()
+    Cref, _, _ = oracle.ref_gemm(dA.cpu().numpy(), dB.cpu().numpy())
+    assert np.array_equal(dC.cpu().numpy().astype(np.float64), Cref)
+
+
+@pytest.mark.parametrize("name,splits", [("sgemm_m32n32k32_i32_w1x1_s4_v4_l1_p16", 16),
+                                         ("sgemm_m16n16k32_i16_w1x1_s2_v4_l0_p16", 16)])
+def test_fp32_k_past_2_24_split_over_work_groups(name, splits):
+    # The same exact case through FP32 members that split K over 16
+    # work-groups (524,289 slabs of 32: 16 splits of 32,769 slabs), so the
+    # partial products and the fixed-order reduction run at K > 2^24.
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    abi.variant_manifest_load(tuned.VARIANT_DIR)
+    vid = next(int(l.split()[0]) for l in open(tuned.VARIANT_DIR + "/manifest.txt")
+               if not l.startswith("#") and l.split()[1] == name)
+    M = N = 16
+    K = (1 << 24) + 3
+    assert abi.variant_work_groups(vid, M, N, K) == splits   # one tile, 16 splits
+    dA, dB = _k_past_2_24_operands(M, N, K)
+    dC = torch.full((M, N), float("nan"), device="cuda")
+    abi.sgemm_variant(vid, M, N, K, 1.0, dA, K, dB, N, 0.0, dC, N)
     torch.cuda.synchronize()
     Cref, _, _ = oracle.ref_gemm(dA.cpu().numpy(), dB.cpu().numpy())
     assert np.array_equal(dC.cpu().numpy().astype(np.float64), Cref)

@@ -125,6 +125,27 @@ def test_every_variant_vector_path_padded(loaded):
     assert not fails, "\n".join(fails[:10])
 
 
+def test_every_variant_interior_tiles(loaded):
+    # 520 x 520 x 256 with padded leading dimensions (multiples of 4, NaN in
+    # the padding): two whole 256-row tile rows and columns, every K-step
+    # dividing K, so even the 256-wide tiles get interior work-groups that run
+    # the unmasked loop, beside the edge tiles of the last 8 rows and columns.
+    M, N, K = 520, 520, 256
+    lda, ldb, ldc = K + 4, N + 8, N + 4
+    A = datagen.uniform((25, M, N, K, 0), M, K)
+    B = datagen.uniform((25, M, N, K, 1), K, N)
+    C0 = datagen.uniform((25, M, N, K, 2), M, N)
+    fails = []
+    for vid, name in loaded:
+        C, guard = run_gemm(vid, A, B, C0, 1.0, 0.5, lda, ldb, ldc)
+        try:
+            _check(C, A, B, C0, 1.0, 0.5, name)
+            assert guard, f"{name}: wrote outside C"
+        except AssertionError as e:
+            fails.append(str(e))
+    assert not fails, "\n".join(fails[:10])
+
+
 def test_every_variant_integers_bitwise(loaded):
     # Integer entries in [-8, 8], K = 260: partial sums stay below 2^24, so
     # every variant must reproduce the exact integer result bit for bit.
@@ -239,8 +260,9 @@ def _split_variants(loaded):
 
 def test_k_split_variants_long_k(loaded):
     # Long K over few tiles: every K-split variant splits here.  Two calls in
-    # a row must both be right (the arrival counters reset themselves) and
-    # bitwise equal (partials are summed in a fixed order).
+    # a row must both be right (each call rewrites every slice of partial
+    # products it reduces) and bitwise equal (partials are summed in a fixed
+    # order).
     M, N, K = 96, 80, 2000
     A, B, C0 = datagen.gemm_operands(27, M, N, K, beta=0.75)
     splits = _split_variants(loaded)
