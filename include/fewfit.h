@@ -89,8 +89,15 @@ extern "C" {
  *
  * Variants that split K over work-groups write their partial products to
  * one workspace per device (allocated when such a variant is first loaded)
- * and a second kernel sums them; such calls on one device must not overlap
- * in time (issue them on one stream, or order the streams).
+ * and a second kernel sums them.  Calls that use that workspace (or the
+ * other per-device buffers of sgemm_form()) are ordered across streams by
+ * the library: a call on another stream than the previous such call waits
+ * for it (an event recorded behind each such call), so concurrent calls on
+ * several streams give the same results as one stream.  A call made while
+ * its stream is being captured into a HIP graph takes no part in that
+ * ordering (the library cannot see when the graph is launched): replays of
+ * such a graph are ordered with other calls on the device only by the
+ * stream they are launched on.
  *
  * Each variant is deterministic: the same inputs give bitwise the same C.
  * Different variants may round differently.  The result of every variant
@@ -126,14 +133,13 @@ int variant_set_load(const char *path);
  * operands within 2^18 of each matrix's largest magnitude; smaller ones
  * lose bits of their low piece to FP16 underflow), plus FP32 accumulation.
  * The fp16s and fp16x3 forms first reduce max|A| and max|B| on the device
- * into the per-device workspace (calls on one device must not overlap in
- * time) and need finite inputs.  Pre-split variants (LDS mode 2) first form the
- * pieces of A and B into a 1 GiB per-device pieces workspace (allocated
- * when such a variant is loaded; calls on one device must not overlap in
- * time) and return FF_ERR_TOO_LARGE when 2 * T * (Mp + Np) * Kp bytes
- * exceed it (T pieces per value, Mp, Np rounded up to the tile, Kp = K
- * rounded up to 64).  Other semantics as sgemm(); FF_ERR_ARG for an
- * unknown form.
+ * into the per-device workspace and need finite inputs.  Pre-split variants
+ * (LDS mode 2) first form the pieces of A and B into a 1 GiB per-device
+ * pieces workspace (allocated when such a variant is loaded) and return
+ * FF_ERR_TOO_LARGE when 2 * T * (Mp + Np) * Kp bytes exceed it (T pieces
+ * per value, Mp, Np rounded up to the tile, Kp = K rounded up to 64).  Calls
+ * on several streams are ordered on these buffers as described at sgemm().
+ * Other semantics as sgemm(); FF_ERR_ARG for an unknown form.
  */
 int sgemm_form(int form, int64_t M, int64_t N, int64_t K, float alpha,
                const float *A, int64_t lda, const float *B, int64_t ldb,

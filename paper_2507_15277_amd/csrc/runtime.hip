@@ -27,6 +27,7 @@
 
 #include "../../include/fewfit.h"
 #include "ptune_internal.h"
+#include "setfile.h"
 
 #define FF_EXPORT extern "C" __attribute__((visibility("default")))
 
@@ -53,13 +54,9 @@ int hip_fail(hipError_t e, const char* what)
 // ---------------------------------------------------------------------------
 // Variant descriptors and registry
 
-struct Variant {
-    int id = -1;
-    std::string name;
-    int mwg = 0, nwg = 0, kwg = 0, mi = 0, wm = 0, wn = 0, sk = 0, vw = 0, lds = 0, gm = 0, sg = 0;
-    int prec = 0;  // 0 FP32 MFMA; 1 bf16x3, 2 bf16x6, 3 scaled fp16, 4 scaled fp16 in two pieces
-                   // (16-bit MFMA, FP32 accumulation)
-    int pd = 1;    // prefetch depth (compiled into the kernel; not a launch parameter)
+struct Variant : FfDesc {
+    Variant() = default;
+    explicit Variant(const FfDesc& d) : FfDesc(d) {}
     hipModule_t mod = nullptr;
     hipFunction_t fvec = nullptr;  // VW-wide loads
     hipFunction_t fsca = nullptr;  // scalar loads
@@ -68,35 +65,7 @@ struct Variant {
     int grp_blocks = 0;            // grouped grid: resident work-groups per device
     hipFunction_t fpa = nullptr;   // pre-split forms (LDS mode 2): pieces of A
     hipFunction_t fpb = nullptr;   // pre-split forms: pieces of B, transposed
-    bool presplit() const { return prec > 0 && lds == 2; }
-    int terms() const   // 16-bit pieces per value: bf16x3 2, bf16x6 3, fp16s 1, fp16x3 2
-    {
-        switch (prec) {
-            case 1: case 4: return 2;
-            case 2: return 3;
-            default: return 1;
-        }
-    }
-    bool scaled() const { return prec >= 3; }   // per-matrix power-of-two prescale
-    int threads() const { return 64 * wm * wn * sk; }
 };
-
-// "<id> <name> MWG NWG KWG MI WM WN SK VW LDS GM SG PREC PD"
-bool parse_descriptor(std::istringstream& is, Variant& v)
-{
-    if (!(is >> v.id >> v.name >> v.mwg >> v.nwg >> v.kwg >> v.mi >> v.wm >> v.wn >> v.sk >> v.vw >> v.lds >> v.gm >>
-          v.sg >> v.prec >> v.pd))
-        return false;
-    if (v.pd < 1 || v.pd > 2) return false;
-    if (v.id < 0 || v.mwg <= 0 || v.nwg <= 0 || v.kwg <= 0 || (v.mi != 16 && v.mi != 32) || v.wm <= 0 ||
-        v.wn <= 0 || v.sk <= 0 || (v.vw != 1 && v.vw != 2 && v.vw != 4) || v.lds < 0 || v.lds > 2 || (v.lds == 2 && v.vw != 4) ||
-        v.gm <= 0 || v.sg < 1 || v.sg > 64 || v.prec < 0 || v.prec > 4 || v.threads() > 1024)
-        return false;
-    if (v.prec > 0 && (v.sk != 1 || v.lds < 1)) return false;
-    for (char c : v.name)
-        if (!(isalnum((unsigned char)c) || c == '_')) return false;
-    return true;
-}
 
 struct VarSet {
     std::vector<int> ids;                        // members
@@ -113,8 +82,8 @@ struct VarSet {
     std::vector<double> train_lg;                // log2 sizes of the training shapes
 };
 
-constexpr int kForms = 5;
-constexpr int kMaxMembers = 64;  // variants in one set
+constexpr int kForms = kFfForms;
+constexpr int kMaxMembers = kFfMaxMembers;  // variants in one set
 std::mutex g_mu;
 std::map<int, std::shared_ptr<Variant>> g_variants;
 std::shared_ptr<const VarSet> g_set[kForms];  // one loaded set per precision form
@@ -128,6 +97,14 @@ struct Workspace {
     float* ws = nullptr;
     float* scale = nullptr;  // FP16 forms: block maxima of |A| and |B|, then the exponents {eA, eB}
     short* pieces = nullptr; // pre-split forms: 16-bit pieces of A and B
+    // Order of the calls that use these buffers, across streams: `last` is
+    // recorded on the stream of the latest such call (`last_stream`), and a
+    // call on another stream first waits for it.  `mu` keeps the wait, the
+    // launches and the record of one call together.
+    std::mutex mu;
+    hipEvent_t last = nullptr;
+    hipStream_t last_stream = nullptr;
+    bool last_valid = false;
 };
 // Pieces of the pre-split forms: TERMS planes of A (Mp x Kp) and of B
 // (Np x Kp) 16-bit values, Mp, Np rounded up to the tile and Kp to 64.
@@ -135,6 +112,8 @@ constexpr size_t kPieceBytes = size_t(1) << 30;
 constexpr int kPieceKPad = 64;
 Workspace g_ws[kMaxDevices];
 constexpr int kMaxBlocks = 1024;  // per matrix, for the |A|, |B| maxima
+// Maxima of both matrices, then the two exponents.
+constexpr size_t kScaleBytes = (2 * kMaxBlocks + 4) * sizeof(float);
 
 int ensure_workspace()
 {
@@ -145,10 +124,13 @@ int ensure_workspace()
     Workspace& w = g_ws[dev];
     if (w.ws != nullptr) return FF_OK;
     e = hipMalloc(&w.ws, kWsBytes);
-    if (e == hipSuccess) e = hipMalloc(&w.scale, (2 * kMaxBlocks + 4) * sizeof(float));
+    if (e == hipSuccess) e = hipMalloc(&w.scale, kScaleBytes);
+    if (e == hipSuccess && w.last == nullptr) e = hipEventCreateWithFlags(&w.last, hipEventDisableTiming);
     if (e != hipSuccess) {
         if (w.ws) (void)hipFree(w.ws);
-        w = Workspace{};
+        if (w.scale) (void)hipFree(w.scale);
+        w.ws = nullptr;
+        w.scale = nullptr;
         return hip_fail(e, "allocate workspace");
     }
     return FF_OK;
@@ -161,6 +143,10 @@ int ensure_pieces()
     if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
     if (dev < 0 || dev >= kMaxDevices) return fail(FF_ERR_ARG, "device %d beyond the supported %d", dev, kMaxDevices);
     if (g_ws[dev].pieces != nullptr) return FF_OK;
+    if (g_ws[dev].last == nullptr) {
+        e = hipEventCreateWithFlags(&g_ws[dev].last, hipEventDisableTiming);
+        if (e != hipSuccess) return hip_fail(e, "create the workspace event");
+    }
     e = hipMalloc(&g_ws[dev].pieces, kPieceBytes);
     if (e != hipSuccess) {
         g_ws[dev].pieces = nullptr;
@@ -476,8 +462,28 @@ int64_t launch_groups(const Variant& v, int64_t M, int64_t N, int64_t K, bool ha
     return nb * split_count(v, M, N, K, have_ws);
 }
 
+// Device buffers one call may use, and their sizes: the K-split slices, the
+// FP16 maxima and exponents, the pieces of the pre-split forms.  Null where
+// absent.
+struct Buffers {
+    float* ws = nullptr;
+    size_t ws_bytes = 0;
+    float* scale = nullptr;
+    short* pieces = nullptr;
+    size_t pieces_bytes = 0;
+};
+
+// Bytes of pieces a pre-split variant forms for (M, N, K): T planes of A
+// (Mp x Kp) and of B (Np x Kp) 16-bit values.
+size_t presplit_bytes(const Variant& v, int64_t M, int64_t N, int64_t K)
+{
+    const int64_t Mp = (M + v.mwg - 1) / v.mwg * v.mwg, Np = (N + v.nwg - 1) / v.nwg * v.nwg;
+    return (size_t)(2 * (int64_t)v.terms() * (Mp + Np) * launch_k(v, K));
+}
+
 int launch_variant(const Variant& v, int64_t M, int64_t N, int64_t K, float alpha, const float* A,
-                   int64_t lda, const float* B, int64_t ldb, float beta, float* C, int64_t ldc, hipStream_t s)
+                   int64_t lda, const float* B, int64_t ldb, float beta, float* C, int64_t ldc, const Buffers& buf,
+                   hipStream_t s)
 {
     const int64_t nbm = (M + v.mwg - 1) / v.mwg, nbn = (N + v.nwg - 1) / v.nwg;
     const int64_t nb = nbm * nbn;
@@ -493,41 +499,43 @@ int launch_variant(const Variant& v, int64_t M, int64_t N, int64_t K, float alph
                             aligned_for(A, w) && aligned_for(B, w));
     hipFunction_t f = vec ? v.fvec : v.fsca;
     const float* prescale = nullptr;
+    // Every check that can fail comes before the first launch.
+    const int64_t nkt = (launch_k(v, K) + v.kwg - 1) / v.kwg;
+    float* ws = buf.ws;
+    int splits = split_count(v, M, N, K, ws != nullptr);
+    if (splits == 1) ws = nullptr;
+    if (splits > 1 && (size_t)splits * (size_t)(M * N) * sizeof(float) > buf.ws_bytes)
+        return fail(FF_ERR_TOO_LARGE, "%d K splits of %lld x %lld exceed the %zu-byte workspace", splits,
+                    (long long)M, (long long)N, buf.ws_bytes);
+    if (v.scaled() && buf.scale == nullptr) return fail(FF_ERR_HIP, "fp16 form: no scale buffer on this device");
+    if (v.presplit()) {
+        if (buf.pieces == nullptr) return fail(FF_ERR_HIP, "pre-split form: no pieces workspace on this device");
+        const size_t need = presplit_bytes(v, M, N, K);
+        if (need > buf.pieces_bytes)
+            return fail(FF_ERR_TOO_LARGE, "pre-split form: %zu bytes of pieces exceed the %zu-byte workspace", need,
+                        buf.pieces_bytes);
+    }
     if (v.scaled()) {
-        int dev = 0;
-        if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices || g_ws[dev].scale == nullptr)
-            return fail(FF_ERR_HIP, "fp16 form: no scale buffer on this device");
-        float* buf = g_ws[dev].scale;
+        float* sbuf = buf.scale;
         // One block per row unit (a row, or kAbsCols columns of it), at
         // most kMaxBlocks blocks per matrix.
         const int64_t units = std::max(M * ((K + kAbsCols - 1) / kAbsCols), K * ((N + kAbsCols - 1) / kAbsCols));
         const int nbk = (int)std::max<int64_t>(1, std::min<int64_t>(kMaxBlocks, units));
-        hipLaunchKernelGGL(ff_absmax_blocks, dim3(2 * nbk), dim3(256), 0, s, M, K, A, lda, N, B, ldb, nbk, buf);
-        hipLaunchKernelGGL(ff_fp16_prescale, dim3(1), dim3(256), 0, s, nbk, buf);
+        hipLaunchKernelGGL(ff_absmax_blocks, dim3(2 * nbk), dim3(256), 0, s, M, K, A, lda, N, B, ldb, nbk, sbuf);
+        hipLaunchKernelGGL(ff_fp16_prescale, dim3(1), dim3(256), 0, s, nbk, sbuf);
         hipError_t e0 = hipGetLastError();
         if (e0 != hipSuccess) return hip_fail(e0, "launch fp16 prescale");
-        prescale = buf + 2 * kMaxBlocks;
+        prescale = sbuf + 2 * kMaxBlocks;
     }
-    const int64_t nkt = (launch_k(v, K) + v.kwg - 1) / v.kwg;
-    float* ws = current_workspace();
-    int splits = split_count(v, M, N, K, ws != nullptr);
-    if (splits == 1) ws = nullptr;
     int kper = (int)((nkt + splits - 1) / splits);
     int Mi = (int)M, Ni = (int)N, Ki = (int)K;
     long la = (long)lda, lb = (long)ldb, lc = (long)ldc;
     hipError_t e;
     if (v.presplit()) {
         // Form the pieces of A and B, then the GEMM on them.
-        int dev = 0;
-        if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices || g_ws[dev].pieces == nullptr)
-            return fail(FF_ERR_HIP, "pre-split form: no pieces workspace on this device");
         int Mp = (int)(nbm * v.mwg), Np = (int)(nbn * v.nwg), Kp = (int)launch_k(v, K);
         const int64_t T = v.terms();
-        const int64_t need = 2 * T * ((int64_t)Mp + Np) * Kp;
-        if (need > (int64_t)kPieceBytes)
-            return fail(FF_ERR_TOO_LARGE, "pre-split form: %lld bytes of pieces exceed the %zu-byte workspace",
-                        (long long)need, kPieceBytes);
-        short* PA = g_ws[dev].pieces;
+        short* PA = buf.pieces;
         short* PB = PA + T * (int64_t)Mp * Kp;
         long pa_plane = (long)Mp * Kp, pb_plane = (long)Np * Kp;
         int vecA = (K % 4 == 0 && lda % 4 == 0 && aligned_for(A, 4)) ? 1 : 0;
@@ -568,20 +576,25 @@ int launch_variant(const Variant& v, int64_t M, int64_t N, int64_t K, float alph
     return FF_OK;
 }
 
-// Shared body of sgemm() and sgemm_variant(); `v` may be null for the
-// dispatch path, in which case the set picks it.
-int gemm_common(const Variant* v, int form, int64_t M, int64_t N, int64_t K, float alpha, const float* A,
-                int64_t lda, const float* B, int64_t ldb, float beta, float* C, int64_t ldc, void* stream)
+// Validation, quick returns and the choice of variant shared by every GEMM
+// entry point.  Returns FF_OK with *v set when a GEMM kernel must run,
+// FF_OK with *v null when the call is complete (nothing to do, or C was
+// only scaled), or an error.  `v` in: the explicit variant, or null for
+// dispatch through the set of `form`.
+int gemm_prepare(const Variant*& v, std::shared_ptr<Variant>& hold, int form, int64_t M, int64_t N, int64_t K,
+                 float alpha, const float* A, int64_t lda, const float* B, int64_t ldb, float beta, float* C,
+                 int64_t ldc, hipStream_t s)
 {
     int rc = validate(M, N, K, alpha, A, lda, B, ldb, beta, C, ldc);
     if (rc != FF_OK) return rc;
-    hipStream_t s = static_cast<hipStream_t>(stream);
-    if (M == 0 || N == 0) return FF_OK;
-    if (alpha == 0.0f || K == 0) {
-        if (beta == 1.0f) return FF_OK;
-        return launch_scale(M, N, beta, C, ldc, s);
+    if (M == 0 || N == 0) {
+        v = nullptr;
+        return FF_OK;
     }
-    std::shared_ptr<Variant> hold;
+    if (alpha == 0.0f || K == 0) {
+        v = nullptr;
+        return beta == 1.0f ? FF_OK : launch_scale(M, N, beta, C, ldc, s);
+    }
     if (v == nullptr) {
         int id = variant_select_form(form, M, N, K);
         if (id < 0) return id;
@@ -591,7 +604,51 @@ int gemm_common(const Variant* v, int form, int64_t M, int64_t N, int64_t K, flo
         hold = it->second;
         v = hold.get();
     }
-    return launch_variant(*v, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, s);
+    return FF_OK;
+}
+
+bool stream_capturing(hipStream_t s)
+{
+    hipStreamCaptureStatus st = hipStreamCaptureStatusNone;
+    return hipStreamIsCapturing(s, &st) == hipSuccess && st != hipStreamCaptureStatusNone;
+}
+
+// Shared body of sgemm(), sgemm_form() and sgemm_variant(); `v` may be null
+// for the dispatch path, in which case the set picks it.  A call that uses
+// the device's shared buffers (K-split slices, FP16 exponents, pieces) is
+// ordered after the previous such call when that one ran on another stream:
+// it waits for the event recorded behind it, then records its own.  Calls
+// made while their stream is captured into a graph neither wait nor record
+// (an event recorded inside a capture cannot be waited on outside it).
+int gemm_common(const Variant* v, int form, int64_t M, int64_t N, int64_t K, float alpha, const float* A,
+                int64_t lda, const float* B, int64_t ldb, float beta, float* C, int64_t ldc, void* stream)
+{
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    std::shared_ptr<Variant> hold;
+    int rc = gemm_prepare(v, hold, form, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, s);
+    if (rc != FF_OK || v == nullptr) return rc;
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    if (dev < 0 || dev >= kMaxDevices) return fail(FF_ERR_ARG, "device %d beyond the supported %d", dev, kMaxDevices);
+    Workspace& w = g_ws[dev];
+    Buffers buf{w.ws, kWsBytes, w.scale, w.pieces, kPieceBytes};
+    const bool shared = v->scaled() || v->presplit() || split_count(*v, M, N, K, buf.ws != nullptr) > 1;
+    if (!shared) return launch_variant(*v, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, buf, s);
+    std::lock_guard<std::mutex> lk(w.mu);
+    const bool capturing = stream_capturing(s);
+    if (!capturing && w.last_valid && w.last_stream != s) {
+        e = hipStreamWaitEvent(s, w.last, 0);
+        if (e != hipSuccess) return hip_fail(e, "order the workspace after the previous call");
+    }
+    rc = launch_variant(*v, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, buf, s);
+    if (rc == FF_OK && !capturing && w.last != nullptr) {
+        e = hipEventRecord(w.last, s);
+        if (e != hipSuccess) return hip_fail(e, "record the workspace event");
+        w.last_stream = s;
+        w.last_valid = true;
+    }
+    return rc;
 }
 
 std::shared_ptr<Variant> find_variant(int id)
@@ -688,6 +745,7 @@ ff_screen_cmp(int64_t M, int64_t N, const float* C, int64_t ldc, const double* r
 
 }  // namespace
 
+
 // ===========================================================================
 // Exported C ABI
 
@@ -696,23 +754,13 @@ FF_EXPORT const char* fewfit_last_error(void) { return g_err.c_str(); }
 FF_EXPORT int variant_manifest_load(const char* dir)
 {
     if (dir == nullptr) return fail(FF_ERR_ARG, "variant_manifest_load: dir is NULL");
-    const std::string d(dir);
-    std::ifstream f(d + "/manifest.txt");
-    if (!f) return fail(FF_ERR_IO, "cannot open %s/manifest.txt", dir);
-    std::vector<Variant> list;
-    std::string line;
-    int lineno = 0;
-    while (std::getline(f, line)) {
-        ++lineno;
-        if (line.empty() || line[0] == '#') continue;
-        std::istringstream is(line);
-        Variant v;
-        if (!parse_descriptor(is, v)) return fail(FF_ERR_PARSE, "manifest line %d: bad descriptor", lineno);
-        list.push_back(v);
-    }
+    std::vector<FfDesc> list;
+    std::string err;
+    int rc = ff_read_manifest(dir, list, err);
+    if (rc != FF_OK) return fail(rc, "%s", err.c_str());
     std::lock_guard<std::mutex> lk(g_mu);
-    for (const Variant& v : list) {
-        int rc = register_variant(v, d);
+    for (const FfDesc& d : list) {
+        rc = register_variant(Variant(d), dir);
         if (rc != FF_OK) return rc;
     }
     return (int)list.size();
@@ -777,120 +825,38 @@ static int wave_table(VarSet& set)
     return FF_OK;
 }
 
-// Set file format (text, '#' comments):
-//   fewfit-set 1
-//   arch <gfx name>
-//   codedir <dir>          code objects, relative to the set file's directory
-//   form <name>            optional: fp32 (default), bf16x3, bf16x6, fp16s or fp16x3;
-//                          every member must be of that form
-//   variant <descriptor>   k lines, descriptor as in the manifest
-//   rule <M> <N> <K> <id> <c_1> ... <c_k>
-//                          one line per training shape (after the variant
-//                          lines): its winner, a member, and every member's
-//                          log-slowdown on it ("inf" where it failed)
-//   end
+// Load a set file (format and checks in setfile.cpp).
 FF_EXPORT int variant_set_load(const char* path)
 {
     if (path == nullptr) return fail(FF_ERR_ARG, "variant_set_load: path is NULL");
-    std::ifstream f(path);
-    if (!f) return fail(FF_ERR_IO, "cannot open set file %s", path);
-    auto set = std::make_shared<VarSet>();
-    std::vector<Variant> members;
-    std::string arch, codedir, line;
-    int form = 0;
-    bool header = false, ended = false;
-    int lineno = 0;
-    while (std::getline(f, line)) {
-        ++lineno;
-        size_t h = line.find('#');
-        if (h != std::string::npos) line = line.substr(0, h);
-        std::istringstream is(line);
-        std::string key;
-        if (!(is >> key)) continue;
-        if (ended) return fail(FF_ERR_PARSE, "%s:%d: text after 'end'", path, lineno);
-        if (!header) {
-            int ver = 0;
-            if (key != "fewfit-set" || !(is >> ver) || ver != 1)
-                return fail(FF_ERR_PARSE, "%s:%d: expected 'fewfit-set 1'", path, lineno);
-            header = true;
-            continue;
-        }
-        std::string extra;
-        if (key == "arch") {
-            if (!(is >> arch)) return fail(FF_ERR_PARSE, "%s:%d: arch needs a value", path, lineno);
-        } else if (key == "codedir") {
-            if (!(is >> codedir)) return fail(FF_ERR_PARSE, "%s:%d: codedir needs a value", path, lineno);
-        } else if (key == "form") {
-            std::string f;
-            static const char* names[kForms] = {"fp32", "bf16x3", "bf16x6", "fp16s", "fp16x3"};
-            if (!(is >> f)) return fail(FF_ERR_PARSE, "%s:%d: form needs a value", path, lineno);
-            form = -1;
-            for (int i = 0; i < kForms; ++i)
-                if (f == names[i]) form = i;
-            if (form < 0) return fail(FF_ERR_PARSE, "%s:%d: unknown form '%s'", path, lineno, f.c_str());
-        } else if (key == "variant") {
-            Variant v;
-            if (!parse_descriptor(is, v)) return fail(FF_ERR_PARSE, "%s:%d: bad variant descriptor", path, lineno);
-            for (const Variant& o : members)
-                if (o.id == v.id) return fail(FF_ERR_PARSE, "%s:%d: duplicate variant %d", path, lineno, v.id);
-            if (!set->shapes.empty())
-                return fail(FF_ERR_PARSE, "%s:%d: variant lines must precede the rules", path, lineno);
-            members.push_back(v);
-            set->ids.push_back(v.id);
-        } else if (key == "rule") {
-            long long m, n, k;
-            int id;
-            if (!(is >> m >> n >> k >> id) || m < 1 || n < 1 || k < 1)
-                return fail(FF_ERR_PARSE, "%s:%d: bad rule", path, lineno);
-            const auto pos = std::find(set->ids.begin(), set->ids.end(), id);
-            if (pos == set->ids.end())
-                return fail(FF_ERR_PARSE, "%s:%d: rule names variant %d outside the set", path, lineno, id);
-            std::vector<double> c(set->ids.size());
-            for (size_t j = 0; j < c.size(); ++j) {
-                std::string tok;
-                if (!(is >> tok)) return fail(FF_ERR_PARSE, "%s:%d: rule needs %zu member costs", path, lineno, c.size());
-                char* end = nullptr;
-                c[j] = (tok == "inf") ? INFINITY : std::strtod(tok.c_str(), &end);
-                if (tok != "inf" && (end == tok.c_str() || *end != '\0' || !(c[j] >= 0.0)))
-                    return fail(FF_ERR_PARSE, "%s:%d: bad member cost '%s'", path, lineno, tok.c_str());
-            }
-            if (c[pos - set->ids.begin()] != *std::min_element(c.begin(), c.end()))
-                return fail(FF_ERR_PARSE, "%s:%d: rule winner is not the cheapest member", path, lineno);
-            set->shapes.push_back({m, n, k});
-            set->flat.insert(set->flat.end(), {(int64_t)m, (int64_t)n, (int64_t)k});
-            set->winners.push_back(id);
-            set->cost.insert(set->cost.end(), c.begin(), c.end());
-        } else if (key == "end") {
-            ended = true;
-        } else {
-            return fail(FF_ERR_PARSE, "%s:%d: unknown key '%s'", path, lineno, key.c_str());
-        }
-        if (key != "end" && (is >> extra)) return fail(FF_ERR_PARSE, "%s:%d: trailing text", path, lineno);
-    }
-    if (!header) return fail(FF_ERR_PARSE, "%s: empty set file", path);
-    if (!ended) return fail(FF_ERR_PARSE, "%s: missing 'end' (truncated file?)", path);
-    if (arch.empty() || codedir.empty() || members.empty() || set->shapes.empty())
-        return fail(FF_ERR_PARSE, "%s: needs arch, codedir, at least one variant and one rule", path);
-    for (const Variant& v : members)
-        if (v.prec != form) return fail(FF_ERR_PARSE, "%s: variant %d is not of the set's form", path, v.id);
-    if (members.size() > (size_t)kMaxMembers)
-        return fail(FF_ERR_PARSE, "%s: %zu members exceed the limit of %d", path, members.size(), kMaxMembers);
-
+    FfSetFile file;
+    std::string err;
+    int rc = ff_read_set_file(path, file, err);
+    if (rc != FF_OK) return fail(rc, "%s", err.c_str());
     std::string dev;
-    int rc = device_arch(dev);
+    rc = device_arch(dev);
     if (rc != FF_OK) return rc;
-    if (dev != arch) return fail(FF_ERR_ARCH, "set built for %s, device is %s", arch.c_str(), dev.c_str());
+    if (dev != file.arch) return fail(FF_ERR_ARCH, "set built for %s, device is %s", file.arch.c_str(), dev.c_str());
 
+    auto set = std::make_shared<VarSet>();
+    for (const FfDesc& d : file.members) {
+        set->ids.push_back(d.id);
+        set->members.emplace_back(d);
+    }
+    set->shapes = file.shapes;
+    for (const auto& sh : file.shapes) set->flat.insert(set->flat.end(), {sh[0], sh[1], sh[2]});
+    set->winners = file.winners;
+    set->cost = file.cost;
+    const std::string& codedir = file.codedir;
     const std::string dir = codedir[0] == '/' ? codedir : dirname_of(path) + "/" + codedir;
     std::lock_guard<std::mutex> lk(g_mu);
-    for (const Variant& v : members) {
+    for (const Variant& v : set->members) {
         rc = register_variant(v, dir);
         if (rc != FF_OK) return rc;
     }
-    set->members = members;
     rc = wave_table(*set);
     if (rc != FF_OK) return rc;
-    g_set[form] = set;
+    g_set[file.form] = set;
     return (int)set->ids.size();
 }
 
