@@ -146,6 +146,31 @@ int sgemm_form(int form, int64_t M, int64_t N, int64_t K, float alpha,
                float beta, float *C, int64_t ldc, void *stream);
 
 /*
+ * sgemm_form() for callers that cannot allocate device memory: code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc.
+ * Same dispatch, split count and kernels as sgemm_form(), so the result is
+ * bitwise equal to sgemm_form()'s on the same inputs; but every scratch
+ * buffer the kernels use comes from one fixed device array of
+ * FF_NOALLOC_SCRATCH_BYTES (256 MiB), which each device holds from this
+ * entry point's first call on it until the process ends.  The call makes no
+ * hipMalloc, hipFree or other allocating call (the variant set must be
+ * loaded beforehand; variant_set_load() allocates).  Layout of the array:
+ * 16 KiB of FP16 block maxima and exponents, then the pre-split pieces
+ * (2 * T * (Mp + Np) * Kp bytes, as at sgemm_form(), rounded up to 256),
+ * then the K-split slices (splits * M * N * 4 bytes); a call that needs
+ * more than the array returns FF_ERR_TOO_LARGE before any launch.  Every
+ * call on one device shares that device's array, which keeps the last
+ * call's contents (nothing in it must start at zero: each call writes what
+ * it reads).  Calls that overlap in time on one device race and give wrong
+ * results: issue them on one stream, or order the streams.  Returns as
+ * sgemm_form(); FF_ERR_HIP if the array's device address cannot be had.
+ */
+#define FF_NOALLOC_SCRATCH_BYTES ((size_t)256 << 20)
+int sgemm_form_noalloc(int form, int64_t M, int64_t N, int64_t K, float alpha,
+                       const float *A, int64_t lda, const float *B, int64_t ldb,
+                       float beta, float *C, int64_t ldc, void *stream);
+
+/*
  * Variant id that sgemm() would run for (M, N, K) under the loaded set.
  * Fig. 1 leaves the online picker open and Sec. V-I names unseen inputs as
  * a limitation; the rule used here (ptune_dispatch): find the training

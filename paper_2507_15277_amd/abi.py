@@ -31,7 +31,7 @@ EXPORTS = ("sgemm", "sgemm_form", "variant_set_load", "variant_select", "variant
            "sgemm_time", "screen_reference", "screen_compare", "ptune_postprocess",
            "ptune_cost", "ptune_select", "ptune_assign", "ptune_nearest", "ptune_dispatch",
            "ptune_select_total", "ptune_kmeans", "ptune_tree", "ptune_tree_route", "sgemm_grouped_plan",
-           "sgemm_grouped", "variant_work_groups")
+           "sgemm_grouped", "variant_work_groups", "sgemm_form_noalloc")
 
 
 class FewfitError(RuntimeError):
@@ -54,6 +54,7 @@ def lib():
         gemm_args = [i64, i64, i64, f32, vp, i64, vp, i64, f32, vp, i64, vp]
         L.sgemm.argtypes = gemm_args
         L.sgemm_form.argtypes = [i32] + gemm_args
+        L.sgemm_form_noalloc.argtypes = [i32] + gemm_args
         L.variant_select_form.argtypes = [i32, i64, i64, i64]
         L.sgemm_variant.argtypes = [i32] + gemm_args
         L.sgemm_time.argtypes = [i32] + gemm_args + [i32, i32, i32, vp]
@@ -123,6 +124,11 @@ def sgemm(M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, stream=None):
 def sgemm_form(form, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, stream=None):
     return _check(lib().sgemm_form(form, M, N, K, alpha, _ptr(A), lda, _ptr(B), ldb, beta, _ptr(C), ldc,
                                    _stream(stream)))
+
+
+def sgemm_form_noalloc(form, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, stream=None):
+    return _check(lib().sgemm_form_noalloc(form, M, N, K, alpha, _ptr(A), lda, _ptr(B), ldb, beta, _ptr(C), ldc,
+                                           _stream(stream)))
 
 
 def variant_select_form(form, M, N, K):

@@ -30,7 +30,7 @@ DEVICE_FLAGS = ["-O3", "-std=c++17", f"--offload-arch={ARCH}",
 
 
 def build_library(verbose=False) -> str:
-    srcs = [os.path.join(CSRC, "runtime.hip"), os.path.join(CSRC, "ptune.cpp"),
+    srcs = [os.path.join(CSRC, "runtime.hip"), os.path.join(CSRC, "noalloc.hip"), os.path.join(CSRC, "ptune.cpp"),
             os.path.join(CSRC, "setfile.cpp")]
     tmp = LIB + ".tmp"
     cmd = [HIPCC, *DEVICE_FLAGS, "-fPIC", "-shared", "-fvisibility=hidden", "-Wall",

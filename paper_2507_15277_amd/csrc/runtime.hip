@@ -27,6 +27,7 @@
 
 #include "../../include/fewfit.h"
 #include "ptune_internal.h"
+#include "runtime_internal.h"
 #include "setfile.h"
 
 #define FF_EXPORT extern "C" __attribute__((visibility("default")))
@@ -745,6 +746,43 @@ ff_screen_cmp(int64_t M, int64_t N, const float* C, int64_t ldc, const double* r
 
 }  // namespace
 
+// ===========================================================================
+// Internal entry points for the allocation-free path (noalloc.hip)
+
+namespace fewfit_internal {
+
+int set_error(int code, const char* msg) { return fail(code, "%s", msg); }
+
+int gemm_scratch(int form, int64_t M, int64_t N, int64_t K, float alpha, const float* A, int64_t lda,
+                 const float* B, int64_t ldb, float beta, float* C, int64_t ldc, void* stream, void* scratch,
+                 size_t bytes)
+{
+    if (form < 0 || form >= kForms) return fail(FF_ERR_ARG, "sgemm_form_noalloc: unknown form %d", form);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const Variant* v = nullptr;
+    std::shared_ptr<Variant> hold;
+    int rc = gemm_prepare(v, hold, form, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, s);
+    if (rc != FF_OK || v == nullptr) return rc;
+    // [0, kScaleRegion): maxima and exponents; then the pieces; then the
+    // K-split slices, each region starting on a 256-byte boundary.
+    constexpr size_t kScaleRegion = 16 << 10;
+    static_assert(kScaleBytes <= kScaleRegion, "scale region");
+    auto up256 = [](size_t x) { return (x + 255) / 256 * 256; };
+    const size_t pieces = v->presplit() ? up256(presplit_bytes(*v, M, N, K)) : 0;
+    const int splits = split_count(*v, M, N, K, true);
+    const size_t slices = splits > 1 ? (size_t)splits * (size_t)(M * N) * sizeof(float) : 0;
+    if (scratch == nullptr || kScaleRegion + pieces + slices > bytes)
+        return fail(FF_ERR_TOO_LARGE,
+                    "sgemm_form_noalloc: the call needs %zu bytes of scratch (%zu of pieces, %d K-split slices of "
+                    "%zu) beyond the %zu-byte array", kScaleRegion + pieces + slices, pieces, splits,
+                    slices / std::max(splits, 1), bytes);
+    char* base = static_cast<char*>(scratch);
+    Buffers buf{reinterpret_cast<float*>(base + kScaleRegion + pieces), bytes - kScaleRegion - pieces,
+                reinterpret_cast<float*>(base), reinterpret_cast<short*>(base + kScaleRegion), pieces};
+    return launch_variant(*v, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, buf, s);
+}
+
+}  // namespace fewfit_internal
 
 // ===========================================================================
 // Exported C ABI
