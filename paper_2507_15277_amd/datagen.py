@@ -106,3 +106,20 @@ def random_split(seed, n_train=14, shapes=None):
 
 def square_shapes():
     return [(s, s, s) for s in SQUARE_SIZES]
+
+
+# The paper's input grid (Sec. V-B): M, N, K each in {256, 512, 1024, 4096}.
+PAPER_LEVELS = (256, 512, 1024, 4096)
+
+
+def fresh_shapes(n_random=20, seed=0, lo=128, hi=8192):
+    """Shapes that took no part in choosing a set or the dispatch rule: the
+    37 shapes of the paper's {256, 512, 1024, 4096}^3 grid that lie off the
+    27-shape tuning grid (each has a 512), then ``n_random`` shapes with M,
+    N, K each log-uniform on [lo, hi], rounded to integers."""
+    grid = set(grid27())
+    paper = [tuple(s) for s in itertools.product(PAPER_LEVELS, repeat=3) if tuple(s) not in grid]
+    rng = np.random.default_rng([6, seed])
+    x = np.exp(rng.uniform(np.log(lo), np.log(hi), (n_random, 3)))
+    rand = [tuple(int(v) for v in np.clip(np.rint(r), lo, hi)) for r in x]
+    return paper + rand

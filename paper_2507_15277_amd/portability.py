@@ -35,6 +35,9 @@ from .tune import load_rows, kernel_hash, current_hashes
 PKG = os.path.dirname(os.path.abspath(__file__))
 DATA_DIR = os.path.join(PKG, "data")
 TABLE = os.path.join(DATA_DIR, "mi355x_table.jsonl")
+# A second, independent FP32 table of the grid (another lease), for the
+# robustness of the selection.
+TABLE2 = os.path.join(DATA_DIR, "mi355x_table_run2.jsonl")
 KS = (1, 2, 4, 8)
 
 
@@ -210,6 +213,116 @@ def precision_report(rows, variants, write_sets=False, log=print):
     return out
 
 
+def read_set(path):
+    """(members, training shapes, ntrain x k member log-slowdowns) of a set file."""
+    members, train, cost = [], [], []
+    with open(path) as f:
+        for line in f:
+            p = line.split("#")[0].split()
+            if not p:
+                continue
+            if p[0] == "variant":
+                members.append(int(p[1]))
+            elif p[0] == "rule":
+                train.append(tuple(int(x) for x in p[1:4]))
+                cost.append([float(x) for x in p[5:]])
+    return members, train, np.array(cost)
+
+
+def fresh_report(rows, variants, log=print):
+    """Generalisation to shapes that chose nothing (Sec. V-H, V-I, Fig. 1):
+    the committed sets and their dispatch rule, frozen, on the 37 shapes of
+    the paper's {256, 512, 1024, 4096}^3 grid off the tuning grid and on
+    seeded log-uniform shapes in [128, 8192].  Per set: the fraction of the
+    per-shape best realised through dispatch and with a perfect in-set pick,
+    and the slowdown over the per-shape best (S/O) as a histogram."""
+    shapes = datagen.fresh_shapes()
+    n_paper = len(shapes) - 20
+    nv = len(variants)
+    t = matrix(rows, shapes, 0.0, nv)
+    fp32 = np.array([variants[v].prec == 0 for v in range(nv)])
+    t[~fp32, :] = np.inf
+    cols = [j for j in range(len(shapes)) if np.isfinite(t[:, j]).any()]
+    if len(cols) < len(shapes):
+        return None
+    best = t.min(axis=0)
+    out = {"shapes": [list(s) for s in shapes], "n_paper_grid": n_paper,
+           "geomean_tflops_best": geomean(tflops(s, best[j]) for j, s in enumerate(shapes)), "sets": {}}
+    edges = SO_EDGES + (math.inf,)
+    labels = [("fixed", tuned.FIXED_SET)] + \
+        [(f"k{k}", tuned.set_path(k)) for k in KS]
+    for label, path in labels:
+        members, train, cost = read_set(path)
+        picks = [dispatch(train, members, cost, *s) for s in shapes]
+        real = [float(best[j] / t[picks[j], j]) for j in range(len(shapes))]
+        inset = [float(best[j] / min(t[v, j] for v in members)) for j in range(len(shapes))]
+        so = [1.0 / x for x in real]
+        rec = {"members": members,
+               "frac_realised": geomean(real), "frac_inset": geomean(inset),
+               "frac_realised_paper_grid": geomean(real[:n_paper]),
+               "frac_realised_random": geomean(real[n_paper:]),
+               "frac_inset_paper_grid": geomean(inset[:n_paper]),
+               "frac_inset_random": geomean(inset[n_paper:]),
+               "geomean_tflops_realised": geomean(tflops(s, t[picks[j], j]) for j, s in enumerate(shapes)),
+               "so_max": max(so),
+               "so_hist": {"edges": list(SO_EDGES),
+                           "counts": [sum(1 for x in so if lo <= x < hi) for lo, hi in zip(edges[:-1], edges[1:])]},
+               "per_shape": [{"M": s[0], "N": s[1], "K": s[2], "variant": int(picks[j]),
+                              "frac": real[j], "inset_frac": inset[j]} for j, s in enumerate(shapes)]}
+        out["sets"][label] = rec
+        log(f"[fresh] {label}: realised {rec['frac_realised']:.4f} (paper grid {rec['frac_realised_paper_grid']:.4f}, "
+            f"random {rec['frac_realised_random']:.4f}), in-set {rec['frac_inset']:.4f}, max S/O {rec['so_max']:.2f}")
+    return out
+
+
+def robustness_report(rows, rows2, variants, log=print):
+    """How much the selection rests on one table build (Sec. V-C, V-E): a
+    second FP32 table of the same grid, timed independently on another
+    lease, against the first.  Per shape the spread of the per-shape best;
+    per k the sets chosen from each table, their overlap, each set's
+    fraction of the per-shape best on the other table, and the sets chosen
+    from mean instead of median times; the shader clock seen while timing."""
+    shapes = datagen.grid27()
+    nv = len(variants)
+    t1 = matrix(rows, shapes, 0.0, nv)
+    t2 = matrix(rows2, shapes, 0.0, nv)
+    if not (np.isfinite(t2).any(axis=0).all() and np.isfinite(t1).any(axis=0).all()):
+        return None
+    tm = matrix(rows, shapes, 0.0, nv, field="ms_mean")
+    train, _ = datagen.checkerboard_split(shapes)
+    train_idx = [shapes.index(s) for s in train]
+    b1, b2 = t1.min(axis=0), t2.min(axis=0)
+    spread = np.abs(b2 / b1 - 1.0)
+    out = {"per_shape_best_rel_diff_median": float(np.median(spread)),
+           "per_shape_best_rel_diff_max": float(np.max(spread)),
+           "geomean_tflops_best": [geomean(tflops(s, b1[j]) for j, s in enumerate(shapes)),
+                                   geomean(tflops(s, b2[j]) for j, s in enumerate(shapes))],
+           "same_per_shape_winner": int(sum(int(np.argmin(t1[:, j])) == int(np.argmin(t2[:, j]))
+                                            for j in range(len(shapes)))),
+           "sets": {}}
+    for k in KS:
+        k1, c1, _ = abi.ptune_select(t1, k, shapes=train_idx, method=-1)
+        k2, c2, _ = abi.ptune_select(t2, k, shapes=train_idx, method=-1)
+        km, _, _ = abi.ptune_select(tm, k, shapes=train_idx, method=-1)
+        rec = {"kappa_run1": list(k1), "kappa_run2": list(k2), "overlap": len(set(k1) & set(k2)),
+               "train_frac_run1": 1.0 / c1, "train_frac_run2": 1.0 / c2,
+               "run1_set_on_run2": 1.0 / abi.ptune_cost(t2, k1, train_idx),
+               "run2_set_on_run1": 1.0 / abi.ptune_cost(t1, k2, train_idx),
+               "all27_run1_set_on_run2": 1.0 / abi.ptune_cost(t2, k1),
+               "kappa_mean_selection": list(km), "mean_vs_median_overlap": len(set(km) & set(k1)),
+               "mean_set_train_frac_median_times": 1.0 / abi.ptune_cost(t1, km, train_idx)}
+        out["sets"][str(k)] = rec
+        log(f"[robust] k={k}: run1 {list(k1)} run2 {list(k2)} overlap {rec['overlap']}; run1 set on run2 "
+            f"{rec['run1_set_on_run2']:.4f} (own {rec['train_frac_run2']:.4f}); mean-selected {list(km)}")
+    for name, rr in (("run1", rows), ("run2", rows2)):
+        clk = [r["sclk_mhz"] for r in rr if r.get("sclk_mhz") and r.get("status") == "ok"
+               and (r["M"], r["N"], r["K"]) in set(shapes)]
+        if clk:
+            out[f"sclk_mhz_{name}"] = {"median": float(np.median(clk)), "min": float(np.min(clk)),
+                                       "max": float(np.max(clk)), "samples": len(clk)}
+    return out
+
+
 def selector_comparison(t, shapes, train_idx, runs=30, log=print):
     """PortabilityTune (exact search) against the paper's two pruning
     implementations (Sec. IV-C-2, IV-C-3), on the training shapes, for each
@@ -379,6 +492,9 @@ def run(table=TABLE, write_sets=False, splits=5, log=print):
     report["selectors"] = selector_comparison(t, shapes, train_idx, log=log)
     report["fleet"] = fleet_comparison(t, shapes, log=log)
     report["precision"] = precision_report(rows, variants, write_sets, log)
+    report["fresh"] = fresh_report(rows, variants, log)
+    if os.path.exists(TABLE2):
+        report["robustness"] = robustness_report(rows, load_rows(TABLE2, {kernel_hash()}), variants, log)
     if write_sets:
         tuned.write_fixed_set()
     report["screen"] = {

@@ -40,7 +40,7 @@ KERNEL_SRC = os.path.join(PKG, "csrc", "sgemm_variant.hip")
 SPLIT_SRC = os.path.join(PKG, "csrc", "sgemm_split.hip")
 
 # Seed tags of the workloads (first element of every seed tuple).
-CFG_SQUARE, CFG_GRID, CFG_PRECISION = 2, 3, 5
+CFG_SQUARE, CFG_GRID, CFG_PRECISION, CFG_FRESH = 2, 3, 5, 6
 
 # Per-product truncation error of each 16-bit form, as a multiple of |a||b|,
 # and its number of term products.  Round-to-nearest bf16 keeps 8 bits
@@ -105,6 +105,10 @@ def workload(sets):
             jobs += [(CFG_SQUARE, M, N, K, beta, "uniform") for (M, N, K) in datagen.square_shapes()]
     if "precision" in sets:
         jobs += [(CFG_PRECISION, M, N, K, 0.0, "lognormal") for (M, N, K) in datagen.grid27()]
+    if "fresh" in sets:
+        # Shapes that chose nothing: timed after the sets and the dispatch
+        # rule are frozen, to measure how the sets generalise.
+        jobs += [(CFG_FRESH, M, N, K, 0.0, "uniform") for (M, N, K) in datagen.fresh_shapes()]
     # A shape shared by two sets is timed once (the first set's inputs).
     seen, out = set(), []
     for j in jobs:
@@ -152,6 +156,22 @@ def load_rows(path, khash=None, directory=VARIANT_DIR):
     return rows
 
 
+def gpu_clock_mhz():
+    """Current shader clock of the first GPU in MHz, from the driver's DPM
+    table in sysfs (the level marked '*'), or None where it is not readable."""
+    import glob
+    for path in sorted(glob.glob("/sys/class/drm/card*/device/pp_dpm_sclk")):
+        try:
+            with open(path) as f:
+                for line in f:
+                    if line.rstrip().endswith("*"):
+                        mhz = line.split(":", 1)[1].strip().rstrip("*").strip()
+                        return float(mhz.lower().replace("mhz", ""))
+        except (OSError, ValueError, IndexError):
+            continue
+    return None
+
+
 def _median(xs):
     s = sorted(xs)
     n = len(s)
@@ -189,6 +209,7 @@ def tune(out, sets=("grid", "extra", "square"), variants=None, target_ms=2.0, tr
         ref = torch.empty(M * N, dtype=torch.float64, device="cuda")
         tol = torch.empty(M * N, dtype=torch.float64, device="cuda")
         abi.screen_reference(M, N, K, 1.0, dA, K, dB, N, beta, dC0, N, ref, tol)
+        clk_start = gpu_clock_mhz()
         best = {}
         flops = 2.0 * M * N * K
         n_ok = 0
@@ -234,14 +255,16 @@ def tune(out, sets=("grid", "extra", "square"), variants=None, target_ms=2.0, tr
             n_ok += 1
             row.update(status="ok", ms=med, ms_mean=sum(ms_list) / len(ms_list),
                        ms_min=min(ms_list), ms_max=max(ms_list), reps=reps, trials=ntr,
-                       tflops=flops / med / 1e9)
+                       tflops=flops / med / 1e9, sclk_mhz=gpu_clock_mhz(), sclk_shape_start_mhz=clk_start)
             f.write(json.dumps(row) + "\n")
         f.flush()
         del dA, dB, dC0, dC, ref, tol
         torch.cuda.empty_cache()
         bests = " ".join(f"{abi.FORM_NAMES[p]} {flops / b / 1e9:.2f}" for p, b in sorted(best.items()))
+        clk_end = gpu_clock_mhz()
         log(f"[tune] {M}x{N}x{K} beta={beta} {data}: {n_ok}/{len(todo)} ok, best TFLOP/s {bests}, "
-            f"{time.time() - t0:.1f} s (total {time.time() - t_start:.0f} s)")
+            f"{time.time() - t0:.1f} s (total {time.time() - t_start:.0f} s), shader clock "
+            f"{clk_start} -> {clk_end} MHz")
         sys.stdout.flush()
     f.close()
 

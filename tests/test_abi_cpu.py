@@ -338,3 +338,34 @@ def test_evaluate_slowdown_histogram():
     winners = sorted({int(np.argmin(t[:, j])) for j in range(len(shapes))})
     ev_all = portability.evaluate(t, shapes, list(range(len(shapes))), tuple(winners))
     assert ev_all["so_max"] == pytest.approx(1.0) and ev_all["so_hist"]["counts"][0] == len(shapes)
+
+
+def test_fresh_shapes_recipe():
+    # The shapes that chose nothing: the 37 shapes of the paper's
+    # {256, 512, 1024, 4096}^3 grid off the tuning grid (each holds a 512),
+    # then 20 seeded log-uniform integer shapes in [128, 8192]; none is a
+    # training or held-out shape of the tuning grid.
+    f = datagen.fresh_shapes()
+    assert len(f) == 57 and len(set(f)) == 57
+    assert all(512 in s for s in f[:37])
+    assert not set(f) & set(datagen.grid27())
+    assert all(128 <= x <= 8192 for s in f[37:] for x in s)
+    assert f == datagen.fresh_shapes()
+
+
+def test_fresh_report_on_a_synthetic_table():
+    # portability.fresh_report with the committed sets on random times over
+    # the real family: fractions are at most 1, a perfect in-set pick is at
+    # least the dispatched pick, and the S/O histogram counts every shape.
+    from paper_2507_15277_amd import portability
+    variants = portability.read_variants()
+    rng = np.random.default_rng(78)
+    rows = [{"M": s[0], "N": s[1], "K": s[2], "beta": 0.0, "status": "ok", "variant": v,
+             "ms": float(np.exp(rng.normal(0, 0.5)))}
+            for s in datagen.fresh_shapes() for v in variants if variants[v].prec == 0]
+    rep = portability.fresh_report(rows, variants, log=lambda *_: None)
+    assert set(rep["sets"]) == {"fixed", "k1", "k2", "k4", "k8"}
+    for rec in rep["sets"].values():
+        assert 0 < rec["frac_realised"] <= rec["frac_inset"] <= 1.0
+        assert sum(rec["so_hist"]["counts"]) == 57
+        assert rec["so_max"] == pytest.approx(1.0 / min(r["frac"] for r in rec["per_shape"]))
