@@ -40,6 +40,17 @@ def batch_shapes(count=2000, seed=0, lo=16, hi=1024, step=16):
     return [tuple(int(v) for v in r) for r in x]
 
 
+def bucket_members(shapes, bucket_of, b):
+    """Problems of bucket b in the order their tiles enter the work list:
+    K descending (a tile's work is proportional to K), then M*N descending.
+    Work-group w takes tiles w, w + G, ... of the list, so the heavy tiles
+    are dealt out first and the light ones even out the end of the launch
+    (longest-processing-time-first), instead of a random order leaving
+    some work-groups with several heavy tiles at the end."""
+    idx = [i for i in range(len(shapes)) if bucket_of[i] == b]
+    return sorted(idx, key=lambda i: (-shapes[i][2], -shapes[i][0] * shapes[i][1], i))
+
+
 def buckets_of(shapes, nb):
     """Bucket index per problem: quantiles of log(M N K), nb buckets."""
     w = np.log(np.array([m * n * k for m, n, k in shapes], dtype=np.float64))
@@ -160,7 +171,7 @@ def tune_buckets(batch, bucket_of, nb, candidates, log=print):
     screen: {bucket: (vid, ms)}."""
     best = {}
     for b in range(nb):
-        idx = [i for i in range(len(batch.shapes)) if bucket_of[i] == b]
+        idx = bucket_members(batch.shapes, bucket_of, b)
         if not idx:
             continue
         refs = screen_refs(batch, idx)
@@ -205,7 +216,7 @@ def run(count=2000, nb=4, seed=0, log=print, bucket_variants=None):
             raise ValueError(f"need {nb} FP32 variant ids, one per bucket")
         best = {b: (v, float("nan")) for b, v in enumerate(bucket_variants) if np.any(bucket_of == b)}
     tune_s = time.perf_counter() - t0
-    plans = [GroupedPlan(batch, [i for i in range(count) if bucket_of[i] == b], best[b][0]) for b in sorted(best)]
+    plans = [GroupedPlan(batch, bucket_members(shapes, bucket_of, b), best[b][0]) for b in sorted(best)]
     stream = torch.cuda.current_stream()
 
     def grouped():
@@ -220,7 +231,7 @@ def run(count=2000, nb=4, seed=0, log=print, bucket_variants=None):
                               stream)
 
     # The grouped launches' results on the screened problems of every bucket.
-    refs = [r for b in sorted(best) for r in screen_refs(batch, [i for i in range(count) if bucket_of[i] == b])]
+    refs = [r for b in sorted(best) for r in screen_refs(batch, bucket_members(shapes, bucket_of, b))]
     batch.C.fill_(float("nan"))
     grouped()
     if not screen_ok(batch, refs):

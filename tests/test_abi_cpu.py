@@ -369,3 +369,17 @@ def test_fresh_report_on_a_synthetic_table():
         assert 0 < rec["frac_realised"] <= rec["frac_inset"] <= 1.0
         assert sum(rec["so_hist"]["counts"]) == 57
         assert rec["so_max"] == pytest.approx(1.0 / min(r["frac"] for r in rec["per_shape"]))
+
+
+def test_bucket_members_order():
+    # The grouped launch deals tiles out heaviest first: K descending, then
+    # M*N descending, ties by problem index; every problem of the bucket
+    # appears once.
+    from paper_2507_15277_amd import batched
+    shapes = batched.batch_shapes(300, 3)
+    bucket_of = batched.buckets_of(shapes, 4)
+    for b in range(4):
+        idx = batched.bucket_members(shapes, bucket_of, b)
+        assert sorted(idx) == [i for i in range(300) if bucket_of[i] == b]
+        keys = [(-shapes[i][2], -shapes[i][0] * shapes[i][1], i) for i in idx]
+        assert keys == sorted(keys)

@@ -157,7 +157,7 @@ def test_full_batch_2000_against_oracle(loaded):
            for i, (M, N, K) in enumerate(shapes)]
     batch = batched.Batch(shapes, host_ops=ops)
     bucket_of = batched.buckets_of(shapes, len(bucket_vids))
-    plans = [batched.GroupedPlan(batch, [i for i in range(count) if bucket_of[i] == b], vid)
+    plans = [batched.GroupedPlan(batch, batched.bucket_members(shapes, bucket_of, b), vid)
              for b, vid in enumerate(bucket_vids)]
     assert sum(p.count for p in plans) == count
     # The largest bucket's tiles outnumber its resident work-groups, so each
