@@ -91,13 +91,16 @@ extern "C" {
  * one workspace per device (allocated when such a variant is first loaded)
  * and a second kernel sums them.  Calls that use that workspace (or the
  * other per-device buffers of sgemm_form()) are ordered across streams by
- * the library: a call on another stream than the previous such call waits
- * for it (an event recorded behind each such call), so concurrent calls on
- * several streams give the same results as one stream.  A call made while
- * its stream is being captured into a HIP graph takes no part in that
- * ordering (the library cannot see when the graph is launched): replays of
- * such a graph are ordered with other calls on the device only by the
- * stream they are launched on.
+ * the library: a call on another stream than the previous such call first
+ * waits for everything enqueued so far on that previous stream (an event
+ * recorded there at that moment), so concurrent calls on several streams
+ * give the same results as one stream; calls on one stream pay nothing
+ * for it.  If the previous stream has been destroyed meanwhile, the call
+ * synchronises the device instead.  A call made while its stream is being
+ * captured into a HIP graph takes no part in that ordering (the library
+ * cannot see when the graph is launched): replays of such a graph are
+ * ordered with other calls on the device only by the stream they are
+ * launched on.
  *
  * Each variant is deterministic: the same inputs give bitwise the same C.
  * Different variants may round differently.  The result of every variant

@@ -98,10 +98,10 @@ struct Workspace {
     float* ws = nullptr;
     float* scale = nullptr;  // FP16 forms: block maxima of |A| and |B|, then the exponents {eA, eB}
     short* pieces = nullptr; // pre-split forms: 16-bit pieces of A and B
-    // Order of the calls that use these buffers, across streams: `last` is
-    // recorded on the stream of the latest such call (`last_stream`), and a
-    // call on another stream first waits for it.  `mu` keeps the wait, the
-    // launches and the record of one call together.
+    // Order of the calls that use these buffers, across streams: the stream
+    // of the latest such call (`last_stream`); a call on another stream
+    // records `last` on it and waits for that event first.  `mu` keeps the
+    // ordering and the launches of one call together.
     std::mutex mu;
     hipEvent_t last = nullptr;
     hipStream_t last_stream = nullptr;
@@ -616,11 +616,16 @@ bool stream_capturing(hipStream_t s)
 
 // Shared body of sgemm(), sgemm_form() and sgemm_variant(); `v` may be null
 // for the dispatch path, in which case the set picks it.  A call that uses
-// the device's shared buffers (K-split slices, FP16 exponents, pieces) is
-// ordered after the previous such call when that one ran on another stream:
-// it waits for the event recorded behind it, then records its own.  Calls
-// made while their stream is captured into a graph neither wait nor record
-// (an event recorded inside a capture cannot be waited on outside it).
+// the device's shared buffers (K-split slices, FP16 exponents, pieces) on
+// another stream than the previous such call is ordered after it: an event
+// is recorded on that previous stream at this moment (behind everything
+// enqueued there so far) and this call's stream waits for it.  Calls on the
+// stream of the previous user need no ordering and cost nothing extra.  If
+// the previous stream is no longer valid (destroyed by its owner), the call
+// waits for the whole device instead.  Calls made while their stream is
+// captured into a graph neither wait nor become the previous user (an event
+// recorded outside a capture cannot be waited on inside it, and the library
+// cannot see when the graph is launched).
 int gemm_common(const Variant* v, int form, int64_t M, int64_t N, int64_t K, float alpha, const float* A,
                 int64_t lda, const float* B, int64_t ldb, float beta, float* C, int64_t ldc, void* stream)
 {
@@ -638,14 +643,17 @@ int gemm_common(const Variant* v, int form, int64_t M, int64_t N, int64_t K, flo
     if (!shared) return launch_variant(*v, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, buf, s);
     std::lock_guard<std::mutex> lk(w.mu);
     const bool capturing = stream_capturing(s);
-    if (!capturing && w.last_valid && w.last_stream != s) {
-        e = hipStreamWaitEvent(s, w.last, 0);
-        if (e != hipSuccess) return hip_fail(e, "order the workspace after the previous call");
+    if (!capturing && w.last_valid && w.last_stream != s && w.last != nullptr) {
+        e = hipEventRecord(w.last, w.last_stream);
+        if (e == hipSuccess) e = hipStreamWaitEvent(s, w.last, 0);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            e = hipDeviceSynchronize();
+            if (e != hipSuccess) return hip_fail(e, "order the workspace after the previous call");
+        }
     }
     rc = launch_variant(*v, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, buf, s);
-    if (rc == FF_OK && !capturing && w.last != nullptr) {
-        e = hipEventRecord(w.last, s);
-        if (e != hipSuccess) return hip_fail(e, "record the workspace event");
+    if (rc == FF_OK && !capturing) {
         w.last_stream = s;
         w.last_valid = true;
     }
