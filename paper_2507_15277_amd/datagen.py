@@ -108,6 +108,13 @@ def square_shapes():
     return [(s, s, s) for s in SQUARE_SIZES]
 
 
+def ragged_grid():
+    """The 27 grid shapes moved off every multiple of 4: (M + 1, N + 3,
+    K + 5).  N and K odd rule out the vector-load kernels and every tile
+    edge is ragged: the unaligned counterpart of the tuning grid."""
+    return [(M + 1, N + 3, K + 5) for (M, N, K) in grid27()]
+
+
 # The paper's input grid (Sec. V-B): M, N, K each in {256, 512, 1024, 4096}.
 PAPER_LEVELS = (256, 512, 1024, 4096)
 

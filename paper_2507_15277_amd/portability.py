@@ -275,6 +275,50 @@ def fresh_report(rows, variants, log=print):
     return out
 
 
+def ragged_report(rows, variants, log=print):
+    """A selection that sees unaligned inputs.  The ragged grid (the 27 grid
+    shapes moved off every multiple of 4, so every variant runs its
+    scalar-load kernel) is timed like the grid; sets are chosen on the 14
+    aligned training shapes (as committed) and on those plus their 14 ragged
+    counterparts, and each is scored with a perfect in-set pick (Fig. 1's
+    evaluation) on the held-out aligned and ragged shapes and on the fresh
+    shapes: how much of the loss on ragged inputs is the selection's."""
+    grid, rag, fresh = datagen.grid27(), datagen.ragged_grid(), datagen.fresh_shapes()
+    shapes = grid + rag + fresh
+    nv = len(variants)
+    t = matrix(rows, shapes, 0.0, nv)
+    t[np.array([variants[v].prec != 0 for v in range(nv)]), :] = np.inf
+    if not np.isfinite(t).any(axis=0).all():
+        return None
+    best = t.min(axis=0)
+    train, _ = datagen.checkerboard_split(grid)
+    tr_g = [grid.index(s) for s in train]
+    tr_r = [len(grid) + j for j in tr_g]
+    ho_g = [j for j in range(len(grid)) if j not in tr_g]
+    ho_r = [len(grid) + j for j in ho_g]
+    n_paper = len(fresh) - 20
+    fr_p = list(range(2 * len(grid), 2 * len(grid) + n_paper))
+    fr_r = list(range(2 * len(grid) + n_paper, len(shapes)))
+
+    def inset(kap, idx):
+        return geomean(best[j] / min(t[v, j] for v in kap) for j in idx)
+
+    out = {"ragged_best_geomean_tflops": geomean(tflops(s, best[len(grid) + j]) for j, s in enumerate(rag)),
+           "aligned_best_geomean_tflops": geomean(tflops(s, best[j]) for j, s in enumerate(grid)), "sets": {}}
+    for k in KS:
+        rec = {}
+        for label, tr in (("aligned_training", tr_g), ("aligned_and_ragged_training", tr_g + tr_r)):
+            kap, _, _ = abi.ptune_select(t, k, shapes=tr, method=-1)
+            rec[label] = {"kappa": list(kap), "heldout_aligned": inset(kap, ho_g), "heldout_ragged": inset(kap, ho_r),
+                          "fresh_paper_grid": inset(kap, fr_p), "fresh_ragged": inset(kap, fr_r)}
+        out["sets"][str(k)] = rec
+        a, m = rec["aligned_training"], rec["aligned_and_ragged_training"]
+        log(f"[ragged] k={k}: aligned training: held-out aligned {a['heldout_aligned']:.3f} ragged "
+            f"{a['heldout_ragged']:.3f}, fresh ragged {a['fresh_ragged']:.3f}; with ragged training: "
+            f"{m['heldout_aligned']:.3f} / {m['heldout_ragged']:.3f} / {m['fresh_ragged']:.3f}")
+    return out
+
+
 def robustness_report(rows, rows2, variants, log=print):
     """How much the selection rests on one table build (Sec. V-C, V-E): a
     second FP32 table of the same grid, timed independently on another
@@ -493,6 +537,7 @@ def run(table=TABLE, write_sets=False, splits=5, log=print):
     report["fleet"] = fleet_comparison(t, shapes, log=log)
     report["precision"] = precision_report(rows, variants, write_sets, log)
     report["fresh"] = fresh_report(rows, variants, log)
+    report["ragged"] = ragged_report(rows, variants, log)
     if os.path.exists(TABLE2):
         report["robustness"] = robustness_report(rows, load_rows(TABLE2, {kernel_hash()}), variants, log)
     if write_sets:

@@ -40,7 +40,7 @@ KERNEL_SRC = os.path.join(PKG, "csrc", "sgemm_variant.hip")
 SPLIT_SRC = os.path.join(PKG, "csrc", "sgemm_split.hip")
 
 # Seed tags of the workloads (first element of every seed tuple).
-CFG_SQUARE, CFG_GRID, CFG_PRECISION, CFG_FRESH = 2, 3, 5, 6
+CFG_SQUARE, CFG_GRID, CFG_PRECISION, CFG_FRESH, CFG_RAGGED = 2, 3, 5, 6, 7
 
 # Per-product truncation error of each 16-bit form, as a multiple of |a||b|,
 # and its number of term products.  Round-to-nearest bf16 keeps 8 bits
@@ -105,6 +105,9 @@ def workload(sets):
             jobs += [(CFG_SQUARE, M, N, K, beta, "uniform") for (M, N, K) in datagen.square_shapes()]
     if "precision" in sets:
         jobs += [(CFG_PRECISION, M, N, K, 0.0, "lognormal") for (M, N, K) in datagen.grid27()]
+    if "ragged" in sets:
+        # The grid moved off every multiple of 4 (scalar-load kernels only).
+        jobs += [(CFG_RAGGED, M, N, K, 0.0, "uniform") for (M, N, K) in datagen.ragged_grid()]
     if "fresh" in sets:
         # Shapes that chose nothing: timed after the sets and the dispatch
         # rule are frozen, to measure how the sets generalise.

@@ -383,3 +383,28 @@ def test_bucket_members_order():
         assert sorted(idx) == [i for i in range(300) if bucket_of[i] == b]
         keys = [(-shapes[i][2], -shapes[i][0] * shapes[i][1], i) for i in idx]
         assert keys == sorted(keys)
+
+
+def test_ragged_grid_recipe():
+    # The unaligned counterpart of the tuning grid: every shape is a grid
+    # shape moved by (1, 3, 5), so N and K are odd and no vector-load kernel
+    # can run.
+    r = datagen.ragged_grid()
+    assert len(r) == 27 and [(m - 1, n - 3, k - 5) for m, n, k in r] == datagen.grid27()
+    assert all(n % 4 and k % 4 for _, n, k in r)
+
+
+def test_ragged_report_on_a_synthetic_table():
+    from paper_2507_15277_amd import portability
+    variants = portability.read_variants()
+    rng = np.random.default_rng(79)
+    shapes = datagen.grid27() + datagen.ragged_grid() + datagen.fresh_shapes()
+    rows = [{"M": s[0], "N": s[1], "K": s[2], "beta": 0.0, "status": "ok", "variant": v,
+             "ms": float(np.exp(rng.normal(0, 0.5)))}
+            for s in shapes for v in variants if variants[v].prec == 0]
+    rep = portability.ragged_report(rows, variants, log=lambda *_: None)
+    for k, rec in rep["sets"].items():
+        for sel in rec.values():
+            assert len(sel["kappa"]) == int(k)
+            assert all(0 < sel[x] <= 1.0 for x in ("heldout_aligned", "heldout_ragged", "fresh_paper_grid",
+                                                 "fresh_ragged"))
