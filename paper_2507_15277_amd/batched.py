@@ -7,7 +7,10 @@ into size buckets by quantiles of log(M N K); for each bucket the autotuner
 times the grouped launch of every FP32 variant and keeps the fastest (the
 per-bucket variant).  One batch then costs one grouped launch per bucket,
 and the launches are captured once in a HIP graph and replayed.  The
-baseline issues one launch per problem with its bucket's variant.
+buckets' problems are disjoint, so their launches may also run
+concurrently: each on its own stream, forked from and joined back into the
+caller's stream (the largest bucket first), eagerly or captured the same
+way.  The baseline issues one launch per problem with its bucket's variant.
 
 This is the batched use of the selection machinery: the buckets play the
 role of the paper's environments and the total time of the batch is the
@@ -116,6 +119,23 @@ class GroupedPlan:
     def launch(self, alpha=1.0, beta=0.0, stream=None):
         abi.sgemm_grouped(self.vid, self.count, self.d_descs, self.d_prefix, self.total, alpha, beta,
                           self.vec, stream)
+
+
+def launch_concurrent(plans, main, sides):
+    """Launch every plan on its own stream: the first on `main`, the others
+    on the streams `sides` (default priority), which first wait for the work
+    already on `main`; `main` then waits for all of them.  The plans write
+    disjoint outputs.  Captured under a graph, the fork and join become the
+    graph's dependencies."""
+    if len(sides) < len(plans) - 1:
+        raise ValueError("one side stream per plan after the first")
+    for s in sides[:len(plans) - 1]:
+        s.wait_stream(main)
+    plans[0].launch(stream=main)
+    for p, s in zip(plans[1:], sides):
+        p.launch(stream=s)
+    for s in sides[:len(plans) - 1]:
+        main.wait_stream(s)
 
 
 def time_it(fn, reps=5, warmup=2):
@@ -249,6 +269,31 @@ def run(count=2000, nb=4, seed=0, log=print, bucket_variants=None):
         for p in plans:
             p.launch(stream=torch.cuda.current_stream())
     ms_graph = time_it(graph.replay, reps=20, warmup=2)
+
+    # The same launches on concurrent streams, the largest bucket first.
+    largest_first = plans[::-1]
+    sides = [torch.cuda.Stream() for _ in largest_first[1:]]
+
+    def concurrent():
+        launch_concurrent(largest_first, torch.cuda.current_stream(), sides)
+
+    batch.C.fill_(float("nan"))
+    concurrent()
+    if not screen_ok(batch, refs):
+        raise RuntimeError("concurrent grouped launches fail the screen")
+    ms_concurrent = time_it(concurrent, reps=10, warmup=2)
+    graph_c = torch.cuda.CUDAGraph()
+    with torch.cuda.stream(side):
+        launch_concurrent(largest_first, side, sides)    # warm the streams before capture
+    stream.wait_stream(side)
+    torch.cuda.synchronize()
+    with torch.cuda.graph(graph_c):
+        launch_concurrent(largest_first, torch.cuda.current_stream(), sides)
+    batch.C.fill_(float("nan"))
+    graph_c.replay()
+    if not screen_ok(batch, refs):
+        raise RuntimeError("the concurrent graph fails the screen")
+    ms_graph_c = time_it(graph_c.replay, reps=20, warmup=2)
     tf = lambda ms: batch.flops / ms / 1e9  # noqa: E731
     rep = {"count": count, "buckets": nb, "seed": seed, "gflop": batch.flops / 1e9,
            "algorithmic_gbytes": sum(4.0 * (M * K + K * N + M * N) for M, N, K in shapes) / 1e9,
@@ -257,11 +302,14 @@ def run(count=2000, nb=4, seed=0, log=print, bucket_variants=None):
                                for b, (v, ms) in best.items()},
            "ms_per_problem_launches": ms_single, "ms_grouped": ms_grouped, "ms_grouped_graph": ms_graph,
            "tflops_per_problem_launches": tf(ms_single), "tflops_grouped": tf(ms_grouped),
-           "tflops_grouped_graph": tf(ms_graph), "bucket_tuning_seconds": tune_s,
+           "tflops_grouped_graph": tf(ms_graph), "ms_concurrent": ms_concurrent,
+           "ms_concurrent_graph": ms_graph_c, "tflops_concurrent": tf(ms_concurrent),
+           "tflops_concurrent_graph": tf(ms_graph_c), "bucket_tuning_seconds": tune_s,
            "screened_problems": len(refs)}
     log(f"[batched] {count} GEMMs, {rep['gflop']:.1f} GFLOP: per-problem launches {ms_single:.3f} ms "
         f"({tf(ms_single):.1f} TFLOP/s), grouped {ms_grouped:.3f} ms ({tf(ms_grouped):.1f}), "
-        f"grouped in a graph {ms_graph:.3f} ms ({tf(ms_graph):.1f})")
+        f"grouped in a graph {ms_graph:.3f} ms ({tf(ms_graph):.1f}), concurrent streams {ms_concurrent:.3f} ms "
+        f"({tf(ms_concurrent):.1f}), concurrent in a graph {ms_graph_c:.3f} ms ({tf(ms_graph_c):.1f})")
     return rep
 
 

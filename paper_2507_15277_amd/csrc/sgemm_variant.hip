@@ -337,23 +337,23 @@ __device__ __forceinline__ void dma_slabs(int M, int N, int K, const float* __re
     __syncthreads();                                     // LDS reused by the caller
 }
 
-// One work-group computes tile (tm, tn) of C over slabs [kt0, kt1) of K
-// (split `part` of `splits` when the K range is split over work-groups).
-// Every wave reaches every barrier and no wave returns early, so the
-// grouped kernel can call this once per tile in a loop.  EDGE false: the
-// tile and its slabs lie inside the matrices, so no load needs a per-element
-// bounds test or select.  Only the prefetch of a slab past the last one
-// (issued unconditionally by the two-deep loop and never staged) is sent to
-// the safe address, by one uniform test of the slab index.
-// Variants with an unmasked copy of the tile loop for interior tiles.
+// Variants with an unmasked copy of the slab loop for interior tiles.
 template <int V> constexpr bool kUnmasked = USE_LDS && !(DMA && V == 4);
 
-template <int V, bool EDGE = true>
-__device__ __forceinline__ void tile_gemm(int M, int N, int K, float alpha,
+// One work-group adds the products of slabs [kt0, kt1) of K for tile
+// (tm, tn) of C to its accumulators.  Every wave reaches every barrier, the
+// loop ends with one (its LDS is free again afterwards), and no wave returns
+// early.  EDGE false: slabs [kt0, kt1) lie inside K, so no load needs a
+// per-element bounds test or select.  Rows of the tile past M read row M - 1
+// instead, and load vectors past N (N a multiple of V) the last vector of
+// their row: both only feed outputs past M or N, which are never stored.
+// Only the prefetch of a slab past kt1 (issued unconditionally by the
+// two-deep loop and never staged) is sent to the safe address, by one
+// uniform test of the slab index.
+template <int V, bool EDGE>
+__device__ __forceinline__ void tile_loop(acc_t (&acc)[RM][RN], int M, int N, int K,
                                           const float* __restrict__ A, long lda,
                                           const float* __restrict__ B, long ldb,
-                                          float beta, float* __restrict__ C, long ldc,
-                                          float* __restrict__ ws, int splits, int part,
                                           int kt0, int kt1, int tm, int tn, float* smem)
 {
     const int m0 = tm * MWG, n0 = tn * NWG;
@@ -367,14 +367,6 @@ __device__ __forceinline__ void tile_gemm(int M, int N, int K, float alpha,
     const int lr = lane % MI;             // lane's row within an MFMA block
     const int lh = lane / MI;             // lane's k group
     const int kg0 = grp * KG + lh * S;    // first k of this lane within a slab
-
-    acc_t acc[RM][RN];
-#pragma unroll
-    for (int i = 0; i < RM; ++i)
-#pragma unroll
-        for (int j = 0; j < RN; ++j)
-            acc[i][j] = acc_t{};
-
 
     if constexpr (USE_LDS) {
         // ---- cooperative slab loads: global -> registers -> LDS ----------
@@ -399,8 +391,9 @@ __device__ __forceinline__ void tile_gemm(int M, int N, int K, float alpha,
                 if (NVA % NT == 0 || v < NVA) {
                     const int row = v / AVEC_ROW, kk = (v % AVEC_ROW) * V;
                     const int m = m0 + row, k = kb + kk;
+                    const int mr = EDGE ? m : min(m, M - 1);
                     oka[rbuf][i] = EDGE ? ((m < M) && (k < K)) : (kt < kt1);
-                    ra[rbuf][i] = load_raw<V>(A + (long)m * lda + k, oka[rbuf][i], A);
+                    ra[rbuf][i] = load_raw<V>(A + (long)mr * lda + k, oka[rbuf][i], A);
                 }
             }
 #pragma unroll
@@ -409,8 +402,9 @@ __device__ __forceinline__ void tile_gemm(int M, int N, int K, float alpha,
                 if (NVB % NT == 0 || v < NVB) {
                     const int row = v / BVEC_ROW, nn = (v % BVEC_ROW) * V;
                     const int k = kb + row, n = n0 + nn;
+                    const int nr = (EDGE || n < N) ? n : N - V;
                     okb[rbuf][i] = EDGE ? ((k < K) && (n < N)) : (kt < kt1);
-                    rb[rbuf][i] = load_raw<V>(B + (long)k * ldb + n, okb[rbuf][i], B);
+                    rb[rbuf][i] = load_raw<V>(B + (long)k * ldb + nr, okb[rbuf][i], B);
                 }
             }
         };
@@ -585,6 +579,49 @@ __device__ __forceinline__ void tile_gemm(int M, int N, int K, float alpha,
         }
     }
 
+}
+
+// One work-group computes tile (tm, tn) of C over slabs [kt0, kt1) of K
+// (split `part` of `splits` when the K range is split over work-groups).
+// Every wave reaches every barrier and no wave returns before the epilogue,
+// so the grouped kernel can call this once per tile in a loop.  EDGE false:
+// all the tile's slabs lie inside K and, if the tile runs past N, N is a
+// multiple of V (the loads of the loop without masks above).  TAIL (with
+// EDGE false): the same, except that the last slab runs past K; the full
+// slabs run the loop without masks and only the last one the masked loop.
+// The epilogue tests every row and column in all three cases.
+template <int V, bool EDGE = true, bool TAIL = false>
+__device__ __forceinline__ void tile_gemm(int M, int N, int K, float alpha,
+                                          const float* __restrict__ A, long lda,
+                                          const float* __restrict__ B, long ldb,
+                                          float beta, float* __restrict__ C, long ldc,
+                                          float* __restrict__ ws, int splits, int part,
+                                          int kt0, int kt1, int tm, int tn, float* smem)
+{
+    const int m0 = tm * MWG, n0 = tn * NWG;
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wid = tid >> 6;
+    const int grp = wid / (WM * WN);      // split-K group
+    const int wq = wid % (WM * WN);
+    const int wm = wq / WN, wn = wq % WN;
+    const int lr = lane % MI;             // lane's row within an MFMA block
+    const int lh = lane / MI;             // lane's k group
+
+    acc_t acc[RM][RN];
+#pragma unroll
+    for (int i = 0; i < RM; ++i)
+#pragma unroll
+        for (int j = 0; j < RN; ++j)
+            acc[i][j] = acc_t{};
+
+    if constexpr (TAIL) {
+        tile_loop<V, false>(acc, M, N, K, A, lda, B, ldb, kt0, kt1 - 1, tm, tn, smem);
+        tile_loop<V, true>(acc, M, N, K, A, lda, B, ldb, kt1 - 1, kt1, tm, tn, smem);
+    } else {
+        tile_loop<V, EDGE>(acc, M, N, K, A, lda, B, ldb, kt0, kt1, tm, tn, smem);
+    }
+
     // ---- reduce split-K groups through LDS ---------------------------------
     if constexpr (SK > 1) {
         if constexpr (USE_LDS) __syncthreads();
@@ -680,14 +717,24 @@ __device__ __forceinline__ void gemm_body(int M, int N, int K, float alpha,
     // This work-group's slabs [kt0, kt1): all of K unless the tile is split.
     const int kt0 = (SG > 1) ? part * kper : 0;
     const int kt1 = (SG > 1) ? min(nkt, kt0 + kper) : nkt;
-    // Interior tiles (the usual case) of the register-staged variants run
-    // without per-element masking.  The load-to-LDS path clamps addresses
-    // instead; the direct-load path measured slower without its selects.
+    // The register-staged variants run the loop without per-element masks
+    // (rows past M and load vectors past N read clamped addresses) unless
+    // the tile runs past N with N not a multiple of the load width; a tile
+    // whose last slab runs past K runs its full slabs so and masks only the
+    // last one.  The load-to-LDS path clamps addresses instead; the
+    // direct-load path measured slower without its selects.
     if constexpr (kUnmasked<V>) {
-        if ((tm + 1) * MWG <= M && (tn + 1) * NWG <= N && kt1 * KWG <= K) {
-            tile_gemm<V, false>(M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, ws, splits, part, kt0, kt1, tm, tn,
-                                smem);
-            return;
+        if ((tn + 1) * NWG <= N || N % V == 0) {
+            if (kt1 * KWG <= K) {
+                tile_gemm<V, false>(M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, ws, splits, part, kt0, kt1, tm,
+                                    tn, smem);
+                return;
+            }
+            if (kt1 - 1 > kt0) {
+                tile_gemm<V, false, true>(M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, ws, splits, part, kt0, kt1,
+                                          tm, tn, smem);
+                return;
+            }
         }
     }
     tile_gemm<V, true>(M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, ws, splits, part, kt0, kt1, tm, tn, smem);
@@ -703,14 +750,22 @@ struct GemmDesc {
 };
 
 // Grouped persistent launch: the tiles of `count` independent problems form
-// one work list (prefix[g] = tiles before problem g, total = all tiles);
-// work-group w takes tiles w, w + gridDim.x, ...  Each problem's tiles are
-// walked row by row.  K is never split here.
+// one work list (prefix[g] = tiles before problem g, total = all tiles),
+// walked in rounds of G = gridDim.x tiles: in round r work-group w takes
+// tile r G + w when r is even and r G + (G - 1 - w) when r is odd, so with
+// the list ordered heaviest first (as the runtime's caller orders it) the
+// work-groups that took the heavier tiles of one round take the lighter
+// ones of the next.  A work-group stops at its first tile past the list
+// (later rounds only hold later tiles).  Each problem's tiles are walked
+// row by row.  K is never split here.
 template <int V>
 __device__ __forceinline__ void grouped_body(const GemmDesc* __restrict__ d, const int* __restrict__ prefix,
                                              int count, int total, float alpha, float beta, float* smem)
 {
-    for (int t = blockIdx.x; t < total; t += gridDim.x) {
+    const int G = gridDim.x;
+    for (int r = 0;; ++r) {
+        const int t = r * G + ((r & 1) ? G - 1 - (int)blockIdx.x : (int)blockIdx.x);
+        if (t >= total) break;
         int lo = 0, hi = count - 1;   // last problem whose first tile is <= t
         while (lo < hi) {
             const int mid = (lo + hi + 1) >> 1;
@@ -724,10 +779,17 @@ __device__ __forceinline__ void grouped_body(const GemmDesc* __restrict__ d, con
         __syncthreads();   // the previous tile is done with LDS
         const int nkt = (p.K + KWG - 1) / KWG;
         if constexpr (kUnmasked<V>) {
-            if ((tm + 1) * MWG <= p.M && (tn + 1) * NWG <= p.N && nkt * KWG <= p.K) {
-                tile_gemm<V, false>(p.M, p.N, p.K, alpha, p.A, p.lda, p.B, p.ldb, beta, p.C, p.ldc, nullptr, 1, 0, 0,
-                                    nkt, tm, tn, smem);
-                continue;
+            if ((tn + 1) * NWG <= p.N || p.N % V == 0) {
+                if (nkt * KWG <= p.K) {
+                    tile_gemm<V, false>(p.M, p.N, p.K, alpha, p.A, p.lda, p.B, p.ldb, beta, p.C, p.ldc, nullptr, 1,
+                                        0, 0, nkt, tm, tn, smem);
+                    continue;
+                }
+                if (nkt > 1) {
+                    tile_gemm<V, false, true>(p.M, p.N, p.K, alpha, p.A, p.lda, p.B, p.ldb, beta, p.C, p.ldc,
+                                              nullptr, 1, 0, 0, nkt, tm, tn, smem);
+                    continue;
+                }
             }
         }
         tile_gemm<V, true>(p.M, p.N, p.K, alpha, p.A, p.lda, p.B, p.ldb, beta, p.C, p.ldc, nullptr, 1, 0, 0,

@@ -125,6 +125,40 @@ def test_grouped_graph_replays(loaded):
         assert torch.equal(batch.C, eager), f"replay {r} differs from the eager result"
 
 
+def test_concurrent_launches_and_graph_replays(loaded):
+    # Three plans of disjoint problems on three streams (forked from and
+    # joined back into the current stream), eagerly and captured in a graph
+    # replayed three times with eager work between: each result against the
+    # oracle and every replay against the eager result.
+    shapes, ops = _small_batch(3, count=36)
+    batch = batched.Batch(shapes, host_ops=ops)
+    idx = list(range(len(shapes)))
+    thirds = [idx[0::3], idx[1::3], idx[2::3]]
+    plans = [batched.GroupedPlan(batch, t, loaded[(11 * j + 3) % len(loaded)]) for j, t in enumerate(thirds)]
+    sides = [torch.cuda.Stream() for _ in plans[1:]]
+    main = torch.cuda.current_stream()
+    batch.C.zero_()
+    batched.launch_concurrent(plans, main, sides)
+    torch.cuda.synchronize()
+    assert not _check_batch(batch, ops, "concurrent")
+    eager = batch.C.clone()
+    warm = torch.cuda.Stream()
+    warm.wait_stream(main)
+    with torch.cuda.stream(warm):
+        batched.launch_concurrent(plans, warm, sides)
+    main.wait_stream(warm)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        batched.launch_concurrent(plans, torch.cuda.current_stream(), sides)
+    for r in range(3):
+        batch.C.zero_()                  # eager work between replays
+        torch.cuda.synchronize()
+        graph.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(batch.C, eager), f"replay {r} differs from the eager result"
+
+
 def test_plan_rejects_bad_problems(loaded):
     d = np.zeros(2, dtype=abi.gemm_desc_dtype())
     d[0] = (16, 16, 16, 4, 4, 4, 4, 4, 4, 0)

@@ -15,7 +15,7 @@ torch = pytest.importorskip("torch")
 
 import oracle
 from paper_2507_15277_amd import abi, datagen, space
-from tests.gpu_util import run_gemm
+from tests.gpu_util import GuardedC, run_gemm
 
 pytestmark = pytest.mark.gpu
 
@@ -120,6 +120,43 @@ def test_every_variant_vector_path_padded(loaded):
         try:
             _check(C, A, B, C0, 1.5, -0.5, name)
             assert guard, f"{name}: wrote outside C"
+        except AssertionError as e:
+            fails.append(str(e))
+    assert not fails, "\n".join(fails[:10])
+
+
+def _offset_matrix(a, ld):
+    """(rows x ld) matrix holding `a`, NaN in the padding, starting one float
+    into its buffer (4-byte but not 16-byte aligned): (tensor, address)."""
+    rows, cols = a.shape
+    flat = np.full(1 + rows * ld + 1, np.nan, np.float32)
+    flat[1:1 + rows * ld].reshape(rows, ld)[:, :cols] = a
+    t = torch.from_numpy(flat).cuda()
+    return t, t.data_ptr() + 4
+
+
+def test_every_variant_unaligned_rows_and_k_tail(loaded):
+    # N a multiple of 4 but K not, odd leading dimensions and base addresses
+    # one float past 16-byte alignment: the register-staged vector kernels
+    # load whole rows in (4-byte aligned) vectors here, and the last slab,
+    # which ends inside a load vector, element by element.  NaN in every
+    # operand's padding and one float past its end must not reach C.
+    M, N, K = 200, 328, 133
+    lda, ldb, ldc = K + 2, N + 1, N + 4
+    A = datagen.uniform((29, M, N, K, 0), M, K)
+    B = datagen.uniform((29, M, N, K, 1), K, N)
+    C0 = datagen.uniform((29, M, N, K, 2), M, N)
+    tA, pA = _offset_matrix(A, lda)
+    tB, pB = _offset_matrix(B, ldb)
+    fails = []
+    for vid, name in loaded:
+        gc = GuardedC(C0, M, N, ldc)
+        abi.sgemm_variant(vid, M, N, K, 1.5, pA, lda, pB, ldb, -0.5, gc.ptr, ldc)
+        torch.cuda.synchronize()
+        C, flat = gc.result()
+        try:
+            _check(C, A, B, C0, 1.5, -0.5, name)
+            assert gc.untouched_outside(flat), f"{name}: wrote outside C"
         except AssertionError as e:
             fails.append(str(e))
     assert not fails, "\n".join(fails[:10])

@@ -1,7 +1,8 @@
-"""CPU model of the register-staged kernels' global loads on interior tiles.
+"""CPU model of the register-staged kernels' global loads without masks.
 
-Interior tiles (the tile and its slabs inside the matrices) run the
-register-staged loop without per-element masks.  The two-deep prefetch loop
+Tiles whose slabs lie inside K run the register-staged loop without
+per-element masks; rows past M read row M - 1 and load vectors past N (N a
+multiple of the load width) the last vector of their row.  The two-deep prefetch loop
 still issues the loads of one slab past the tile's last (they are never
 staged), so those must go to the safe base address.  This test restates the
 loads' index arithmetic and the PD = 1 / PD = 2 call sequences of
@@ -9,6 +10,11 @@ csrc/sgemm_variant.hip and checks that every dereferenced element lies inside
 A (M x lda) and B (K x ldb) for every register-staged kernel of the family
 (both load widths of LDS mode 1 and the scalar-load kernel of load-to-LDS
 variants), on the last interior tile and on the first and last K split.
+
+Tiles whose last slab runs past K (K not a multiple of the slab depth) run
+the unmasked loop over their full slabs only and the masked loop over the
+last one; the second test checks the unmasked phase of those tiles the same
+way, and the third the tiles at the M and N edges of ragged shapes.
 """
 import numpy as np
 import pytest
@@ -31,6 +37,11 @@ def _loads(v, M, N, K, lda, ldb, tm, tn, kt0, kt1, V=None):
             items = items[items < n_items]
             r = base_r + items // vec_row
             c = base_c + (items % vec_row) * V
+            if name == "A":
+                r = np.minimum(r, M - 1)            # rows past M read row M - 1
+            else:
+                c = np.where(c < N, c, N - V)       # vectors past N: the row's last
+            assert np.all(r >= 0) and np.all(c >= 0)
             out[name] = max(out[name], int(np.max(r * ld + c + V - 1)))
 
     out = {"A": -1, "B": -1}
@@ -62,6 +73,17 @@ def _staged_kernels():
     return out
 
 
+def _split_ranges(v, M, N, nkt):
+    """[kt0, kt1) of the first and last K split (the runtime's split count)."""
+    splits = 1
+    if v.sg > 1:
+        sp = min(v.sg, nkt, space.WORKSPACE_BYTES // (M * N * 4))
+        if sp >= 2:
+            splits = -(-nkt // -(-nkt // sp))
+    per = -(-nkt // splits)
+    return {(part * per, min(nkt, part * per + per)) for part in {0, splits - 1}}
+
+
 @pytest.mark.parametrize("shape", [(256, 256, 256), (512, 1024, 768)])
 def test_interior_loads_stay_inside(shape):
     M, N, K = shape
@@ -72,17 +94,51 @@ def test_interior_loads_stay_inside(shape):
         nbm, nbn = M // v.mwg, N // v.nwg
         if K % v.kwg or nbm == 0 or nbn == 0:
             continue
-        nkt = K // v.kwg
-        splits = 1
-        if v.sg > 1:
-            sp = min(v.sg, nkt, space.WORKSPACE_BYTES // (M * N * 4))
-            if sp >= 2:
-                splits = -(-nkt // -(-nkt // sp))
-        per = -(-nkt // splits)
-        for part in {0, splits - 1}:
-            kt0, kt1 = part * per, min(nkt, part * per + per)
+        for kt0, kt1 in _split_ranges(v, M, N, K // v.kwg):
             out = _loads(v, M, N, K, K, N, nbm - 1, nbn - 1, kt0, kt1, vw)
-            assert out["A"] <= (M - 1) * K + K - 1, (v.name, vw, shape, part)
-            assert out["B"] <= (K - 1) * N + N - 1, (v.name, vw, shape, part)
+            assert out["A"] <= (M - 1) * K + K - 1, (v.name, vw, shape, kt0)
+            assert out["B"] <= (K - 1) * N + N - 1, (v.name, vw, shape, kt0)
             checked += 1
+    assert checked > 100
+
+
+@pytest.mark.parametrize("shape", [(256, 256, 261), (512, 1024, 771), (257, 131, 1029)])
+def test_k_tail_unmasked_phase_stays_inside(shape):
+    M, N, K = shape
+    checked = 0
+    for v, vw in _staged_kernels():
+        nbm, nbn = M // v.mwg, N // v.nwg
+        nkt = -(-K // v.kwg)
+        if K % v.kwg == 0 or nbm == 0 or nbn == 0:
+            continue
+        for kt0, kt1 in _split_ranges(v, M, N, nkt):
+            if kt1 * v.kwg <= K or kt1 - 1 <= kt0:
+                continue            # no tail slab, or the masked loop alone
+            assert (kt1 - 1) * v.kwg <= K
+            out = _loads(v, M, N, K, K, N, nbm - 1, nbn - 1, kt0, kt1 - 1, vw)
+            assert out["A"] <= (M - 1) * K + K - 1, (v.name, vw, shape, kt0)
+            assert out["B"] <= (K - 1) * N + N - 1, (v.name, vw, shape, kt0)
+            checked += 1
+    assert checked > 100
+
+
+@pytest.mark.parametrize("shape", [(257, 131, 1029), (100, 1000, 300), (1000, 36, 64), (33, 4097, 515)])
+def test_edge_tiles_stay_inside(shape):
+    M, N, K = shape
+    checked = 0
+    for v, vw in _staged_kernels():
+        nbm, nbn = -(-M // v.mwg), -(-N // v.nwg)
+        nkt = -(-K // v.kwg)
+        for tm, tn in {(nbm - 1, nbn - 1), (nbm - 1, 0), (0, nbn - 1)}:
+            if not ((tn + 1) * v.nwg <= N or N % vw == 0):
+                continue            # the masked loop
+            for kt0, kt1 in _split_ranges(v, M, N, nkt):
+                if kt1 * v.kwg > K:
+                    kt1 -= 1        # the tail slab runs the masked loop
+                if kt1 <= kt0:
+                    continue
+                out = _loads(v, M, N, K, K, N, tm, tn, kt0, kt1, vw)
+                assert out["A"] <= (M - 1) * K + K - 1, (v.name, vw, shape, tm, tn, kt0)
+                assert out["B"] <= (K - 1) * N + N - 1, (v.name, vw, shape, tm, tn, kt0)
+                checked += 1
     assert checked > 100
