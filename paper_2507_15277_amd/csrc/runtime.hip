@@ -293,6 +293,23 @@ int launch_scale(int64_t M, int64_t N, float beta, float* C, int64_t ldc, hipStr
 
 bool aligned_for(const void* p, int vw) { return (reinterpret_cast<uintptr_t>(p) % (4u * vw)) == 0; }
 
+// Whether the vector-load kernel of FP32 variant v can run a problem.  The
+// variants that stage through registers load A along K and B along N in
+// VW-wide vectors that need only 4-byte alignment (the hardware takes
+// multi-dword accesses at any dword address); a load vector that would run
+// past N reads the row's last VW columns instead (N >= VW), and a last slab
+// that ends inside a vector goes element by element.  The load-to-LDS and
+// direct-load variants need K, N, lda and ldb multiples of VW and 16-byte
+// aligned A and B.
+bool fp32_vector_ok(const FfDesc& v, int64_t N, int64_t K, int64_t lda, int64_t ldb, const void* A,
+                    const void* B)
+{
+    const int w = v.vw;
+    if (w <= 1) return false;
+    if (v.lds == 1) return N >= w && aligned_for(A, 1) && aligned_for(B, 1);
+    return K % w == 0 && N % w == 0 && lda % w == 0 && ldb % w == 0 && aligned_for(A, w) && aligned_for(B, w);
+}
+
 // C = alpha * sum_{q < splits} P[q] + beta * C, P[q] the q-th M x N slice of
 // partial products; the splits are added in index order (deterministic).
 // Each thread handles four consecutive columns of one row, with 16-byte
@@ -489,15 +506,11 @@ int launch_variant(const Variant& v, int64_t M, int64_t N, int64_t K, float alph
     const int64_t nbm = (M + v.mwg - 1) / v.mwg, nbn = (N + v.nwg - 1) / v.nwg;
     const int64_t nb = nbm * nbn;
     if (nb > INT32_MAX) return fail(FF_ERR_TOO_LARGE, "sgemm: %lld tiles exceed the grid limit", (long long)nb);
-    // The vector-load kernel needs whole, aligned vectors along K (A rows)
-    // and N (B rows); otherwise the scalar-load kernel of the same variant.
-    const int w = v.vw;
-    // Split-precision variants load B by columns (scalar) and A in 16-byte
-    // vectors; FP32 variants load both in VW-wide vectors.
-    const bool vec = v.prec > 0
-                         ? (K % 4 == 0 && lda % 4 == 0 && aligned_for(A, 4))
-                         : (w > 1 && K % w == 0 && N % w == 0 && lda % w == 0 && ldb % w == 0 &&
-                            aligned_for(A, w) && aligned_for(B, w));
+    // The vector-load kernel where its loads allow (fp32_vector_ok);
+    // otherwise the scalar-load kernel of the same variant.  Split-precision
+    // variants load B by columns (scalar) and A in 16-byte vectors.
+    const bool vec = v.prec > 0 ? (K % 4 == 0 && lda % 4 == 0 && aligned_for(A, 4))
+                                : fp32_vector_ok(v, N, K, lda, ldb, A, B);
     hipFunction_t f = vec ? v.fvec : v.fsca;
     const float* prescale = nullptr;
     // Every check that can fail comes before the first launch.
@@ -1104,8 +1117,7 @@ FF_EXPORT int sgemm_grouped_plan(int id, int count, ff_gemm_desc* descs, int32_t
     auto v = find_variant(id);
     if (!v) return fail(FF_ERR_VARIANT, "variant %d not registered", id);
     if (v->prec != 0) return fail(FF_ERR_ARG, "variant %d has no grouped form", id);
-    const int w = v->vw;
-    bool vec = w > 1;
+    bool vec = v->vw > 1;
     int64_t total = 0;
     for (int g = 0; g < count; ++g) {
         ff_gemm_desc& d = descs[g];
@@ -1118,8 +1130,7 @@ FF_EXPORT int sgemm_grouped_plan(int id, int count, ff_gemm_desc* descs, int32_t
         d.tiles = (int32_t)tiles;
         prefix[g] = (int32_t)total;
         total += tiles;
-        vec = vec && d.K % w == 0 && d.N % w == 0 && d.lda % w == 0 && d.ldb % w == 0 && aligned_for(d.A, w) &&
-              aligned_for(d.B, w);
+        vec = vec && fp32_vector_ok(*v, d.N, d.K, d.lda, d.ldb, d.A, d.B);
     }
     if (vec_ok) *vec_ok = vec ? 1 : 0;
     return (int)total;

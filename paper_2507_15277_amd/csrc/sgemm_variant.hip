@@ -184,6 +184,23 @@ __device__ __forceinline__ void vset(typename VecT<V>::T& v, int e, float x)
 {
     if constexpr (V == 1) { (void)e; v = x; } else { v[e] = x; }
 }
+// Element j of the result is element j + s of v (0 <= s < V); the last s
+// elements keep v's last one.
+template <int V>
+__device__ __forceinline__ typename VecT<V>::T vshift(const typename VecT<V>::T& v, int s)
+{
+    typename VecT<V>::T w = v;
+    if constexpr (V > 1) {
+#pragma unroll
+        for (int j = 0; j < V - 1; ++j) {
+            float x = v[V - 1];
+#pragma unroll
+            for (int t = V - 2; t >= j; --t) x = (j + s == t) ? v[t] : x;
+            w[j] = x;
+        }
+    }
+    return w;
+}
 
 // Edge handling is branch-free: an invalid lane loads V floats from `safe`
 // (any readable address aligned for V) instead of p, and the value is
@@ -340,17 +357,48 @@ __device__ __forceinline__ void dma_slabs(int M, int N, int K, const float* __re
 // Variants with an unmasked copy of the slab loop for interior tiles.
 template <int V> constexpr bool kUnmasked = USE_LDS && !(DMA && V == 4);
 
+template <int V, bool EDGE, bool ONE = false, bool NS = false>
+__device__ __forceinline__ void tile_loop(acc_t (&acc)[RM][RN], int M, int N, int K,
+                                          const float* __restrict__ A, long lda,
+                                          const float* __restrict__ B, long ldb,
+                                          int kt0, int kt1, int tm, int tn, float* smem);
+
+// Slabs [kt0, kt1) with every load masked.  The vector kernels of the
+// register-staged variants also run where K or N is not a multiple of V
+// (their rows need only be 4-byte aligned); there the slabs go element by
+// element.
+template <int V>
+__device__ __forceinline__ void masked_slabs(acc_t (&acc)[RM][RN], int M, int N, int K,
+                                             const float* __restrict__ A, long lda,
+                                             const float* __restrict__ B, long ldb,
+                                             int kt0, int kt1, int tm, int tn, float* smem)
+{
+    if constexpr (V > 1 && kUnmasked<V>) {
+        if (K % V != 0 || N % V != 0) {
+            tile_loop<V, true, true>(acc, M, N, K, A, lda, B, ldb, kt0, kt1, tm, tn, smem);
+            return;
+        }
+    }
+    tile_loop<V, true>(acc, M, N, K, A, lda, B, ldb, kt0, kt1, tm, tn, smem);
+}
+
 // One work-group adds the products of slabs [kt0, kt1) of K for tile
 // (tm, tn) of C to its accumulators.  Every wave reaches every barrier, the
 // loop ends with one (its LDS is free again afterwards), and no wave returns
 // early.  EDGE false: slabs [kt0, kt1) lie inside K, so no load needs a
 // per-element bounds test or select.  Rows of the tile past M read row M - 1
-// instead, and load vectors past N (N a multiple of V) the last vector of
-// their row: both only feed outputs past M or N, which are never stored.
+// instead, and load vectors that run past N read the row's last V columns
+// (N >= V): those wholly past N only feed outputs past N, and the one that
+// straddles N (N not a multiple of V; NS true, for the tile that holds it)
+// has its valid part moved into place when it is staged.  Outputs past M or
+// N are never stored.
 // Only the prefetch of a slab past kt1 (issued unconditionally by the
 // two-deep loop and never staged) is sent to the safe address, by one
-// uniform test of the slab index.
-template <int V, bool EDGE>
+// uniform test of the slab index.  ONE (with EDGE): every element is loaded
+// on its own, with all three bounds tested, straight into the first LDS
+// stage, one slab at a time; for a last slab that ends inside a load vector
+// (K not a multiple of V).
+template <int V, bool EDGE, bool ONE, bool NS>
 __device__ __forceinline__ void tile_loop(acc_t (&acc)[RM][RN], int M, int N, int K,
                                           const float* __restrict__ A, long lda,
                                           const float* __restrict__ B, long ldb,
@@ -402,7 +450,7 @@ __device__ __forceinline__ void tile_loop(acc_t (&acc)[RM][RN], int M, int N, in
                 if (NVB % NT == 0 || v < NVB) {
                     const int row = v / BVEC_ROW, nn = (v % BVEC_ROW) * V;
                     const int k = kb + row, n = n0 + nn;
-                    const int nr = (EDGE || n < N) ? n : N - V;
+                    const int nr = (EDGE || n + V <= N) ? n : N - V;
                     okb[rbuf][i] = EDGE ? ((k < K) && (n < N)) : (kt < kt1);
                     rb[rbuf][i] = load_raw<V>(B + (long)k * ldb + nr, okb[rbuf][i], B);
                 }
@@ -424,7 +472,13 @@ __device__ __forceinline__ void tile_loop(acc_t (&acc)[RM][RN], int M, int N, in
                 const int v = tid + i * NT;
                 if (NVB % NT == 0 || v < NVB) {
                     const int row = v / BVEC_ROW, nn = (v % BVEC_ROW) * V;
-                    *reinterpret_cast<vt*>(sB + row * LDB_S + nn) = EDGE ? zsel<V>(rb[rbuf][i], okb[rbuf][i]) : rb[rbuf][i];
+                    vt x = EDGE ? zsel<V>(rb[rbuf][i], okb[rbuf][i]) : rb[rbuf][i];
+                    if constexpr (NS && !EDGE) {
+                        // The straddling vector was read from N - V.
+                        const int n = n0 + nn;
+                        x = vshift<V>(x, (n < N && n + V > N) ? n - (N - V) : 0);
+                    }
+                    *reinterpret_cast<vt*>(sB + row * LDB_S + nn) = x;
                 }
             }
         };
@@ -465,7 +519,24 @@ __device__ __forceinline__ void tile_loop(acc_t (&acc)[RM][RN], int M, int N, in
             }
         };
 
-        if constexpr (DMA && V == 4) {
+        if constexpr (ONE) {
+            for (int kt = kt0; kt < kt1; ++kt) {
+                const int kb = kt * KWG;
+                for (int e = tid; e < MWG * KWG; e += NT) {
+                    const int r = e / KWG, c = e - r * KWG;
+                    const int m = m0 + r, k = kb + c;
+                    sA0[r * LDA_S + c] = (m < M && k < K) ? A[(long)m * lda + k] : 0.0f;
+                }
+                for (int e = tid; e < KWG * NWG; e += NT) {
+                    const int r = e / NWG, c = e - r * NWG;
+                    const int k = kb + r, n = n0 + c;
+                    sB0[r * LDB_S + c] = (k < K && n < N) ? B[(long)k * ldb + n] : 0.0f;
+                }
+                __syncthreads();
+                compute(0);
+                __syncthreads();
+            }
+        } else if constexpr (DMA && V == 4) {
             dma_slabs(M, N, K, A, lda, B, ldb, m0, n0, kt0, kt1, wid, lane, smem, compute);
         } else if constexpr (PD == 1) {
             gload(kt0, 0);
@@ -585,12 +656,12 @@ __device__ __forceinline__ void tile_loop(acc_t (&acc)[RM][RN], int M, int N, in
 // (split `part` of `splits` when the K range is split over work-groups).
 // Every wave reaches every barrier and no wave returns before the epilogue,
 // so the grouped kernel can call this once per tile in a loop.  EDGE false:
-// all the tile's slabs lie inside K and, if the tile runs past N, N is a
-// multiple of V (the loads of the loop without masks above).  TAIL (with
+// all the tile's slabs lie inside K and N >= V (the loads of the loop
+// without masks above).  TAIL (with
 // EDGE false): the same, except that the last slab runs past K; the full
 // slabs run the loop without masks and only the last one the masked loop.
 // The epilogue tests every row and column in all three cases.
-template <int V, bool EDGE = true, bool TAIL = false>
+template <int V, bool EDGE = true, bool TAIL = false, bool NS = false>
 __device__ __forceinline__ void tile_gemm(int M, int N, int K, float alpha,
                                           const float* __restrict__ A, long lda,
                                           const float* __restrict__ B, long ldb,
@@ -616,10 +687,13 @@ __device__ __forceinline__ void tile_gemm(int M, int N, int K, float alpha,
             acc[i][j] = acc_t{};
 
     if constexpr (TAIL) {
-        tile_loop<V, false>(acc, M, N, K, A, lda, B, ldb, kt0, kt1 - 1, tm, tn, smem);
-        tile_loop<V, true>(acc, M, N, K, A, lda, B, ldb, kt1 - 1, kt1, tm, tn, smem);
+        tile_loop<V, false, false, NS>(acc, M, N, K, A, lda, B, ldb, kt0, kt1 - 1, tm, tn, smem);
+        masked_slabs<V>(acc, M, N, K, A, lda, B, ldb, kt1 - 1, kt1, tm, tn, smem);
     } else {
-        tile_loop<V, EDGE>(acc, M, N, K, A, lda, B, ldb, kt0, kt1, tm, tn, smem);
+        if constexpr (EDGE)
+            masked_slabs<V>(acc, M, N, K, A, lda, B, ldb, kt0, kt1, tm, tn, smem);
+        else
+            tile_loop<V, false, false, NS>(acc, M, N, K, A, lda, B, ldb, kt0, kt1, tm, tn, smem);
     }
 
     // ---- reduce split-K groups through LDS ---------------------------------
@@ -703,6 +777,48 @@ __device__ __forceinline__ void tile_gemm(int M, int N, int K, float alpha,
     }
 }
 
+// Tile (tm, tn) over slabs [kt0, kt1) on the loop without masks, if it can
+// take it (true), else nothing (false).  The register-staged variants run it
+// for every tile (rows past M and load vectors past N read clamped
+// addresses) while N >= V; a tile whose last slab runs past K runs its full
+// slabs so and masks only the last one.  The tile that holds a load vector
+// straddling N gets the copy of the loop that moves it into place, so the
+// others run the loop unchanged.  The load-to-LDS path clamps addresses
+// instead; the direct-load path measured slower without its selects.
+template <int V>
+__device__ __forceinline__ bool tile_unmasked(int M, int N, int K, float alpha,
+                                              const float* __restrict__ A, long lda,
+                                              const float* __restrict__ B, long ldb,
+                                              float beta, float* __restrict__ C, long ldc,
+                                              float* __restrict__ ws, int splits, int part,
+                                              int kt0, int kt1, int tm, int tn, float* smem)
+{
+    if constexpr (kUnmasked<V>) {
+        if (N < V) return false;
+        const bool full = kt1 * KWG <= K;
+        if (!full && kt1 - 1 <= kt0) return false;
+        if constexpr (V > 1) {
+            if ((tn + 1) * NWG > N && N % V != 0) {
+                if (full)
+                    tile_gemm<V, false, false, true>(M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, ws, splits, part,
+                                                     kt0, kt1, tm, tn, smem);
+                else
+                    tile_gemm<V, false, true, true>(M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, ws, splits, part,
+                                                    kt0, kt1, tm, tn, smem);
+                return true;
+            }
+        }
+        if (full)
+            tile_gemm<V, false>(M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, ws, splits, part, kt0, kt1, tm, tn,
+                                smem);
+        else
+            tile_gemm<V, false, true>(M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, ws, splits, part, kt0, kt1, tm,
+                                      tn, smem);
+        return true;
+    }
+    return false;
+}
+
 template <int V>
 __device__ __forceinline__ void gemm_body(int M, int N, int K, float alpha,
                                           const float* __restrict__ A, long lda,
@@ -717,26 +833,8 @@ __device__ __forceinline__ void gemm_body(int M, int N, int K, float alpha,
     // This work-group's slabs [kt0, kt1): all of K unless the tile is split.
     const int kt0 = (SG > 1) ? part * kper : 0;
     const int kt1 = (SG > 1) ? min(nkt, kt0 + kper) : nkt;
-    // The register-staged variants run the loop without per-element masks
-    // (rows past M and load vectors past N read clamped addresses) unless
-    // the tile runs past N with N not a multiple of the load width; a tile
-    // whose last slab runs past K runs its full slabs so and masks only the
-    // last one.  The load-to-LDS path clamps addresses instead; the
-    // direct-load path measured slower without its selects.
-    if constexpr (kUnmasked<V>) {
-        if ((tn + 1) * NWG <= N || N % V == 0) {
-            if (kt1 * KWG <= K) {
-                tile_gemm<V, false>(M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, ws, splits, part, kt0, kt1, tm,
-                                    tn, smem);
-                return;
-            }
-            if (kt1 - 1 > kt0) {
-                tile_gemm<V, false, true>(M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, ws, splits, part, kt0, kt1,
-                                          tm, tn, smem);
-                return;
-            }
-        }
-    }
+    if (tile_unmasked<V>(M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, ws, splits, part, kt0, kt1, tm, tn, smem))
+        return;
     tile_gemm<V, true>(M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, ws, splits, part, kt0, kt1, tm, tn, smem);
 }
 
@@ -778,20 +876,9 @@ __device__ __forceinline__ void grouped_body(const GemmDesc* __restrict__ d, con
         const int tm = local / nbn, tn = local - tm * nbn;
         __syncthreads();   // the previous tile is done with LDS
         const int nkt = (p.K + KWG - 1) / KWG;
-        if constexpr (kUnmasked<V>) {
-            if ((tn + 1) * NWG <= p.N || p.N % V == 0) {
-                if (nkt * KWG <= p.K) {
-                    tile_gemm<V, false>(p.M, p.N, p.K, alpha, p.A, p.lda, p.B, p.ldb, beta, p.C, p.ldc, nullptr, 1,
-                                        0, 0, nkt, tm, tn, smem);
-                    continue;
-                }
-                if (nkt > 1) {
-                    tile_gemm<V, false, true>(p.M, p.N, p.K, alpha, p.A, p.lda, p.B, p.ldb, beta, p.C, p.ldc,
-                                              nullptr, 1, 0, 0, nkt, tm, tn, smem);
-                    continue;
-                }
-            }
-        }
+        if (tile_unmasked<V>(p.M, p.N, p.K, alpha, p.A, p.lda, p.B, p.ldb, beta, p.C, p.ldc, nullptr, 1, 0, 0, nkt,
+                             tm, tn, smem))
+            continue;
         tile_gemm<V, true>(p.M, p.N, p.K, alpha, p.A, p.lda, p.B, p.ldb, beta, p.C, p.ldc, nullptr, 1, 0, 0,
                            nkt, tm, tn, smem);
     }

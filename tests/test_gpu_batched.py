@@ -63,8 +63,10 @@ def test_grouped_matches_oracle(loaded):
 
 
 def test_grouped_scalar_kernel_and_padding(loaded):
-    # Leading dimensions that are not multiples of 4: the plan falls back to
-    # the scalar-load kernel; padding columns hold NaN and must not leak in.
+    # N not a multiple of 4, one problem with N = 3, odd leading dimensions:
+    # the register-staged variants of load width 2 take their vector kernel
+    # (the load vector that straddles N is moved into place), the others the
+    # scalar-load kernel; padding columns hold NaN and must not leak in.
     shapes = [(37, 29, 53), (16, 16, 16), (70, 45, 33), (5, 3, 2)]
     ops, descs = [], []
     buf = []
@@ -80,7 +82,8 @@ def test_grouped_scalar_kernel_and_padding(loaded):
     for vid in loaded[:: max(1, len(loaded) // 12)]:
         d = np.array(descs, dtype=abi.gemm_desc_dtype())
         total, prefix, vec = abi.sgemm_grouped_plan(vid, d)
-        assert not vec
+        desc = abi.variant_info(vid).split()
+        assert bool(vec) == (int(desc[10]) == 1 and 1 < int(desc[9]) <= 3), desc   # LDS mode 1, VW <= min N
         d_dev = torch.from_numpy(d.view(np.uint8)).cuda()
         p_dev = torch.from_numpy(prefix).cuda()
         for (_, _, dC) in buf:
@@ -93,6 +96,44 @@ def test_grouped_scalar_kernel_and_padding(loaded):
             assert np.all(np.isnan(C[:, N:])), "padding written"
             _, S, T = oracle.ref_gemm(A, B)
             assert np.all(np.abs(C[:, :N] - S) <= 4 * A.shape[1] * 2.0 ** -24 * T), (vid, i)
+
+
+def test_grouped_vector_kernel_unaligned_rows(loaded):
+    # N a multiple of 4 in every problem, K and the leading dimensions of A
+    # and B odd: the register-staged variants' plans take the vector kernel
+    # (4-byte aligned rows, the K tail element by element), the others the
+    # scalar one.  NaN in the padding must not leak in.
+    shapes = [(37, 28, 53), (16, 16, 17), (70, 44, 33), (5, 4, 2), (130, 96, 131)]
+    ops, descs, buf = [], [], []
+    for i, (M, N, K) in enumerate(shapes):
+        A = datagen.uniform((62, i, 0), M, K, ld=K + 2)
+        B = datagen.uniform((62, i, 1), K, N, ld=N + 1)
+        ops.append((np.ascontiguousarray(A), np.ascontiguousarray(B)))
+        dA = torch.from_numpy(A.base.copy()).cuda()
+        dB = torch.from_numpy(B.base.copy()).cuda()
+        dC = torch.full((M, N + 2), float("nan"), device="cuda")
+        buf.append((dA, dB, dC))
+        descs.append((dA.data_ptr(), dB.data_ptr(), dC.data_ptr(), A.base.shape[1], N + 1, N + 2, M, N, K, 0))
+    took_vector = 0
+    for vid in loaded[:: max(1, len(loaded) // 16)]:
+        d = np.array(descs, dtype=abi.gemm_desc_dtype())
+        total, prefix, vec = abi.sgemm_grouped_plan(vid, d)
+        desc = abi.variant_info(vid).split()
+        assert bool(vec) == (int(desc[10]) == 1 and int(desc[9]) > 1), desc   # LDS mode 1, VW > 1
+        took_vector += bool(vec)
+        d_dev = torch.from_numpy(d.view(np.uint8)).cuda()
+        p_dev = torch.from_numpy(prefix).cuda()
+        for (_, _, dC) in buf:
+            dC.fill_(float("nan"))
+        abi.sgemm_grouped(vid, len(shapes), d_dev, p_dev, total, 1.0, 0.0, vec)
+        torch.cuda.synchronize()
+        for i, ((A, B), (_, _, dC)) in enumerate(zip(ops, buf)):
+            C = dC.cpu().numpy()
+            N = shapes[i][1]
+            assert np.all(np.isnan(C[:, N:])), "padding written"
+            _, S, T = oracle.ref_gemm(A, B)
+            assert np.all(np.abs(C[:, :N] - S) <= 4 * A.shape[1] * 2.0 ** -24 * T), (vid, i)
+    assert took_vector > 0
 
 
 def test_grouped_graph_replays(loaded):

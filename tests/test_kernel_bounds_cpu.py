@@ -1,8 +1,8 @@
 """CPU model of the register-staged kernels' global loads without masks.
 
 Tiles whose slabs lie inside K run the register-staged loop without
-per-element masks; rows past M read row M - 1 and load vectors past N (N a
-multiple of the load width) the last vector of their row.  The two-deep prefetch loop
+per-element masks; rows past M read row M - 1 and load vectors that run past
+N the row's last V columns (N >= V).  The two-deep prefetch loop
 still issues the loads of one slab past the tile's last (they are never
 staged), so those must go to the safe base address.  This test restates the
 loads' index arithmetic and the PD = 1 / PD = 2 call sequences of
@@ -40,7 +40,7 @@ def _loads(v, M, N, K, lda, ldb, tm, tn, kt0, kt1, V=None):
             if name == "A":
                 r = np.minimum(r, M - 1)            # rows past M read row M - 1
             else:
-                c = np.where(c < N, c, N - V)       # vectors past N: the row's last
+                c = np.where(c + V <= N, c, N - V)  # vectors past N: the row's last V
             assert np.all(r >= 0) and np.all(c >= 0)
             out[name] = max(out[name], int(np.max(r * ld + c + V - 1)))
 
@@ -130,7 +130,7 @@ def test_edge_tiles_stay_inside(shape):
         nbm, nbn = -(-M // v.mwg), -(-N // v.nwg)
         nkt = -(-K // v.kwg)
         for tm, tn in {(nbm - 1, nbn - 1), (nbm - 1, 0), (0, nbn - 1)}:
-            if not ((tn + 1) * v.nwg <= N or N % vw == 0):
+            if N < vw:
                 continue            # the masked loop
             for kt0, kt1 in _split_ranges(v, M, N, nkt):
                 if kt1 * v.kwg > K:
@@ -142,3 +142,33 @@ def test_edge_tiles_stay_inside(shape):
                 assert out["B"] <= (K - 1) * N + N - 1, (v.name, vw, shape, tm, tn, kt0)
                 checked += 1
     assert checked > 100
+
+
+def _vshift(v, s):
+    """The kernel's vshift: element j takes element j + s; the last s keep v[-1]."""
+    V = len(v)
+    return [v[min(j + s, V - 1)] if j < V - 1 else v[V - 1] for j in range(V)]
+
+
+@pytest.mark.parametrize("V", [2, 4])
+@pytest.mark.parametrize("N", [4, 5, 6, 7, 33, 130, 131])
+def test_straddling_vector_staged_in_place(V, N):
+    # One row of B: every load vector of every tile column, with the address
+    # rule of the loop without masks and the shift applied when staged, puts
+    # B[n + j] at staged position j for every column n + j < N.
+    if N < V:
+        return
+    row = np.arange(1000, 1000 + N)
+    for NWG in (16, 64):
+        for n0 in range(0, N, NWG):
+            nshift = n0 + NWG > N and N % V != 0
+            for nn in range(0, NWG, V):
+                n = n0 + nn
+                nr = n if n + V <= N else N - V
+                assert 0 <= nr and nr + V <= N
+                x = list(row[nr:nr + V])
+                if nshift:
+                    x = _vshift(x, n - (N - V) if n < N < n + V else 0)
+                for j in range(V):
+                    if n + j < N:
+                        assert x[j] == row[n + j], (V, N, NWG, n0, nn, j)
