@@ -15,7 +15,7 @@ table, timed live beside the dispatched one), the roofline of the dominant
 kernel, and the FP64 oracle on the host cores as a CPU baseline.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--k 4] [--no-cpu-baseline]
-                    [--form fp32|bf16x3|bf16x6|fp16s|fp16x3] [--cold]
+                    [--form fp32|bf16x3|bf16x6|fp16s|fp16x3|mixed] [--cold]
 
 ``--cold`` times every call on its own after writing a 512 MB scrub buffer
 (more than the 256 MB memory-side cache and the L2s together), so operands
@@ -25,7 +25,11 @@ come from HBM; the default is warm, back-to-back calls.
 (its own k-variant set, ``sgemm_form``) on the precision workload: the 27
 grid shapes with lognormal operands.  Its roofline is priced against the
 16-bit dense MFMA peak with the MFMA work the form issues (its number of
-term products times 2MNK); no CPU baseline is taken for it.
+term products times 2MNK); no CPU baseline is taken for it.  ``--form
+mixed`` runs the set chosen over every form's variants for a normwise error
+of at most 1e-6 (FF_FORM_MIXED): each shape in its dispatched member's form,
+against the fastest variant of any form that meets the target there, and
+each member priced against its own form's peak.
 """
 from __future__ import annotations
 
@@ -42,7 +46,7 @@ sys.path.insert(0, ROOT)
 METRIC = "SGEMM TFLOP/s geomean over (M,N,K) grid; % of per-shape best with k variants"
 FP32_MFMA_PEAK_TFLOPS = 157.3     # MI355X dense FP32 matrix peak (256 CU x 2.4 GHz x 256 flop/clk)
 MFMA16_PEAK_TFLOPS = 2500.0       # MI355X dense bf16 / fp16 matrix peak
-FORMS = {"fp32": 0, "bf16x3": 1, "bf16x6": 2, "fp16s": 3, "fp16x3": 4}
+FORMS = {"fp32": 0, "bf16x3": 1, "bf16x6": 2, "fp16s": 3, "fp16x3": 4, "mixed": 5}
 FORM_PRODUCTS = {"fp32": 1, "bf16x3": 3, "bf16x6": 6, "fp16s": 1, "fp16x3": 3}   # MFMA term products per GEMM
 TARGET_MS_PER_SHAPE = 1.0
 
@@ -183,7 +187,8 @@ def main():
     import torch
 
     from paper_2507_15277_amd import abi, datagen, tuned
-    from paper_2507_15277_amd.portability import TABLE, matrix
+    from paper_2507_15277_amd.abi import FORM_NAMES
+    from paper_2507_15277_amd.portability import ACCURACY_TARGET, TABLE, matrix
     from paper_2507_15277_amd.tune import CFG_PRECISION, current_hashes, kernel_hash, load_rows, read_manifest
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
@@ -198,8 +203,15 @@ def main():
     data = "uniform" if fid == 0 else "lognormal"
     rows = load_rows(TABLE, kernel_hash() if fid == 0 else current_hashes())
     t_table = matrix(rows, shapes, 0.0, data=data)
-    of_form = np.array([prec == fid for _, _, prec in sorted(read_manifest(with_prec=True))])
-    t_table[~of_form[:t_table.shape[0]], :] = np.inf
+    precs = [prec for _, _, prec in sorted(read_manifest(with_prec=True))]
+    if form == "mixed":
+        # The mixed set is compared with the fastest variant of any form that
+        # meets its accuracy target on the shape.
+        err = matrix(rows, shapes, 0.0, nv=t_table.shape[0], data=data, field="err_norm")
+        t_table[~(err <= ACCURACY_TARGET)] = np.inf
+    else:
+        of_form = np.array([prec == fid for prec in precs])
+        t_table[~of_form[:t_table.shape[0]], :] = np.inf
     best_ids = [int(np.argmin(t_table[:, j])) for j in range(len(shapes))]
 
     # Inputs resident in HBM before timing.
@@ -329,18 +341,23 @@ def main():
     def member_roofline(v):
         fl, tm, by, launches = share[v]
         name = abi.variant_info(v).split()[1]
+        mform = FORM_NAMES[precs[v]]      # the member's own form (they differ in the mixed set)
         served = ["x".join(map(str, s)) for j, s in enumerate(shapes) if picks[j] == v]
-        if fid == 0:
+        if mform == "fp32" and fid == 0:
             achieved = fl / tm / 1e9
             r = {"bound": "mfma", "achieved": achieved, "peak": FP32_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s",
                  "frac": achieved / FP32_MFMA_PEAK_TFLOPS,
                  "traffic": measured_traffic(name, args.k, kernel_hash(), served)}
+        elif mform == "fp32":
+            achieved = fl / tm / 1e9
+            r = {"bound": "mfma", "achieved": achieved, "peak": FP32_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s",
+                 "frac": achieved / FP32_MFMA_PEAK_TFLOPS, "traffic": None, "form": mform}
         else:
             # MFMA work the form issues: its term products, each 2MNK on 16-bit MFMA.
-            achieved = FORM_PRODUCTS[form] * fl / tm / 1e9
+            achieved = FORM_PRODUCTS[mform] * fl / tm / 1e9
             r = {"bound": "mfma", "achieved": achieved, "peak": MFMA16_PEAK_TFLOPS, "unit": "TFLOP/s",
                  "frac": achieved / MFMA16_PEAK_TFLOPS, "traffic": None,
-                 "fp32_equivalent_tflops": fl / tm / 1e9, "mfma_products": FORM_PRODUCTS[form]}
+                 "fp32_equivalent_tflops": fl / tm / 1e9, "mfma_products": FORM_PRODUCTS[mform], "form": mform}
         r.update({"kernel": name, "share_of_step": tm / step_ms, "launches_per_step": launches,
                   "flop_per_launch": fl / launches, "algorithmic_bytes_per_launch": by / launches,
                   "ms_per_launch": tm / launches, "shapes": served})
@@ -355,6 +372,10 @@ def main():
     metric = METRIC if fid == 0 else METRIC.replace("SGEMM", f"SGEMM ({form} form)", 1)
     workload = ("27-shape grid {256,1024,4096}^3 FP32 SGEMM, alpha=1 beta=0" if fid == 0 else
                 f"27-shape grid {{256,1024,4096}}^3 SGEMM in the {form} form, lognormal operands, alpha=1 beta=0")
+    if form == "mixed":
+        metric = METRIC.replace("SGEMM", f"SGEMM (any form meeting normwise error <= {ACCURACY_TARGET:g})", 1)
+        workload = (f"27-shape grid {{256,1024,4096}}^3 SGEMM, lognormal operands, alpha=1 beta=0, each shape in "
+                    f"the form its mixed-set member uses (members chosen for normwise error <= {ACCURACY_TARGET:g})")
     out = {
         "metric": metric, "value": value, "unit": "TFLOP/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup,

@@ -64,6 +64,12 @@ extern "C" {
 #define FF_FORM_BF16X6 2  /* split-bf16 in 3 pieces, 6 products */
 #define FF_FORM_FP16S 3   /* per-matrix power-of-two scaled fp16, 1 product */
 #define FF_FORM_FP16X3 4  /* the same scaled fp16 in 2 pieces, 3 products */
+/* Not a form of its own: the slot of a set whose members may be of any of
+ * the forms above, chosen per shape for an accuracy target (portability
+ * tuning over the variants whose measured normwise error meets the target,
+ * the form being one more tuned parameter; Sec. IV-B, Eq. 1).  Each call
+ * runs the chosen member in that member's own form. */
+#define FF_FORM_MIXED 5
 
 /* ---------------------------------------------------------------------
  * Hot path
@@ -114,8 +120,9 @@ int sgemm(int64_t M, int64_t N, int64_t K, float alpha,
 /*
  * Load a variant set file (the output of portability tuning, Sec. IV-B):
  * the k member variants, their parameters, the GPU architecture they were
- * built for, its precision form (a "form" line; FP32 when absent), and the
- * dispatch table of training shapes.  Only the k code
+ * built for, its precision form (a "form" line; FP32 when absent; "mixed"
+ * for FF_FORM_MIXED, whose members may be of any form), and the dispatch
+ * table of training shapes.  Only the k code
  * objects of the set are loaded (Sec. III-B-3: pre-selection keeps the
  * number of shipped variants small).  Replaces any previously loaded set
  * of the same form.  At most 64 members.  The dispatch's wave correction is
@@ -127,7 +134,8 @@ int variant_set_load(const char *path);
 
 /*
  * sgemm() in precision form `form` (FF_FORM_*), dispatched through the set
- * loaded for that form.  The 16-bit forms split each FP32 operand into
+ * loaded for that form (FF_FORM_MIXED: through the mixed set, each call in
+ * its chosen member's form).  The 16-bit forms split each FP32 operand into
  * bfloat16 or scaled float16 pieces inside the kernel and accumulate the
  * piece products in FP32 (not a paper method: an MI355X form of the same
  * operation).  Per-element error, as a multiple of |alpha|(|A||B|): about

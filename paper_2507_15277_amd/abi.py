@@ -22,8 +22,10 @@ FF_ERR_M, FF_ERR_N, FF_ERR_K = -1, -2, -3
 FF_ERR_A, FF_ERR_LDA, FF_ERR_B, FF_ERR_LDB, FF_ERR_C, FF_ERR_LDC = -5, -6, -7, -8, -10, -11
 FF_ERR_NO_SET, FF_ERR_VARIANT, FF_ERR_PARSE = -100, -101, -102
 FF_ERR_ARCH, FF_ERR_HIP, FF_ERR_IO, FF_ERR_TOO_LARGE, FF_ERR_ARG = -103, -104, -105, -106, -107
-FF_FORM_FP32, FF_FORM_BF16X3, FF_FORM_BF16X6, FF_FORM_FP16S = 0, 1, 2, 3
-FORM_NAMES = ("fp32", "bf16x3", "bf16x6", "fp16s", "fp16x3")
+FF_FORM_FP32, FF_FORM_BF16X3, FF_FORM_BF16X6, FF_FORM_FP16S, FF_FORM_FP16X3 = 0, 1, 2, 3, 4
+FORM_NAMES = ("fp32", "bf16x3", "bf16x6", "fp16s", "fp16x3")   # a variant's precision form
+FF_FORM_MIXED = 5            # the set slot whose members may be of any form
+SET_FORMS = FORM_NAMES + ("mixed",)
 
 EXPORTS = ("sgemm", "sgemm_form", "variant_set_load", "variant_select", "variant_select_form",
            "fewfit_last_error",

@@ -69,8 +69,9 @@ int ff_read_manifest(const char* dir, std::vector<FfDesc>& out, std::string& err
 //   fewfit-set 1
 //   arch <gfx name>
 //   codedir <dir>          code objects, relative to the set file's directory
-//   form <name>            optional: fp32 (default), bf16x3, bf16x6, fp16s or fp16x3;
-//                          every member must be of that form
+//   form <name>            optional: fp32 (default), bf16x3, bf16x6, fp16s or fp16x3,
+//                          and every member is of that form; or mixed, members of
+//                          any form (a set chosen for an accuracy target)
 //   variant <descriptor>   k lines, descriptor as in the manifest
 //   rule <M> <N> <K> <id> <c_1> ... <c_k>
 //                          one line per training shape (after the variant
@@ -108,7 +109,7 @@ int ff_read_set_file(const char* path, FfSetFile& set, std::string& err)
             if (!(is >> set.codedir)) return parse_fail(err, FF_ERR_PARSE, "%s:%ld: codedir needs a value", path, lineno);
         } else if (key == "form") {
             std::string name;
-            static const char* names[kFfForms] = {"fp32", "bf16x3", "bf16x6", "fp16s", "fp16x3"};
+            static const char* names[kFfForms] = {"fp32", "bf16x3", "bf16x6", "fp16s", "fp16x3", "mixed"};
             if (!(is >> name)) return parse_fail(err, FF_ERR_PARSE, "%s:%ld: form needs a value", path, lineno);
             set.form = -1;
             for (int i = 0; i < kFfForms; ++i)
@@ -160,6 +161,7 @@ int ff_read_set_file(const char* path, FfSetFile& set, std::string& err)
     if (set.arch.empty() || set.codedir.empty() || set.members.empty() || set.shapes.empty())
         return parse_fail(err, FF_ERR_PARSE, "%s: needs arch, codedir, at least one variant and one rule", path);
     for (const FfDesc& v : set.members)
-        if (v.prec != set.form) return parse_fail(err, FF_ERR_PARSE, "%s: a variant is not of the set's form", path);
+        if (set.form != kFfPrecForms && v.prec != set.form)
+            return parse_fail(err, FF_ERR_PARSE, "%s: a variant is not of the set's form", path);
     return FF_OK;
 }

@@ -9,7 +9,8 @@
 #include <string>
 #include <vector>
 
-constexpr int kFfForms = 5;        // precision forms (FF_FORM_*)
+constexpr int kFfPrecForms = 5;    // precision forms of a variant (FF_FORM_FP32 .. FF_FORM_FP16X3)
+constexpr int kFfForms = 6;        // set slots: the precision forms and FF_FORM_MIXED
 constexpr int kFfMaxMembers = 64;  // variants in one set
 
 // One compiled variant's parameters:

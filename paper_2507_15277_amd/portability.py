@@ -213,6 +213,91 @@ def precision_report(rows, variants, write_sets=False, log=print):
     return out
 
 
+ACCURACY_TARGET = 1e-6   # normwise error against FP64, the mixed set's target
+
+
+def accuracy_report(rows, variants, target=ACCURACY_TARGET, write_sets=False, log=print):
+    """Portability tuning with the precision form as one more variant
+    parameter and an accuracy target as a constraint: on the lognormal grid a
+    variant's time counts on a shape only where its measured normwise error
+    meets the target (elsewhere +inf, as for a variant that fails the screen,
+    Sec. V-C), then Eq. 1 selects k members from all forms together.  Beside
+    it, the same selection within each form alone, and the unconstrained FP32
+    set with the number of shapes where its dispatched member misses the
+    target.  The k = 4 mixed set is written as the FF_FORM_MIXED set."""
+    shapes = datagen.grid27()
+    nv = len(variants)
+    t = matrix(rows, shapes, 0.0, nv, data="lognormal")
+    en = matrix(rows, shapes, 0.0, nv, data="lognormal", field="err_norm")
+    if not np.isfinite(t).any():
+        return None
+    prec = np.array([variants[v].prec for v in range(nv)])
+    ok = np.isfinite(en) & (en <= target)
+    tt = np.where(ok, t, np.inf)
+    train, _ = datagen.checkerboard_split(shapes)
+    train_idx = [shapes.index(s) for s in train]
+    out = {"target_err_norm": target, "data": "lognormal",
+           "shapes_with_a_variant_meeting_target": {
+               "any": int(ok.any(axis=0).sum()),
+               **{abi.FORM_NAMES[p]: int(ok[prec == p].any(axis=0).sum()) for p in range(len(abi.FORM_NAMES))}},
+           "per_shape_best_geomean_tflops": {}, "sets": {}, "single_form_k4": {}}
+
+    def best_geomean(m):
+        b = np.min(m, axis=0)
+        return geomean(tflops(s, b[j]) for j, s in enumerate(shapes)) if np.isfinite(b).all() else None
+    out["per_shape_best_geomean_tflops"]["mixed"] = best_geomean(tt)
+    for p in range(len(abi.FORM_NAMES)):
+        out["per_shape_best_geomean_tflops"][abi.FORM_NAMES[p]] = best_geomean(
+            np.where((prec == p)[:, None], tt, np.inf))
+
+    def realised_errors(ev):
+        return [float(en[r["variant"], j]) for j, r in enumerate(ev["per_shape"])]
+    for k in KS:
+        kappa, cost, _ = abi.ptune_select(tt, k, shapes=train_idx, method=-1)
+        ev = evaluate(tt, shapes, train_idx, kappa)
+        errs = realised_errors(ev)
+        out["sets"][str(k)] = {
+            "kappa": list(kappa), "names": [variants[v].name for v in kappa],
+            "forms": [abi.FORM_NAMES[prec[v]] for v in kappa], "train_frac": 1.0 / cost,
+            "heldout_realised": ev["frac_heldout_realised"],
+            "geomean_tflops_realised": ev["geomean_tflops_realised"],
+            "realised_meeting_target": sum(1 for e in errs if e <= target),
+            "realised_max_err_norm": max(errs),
+            "per_shape": [{"M": r["M"], "N": r["N"], "K": r["K"], "variant": r["variant"],
+                           "form": abi.FORM_NAMES[prec[r["variant"]]], "tflops": r["tflops"],
+                           "err_norm": e} for r, e in zip(ev["per_shape"], errs)]}
+        log(f"[accuracy] k={k} at err <= {target:g}: {list(kappa)} "
+            f"({', '.join(out['sets'][str(k)]['forms'])}), geomean {ev['geomean_tflops_realised']:.2f} "
+            f"TFLOP/s, held-out realised {ev['frac_heldout_realised']:.3f}")
+        if write_sets and k == 4:
+            members = [(v, variants[v]) for v in kappa]
+            rules = [(*shapes[j], w, ev["costs"][i])
+                     for i, (j, w) in enumerate(zip(train_idx, ev["winners"]))]
+            tuned.write_set_file(
+                tuned.set_path(4, "mixed"), members, rules, form="mixed",
+                comments=(f"PortabilityTune k=4 over every form's variants on the 14 checkerboard training "
+                          f"shapes, lognormal operands, counting a variant only where its normwise error "
+                          f"is at most {target:g}",))
+    for p in range(len(abi.FORM_NAMES)):
+        tp = np.where((prec == p)[:, None], tt, np.inf)
+        if not np.isfinite(tp).any(axis=0).all():
+            continue
+        kappa, cost, _ = abi.ptune_select(tp, 4, shapes=train_idx, method=-1)
+        ev = evaluate(tp, shapes, train_idx, kappa)
+        out["single_form_k4"][abi.FORM_NAMES[p]] = {
+            "kappa": list(kappa), "geomean_tflops_realised": ev["geomean_tflops_realised"],
+            "heldout_realised": ev["frac_heldout_realised"]}
+    # The unconstrained FP32 set (its timing on these inputs, no target).
+    t32 = np.where((prec == 0)[:, None], t, np.inf)
+    kappa, _, _ = abi.ptune_select(t32, 4, shapes=train_idx, method=-1)
+    ev = evaluate(t32, shapes, train_idx, kappa)
+    errs = realised_errors(ev)
+    out["fp32_k4_unconstrained"] = {"kappa": list(kappa), "geomean_tflops_realised": ev["geomean_tflops_realised"],
+                                    "realised_meeting_target": sum(1 for e in errs if e <= target),
+                                    "realised_max_err_norm": max(errs)}
+    return out
+
+
 def read_set(path):
     """(members, training shapes, ntrain x k member log-slowdowns) of a set file."""
     members, train, cost = [], [], []
@@ -536,6 +621,7 @@ def run(table=TABLE, write_sets=False, splits=5, log=print):
     report["selectors"] = selector_comparison(t, shapes, train_idx, log=log)
     report["fleet"] = fleet_comparison(t, shapes, log=log)
     report["precision"] = precision_report(rows, variants, write_sets, log)
+    report["accuracy"] = accuracy_report(rows, variants, write_sets=write_sets, log=log)
     report["fresh"] = fresh_report(rows, variants, log)
     report["ragged"] = ragged_report(rows, variants, log)
     if os.path.exists(TABLE2):

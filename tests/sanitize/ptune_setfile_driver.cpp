@@ -53,7 +53,8 @@ void parser_cases(const std::string& sets, const std::string& variants, const st
     expect(ff_read_manifest(variants.c_str(), manifest, err) == FF_OK && !manifest.empty(), "manifest parses");
     expect(ff_read_manifest((scratch + "/none").c_str(), manifest, err) == FF_ERR_IO, "missing manifest is FF_ERR_IO");
     const char* names[] = {"set_k1.txt", "set_k2.txt", "set_k4.txt", "set_k8.txt", "fixed_k1.txt",
-                           "set_bf16x3_k4.txt", "set_bf16x6_k4.txt", "set_fp16s_k4.txt", "set_fp16x3_k4.txt"};
+                           "set_bf16x3_k4.txt", "set_bf16x6_k4.txt", "set_fp16s_k4.txt", "set_fp16x3_k4.txt",
+                           "set_mixed_k4.txt"};
     std::mt19937_64 rng(2507);
     const std::string tmp = scratch + "/mutated_set.txt";
     long parsed = 0, refused = 0;
@@ -62,6 +63,12 @@ void parser_cases(const std::string& sets, const std::string& variants, const st
         FfSetFile s;
         expect(ff_read_set_file(path.c_str(), s, err) == FF_OK, ("committed set parses: " + path).c_str());
         expect(s.cost.size() == s.shapes.size() * s.members.size(), "cost is ntrain x k");
+        if (std::string(n) == "set_mixed_k4.txt") {
+            // The mixed slot holds members of more than one precision form.
+            bool several = false;
+            for (const FfDesc& v : s.members) several = several || v.prec != s.members[0].prec;
+            expect(s.form == kFfPrecForms && several, "mixed set: its own slot, members of several forms");
+        }
         const std::string text = slurp(path);
         // Truncated at every byte, then random byte edits and token swaps.
         for (size_t cut = 0; cut < text.size(); cut += 1 + text.size() / 400) {

@@ -74,7 +74,8 @@ def test_null_operands_allowed_when_not_read(L):
 def test_form_arguments(L):
     assert L.sgemm_form(7, 4, 4, 4, 1.0, 8, 4, 8, 4, 0.0, 8, 4, None) == abi.FF_ERR_ARG
     assert L.sgemm_form(-1, 4, 4, 4, 1.0, 8, 4, 8, 4, 0.0, 8, 4, None) == abi.FF_ERR_ARG
-    assert L.variant_select_form(5, 1, 1, 1) == abi.FF_ERR_ARG
+    assert L.variant_select_form(6, 1, 1, 1) == abi.FF_ERR_ARG
+    assert L.variant_select_form(abi.FF_FORM_MIXED, 1, 1, 1) == abi.FF_ERR_NO_SET
     assert L.variant_select_form(2, 1, 1, 1) == abi.FF_ERR_NO_SET
     assert L.variant_select_form(4, 1, 1, 1) == abi.FF_ERR_NO_SET
     assert L.sgemm_form(1, -1, 4, 4, 1.0, 8, 4, 8, 4, 0.0, 8, 4, None) == abi.FF_ERR_M
@@ -112,11 +113,29 @@ GOOD_VARIANT = space.DEFAULT.descriptor(0)
      abi.FF_ERR_PARSE),
     (f"fewfit-set 1\narch gfx950\ncodedir .\nform fp64\nvariant {GOOD_VARIANT}\nrule 1 1 1 0 0\nend\n",
      abi.FF_ERR_PARSE),
+    # a form may be given once per set file
+    (f"fewfit-set 1\narch gfx950\ncodedir .\nform mixed\nform mixed x\nvariant {GOOD_VARIANT}\nrule 1 1 1 0 0\n"
+     "end\n", abi.FF_ERR_PARSE),
 ])
+
 def test_set_file_parse_errors(L, tmp_path, body, code):
     p = tmp_path / "set.txt"
     p.write_text(body)
     assert L.variant_set_load(os.fsencode(str(p))) == code, abi.last_error()
+
+
+def test_mixed_set_parses(L, tmp_path):
+    # The mixed slot takes members of any form: the file parses, and only the
+    # device check (no GPU here) can refuse it.
+    split = "7 y 64 64 32 32 2 2 1 4 1 8 1 4 1"      # an fp16x3 descriptor
+    p = tmp_path / "set.txt"
+    p.write_text(f"fewfit-set 1\narch gfx950\ncodedir .\nform mixed\nvariant {GOOD_VARIANT}\nvariant {split}\n"
+                 "rule 1 1 1 0 0 0.5\nend\n")
+    rc = L.variant_set_load(os.fsencode(str(p)))
+    assert rc != abi.FF_ERR_PARSE, abi.last_error()
+    # The same members under a single form are refused.
+    p.write_text(p.read_text().replace("form mixed", "form fp32"))
+    assert L.variant_set_load(os.fsencode(str(p))) == abi.FF_ERR_PARSE
 
 
 def test_set_file_missing(L, tmp_path):
@@ -408,3 +427,33 @@ def test_ragged_report_on_a_synthetic_table():
             assert len(sel["kappa"]) == int(k)
             assert all(0 < sel[x] <= 1.0 for x in ("heldout_aligned", "heldout_ragged", "fresh_paper_grid",
                                                  "fresh_ragged"))
+
+
+def test_accuracy_report_on_a_synthetic_table():
+    # FP32 variants miss the 1e-6 target on every K = 4096 shape, the fp16x3
+    # variants meet it everywhere: the constrained selection must realise a
+    # member that meets the target on all 27 shapes, and FP32 alone covers
+    # only the shapes it meets it on.
+    from paper_2507_15277_amd import portability
+    variants = portability.read_variants()
+    rng = np.random.default_rng(83)
+    rows = []
+    for s in datagen.grid27():
+        for v in variants:
+            p = variants[v].prec
+            if p not in (0, 4):
+                continue
+            err = (2e-6 if s[2] == 4096 else 5e-7) if p == 0 else 3e-7
+            rows.append({"M": s[0], "N": s[1], "K": s[2], "beta": 0.0, "status": "ok", "variant": v,
+                         "data": "lognormal", "ms": float(np.exp(rng.normal(0.3 * (p > 0), 0.5))),
+                         "err_norm": err})
+    rep = portability.accuracy_report(rows, variants, log=lambda *_: None)
+    assert rep["shapes_with_a_variant_meeting_target"]["fp32"] == 18
+    assert rep["shapes_with_a_variant_meeting_target"]["fp16x3"] == 27
+    assert rep["per_shape_best_geomean_tflops"]["fp32"] is None
+    for k, sel in rep["sets"].items():
+        assert len(sel["kappa"]) == int(k)
+        assert sel["realised_meeting_target"] == 27 and sel["realised_max_err_norm"] <= 1e-6
+        assert all(r["form"] == "fp16x3" for r in sel["per_shape"] if r["K"] == 4096)
+    assert set(rep["sets"]["4"]["forms"]) == {"fp32", "fp16x3"}
+    assert rep["fp32_k4_unconstrained"]["realised_meeting_target"] == 18

@@ -25,7 +25,7 @@ from tests.gpu_util import run_gemm
 pytestmark = pytest.mark.gpu
 
 SETS_DIR = os.path.dirname(tuned.set_path(4))
-FORMS = {"fp32": 0, "bf16x3": 1, "bf16x6": 2, "fp16s": 3, "fp16x3": 4}
+FORMS = {"fp32": 0, "bf16x3": 1, "bf16x6": 2, "fp16s": 3, "fp16x3": 4, "mixed": 5}
 
 
 def _parse(path):

@@ -144,6 +144,48 @@ def test_split_forms_full_size_through_set(form, shape):
     assert (lhs <= bound).all(), (form, shape, float(np.max(lhs / bound)))
 
 
+@pytest.mark.parametrize("shape", datagen.grid27(), ids=lambda s: "x".join(map(str, s)))
+def test_mixed_set_full_size_meets_target(shape):
+    # The mixed set (members of several forms chosen for a normwise error of
+    # at most 1e-6 on lognormal operands): each call runs its dispatched
+    # member in that member's form, checked to that form's elementwise bound
+    # on sampled rows and columns, and the normwise error of 64 sampled rows
+    # against the FP64 product must meet the target (the target is on the
+    # whole result, which the rows estimate; the 1.25 covers the sampling).
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    assert abi.variant_set_load(tuned.set_path(4, "mixed")) == 4
+    M, N, K = shape
+    A = datagen.lognormal((51, M, N, K, 0), M, K)
+    B = datagen.lognormal((51, M, N, K, 1), K, N)
+    vid = abi.variant_select_form(abi.FF_FORM_MIXED, M, N, K)
+    form = abi.FORM_NAMES[int(abi.variant_info(vid).split()[13])]
+    C = _gpu_gemm(A, B, abi.FF_FORM_MIXED).astype(np.float64)
+    assert np.isfinite(C).all(), shape
+    rng = np.random.default_rng([11, M, N, K])
+    rows, cols = _sample_idx(rng, M, 64), _sample_idx(rng, N)
+    exact_rows, _, _ = oracle.ref_gemm(np.ascontiguousarray(A[rows]), B)
+    rel = np.linalg.norm(C[rows] - exact_rows) / np.linalg.norm(exact_rows)
+    assert rel <= 1.25e-6, (shape, form, rel)
+    if form == "fp32":
+        Cref, S, T = oracle.ref_gemm(np.ascontiguousarray(A[rows]), np.ascontiguousarray(B[:, cols]))
+        tol = oracle.gemm_tolerance(K, 1.0, 0.0, S, T, None)
+        err = np.abs(C[np.ix_(rows, cols)] - Cref)
+    else:
+        pa, ea = pr.pieces(A, form)
+        pb, eb = pr.pieces(B, form)
+        sc = 2.0 ** -(ea + eb)
+        Cs = np.zeros((len(rows), len(cols)))
+        Ts = np.zeros_like(Cs)
+        for ta, tb in pr.PAIRS[form]:
+            _, s_, t_ = oracle.ref_gemm(np.ascontiguousarray(pa[ta][rows]), np.ascontiguousarray(pb[tb][:, cols]))
+            Cs += s_
+            Ts += t_
+        tol = pr.accumulation_tolerance(K, form, 1.0, 0.0, Ts * sc)
+        err = np.abs(C[np.ix_(rows, cols)] - Cs * sc)
+    assert (err <= tol).all(), (shape, form, float(np.max(err / tol)))
+
+
 def test_fp32_output_past_2_31_elements(k4_set):
     # C of 65,543 x 65,543 floats (4.3e9 elements, 17 GB): every row, tile
     # and element offset must be formed in 64 bits.  K = 5, through the set.
