@@ -17,7 +17,7 @@ role of the paper's environments and the total time of the batch is the
 single-device form of the fleet objective (Eq. 2).
 
     python -m paper_2507_15277_amd.batched [--count 2000] [--buckets 4] [--out report.json]
-                                           [--bucket-variants ID,ID,ID,ID]
+                                           [--bucket-variants ID,ID,ID,ID] [--split-k]
 """
 from __future__ import annotations
 
@@ -54,11 +54,19 @@ def bucket_members(shapes, bucket_of, b):
     return sorted(idx, key=lambda i: (-shapes[i][2], -shapes[i][0] * shapes[i][1], i))
 
 
-def buckets_of(shapes, nb):
-    """Bucket index per problem: quantiles of log(M N K), nb buckets."""
+def buckets_of(shapes, nb, split_k=False):
+    """Bucket index per problem: quantiles of log(M N K), nb buckets.  With
+    split_k the largest bucket is cut again at its median K (K above it goes
+    to bucket nb), so that its long-K problems may take a deeper slab than
+    its short-K ones: nb + 1 buckets."""
     w = np.log(np.array([m * n * k for m, n, k in shapes], dtype=np.float64))
     edges = np.quantile(w, np.linspace(0, 1, nb + 1)[1:-1]) if nb > 1 else []
-    return np.searchsorted(edges, w, side="right").astype(int)
+    b = np.searchsorted(edges, w, side="right").astype(int)
+    if split_k:
+        top = b == nb - 1
+        ks = np.array([k for _, _, k in shapes])
+        b[top & (ks > np.median(ks[top]))] = nb
+    return b
 
 
 class Batch:
@@ -216,7 +224,7 @@ def tune_buckets(batch, bucket_of, nb, candidates, log=print):
     return best
 
 
-def run(count=2000, nb=4, seed=0, log=print, bucket_variants=None):
+def run(count=2000, nb=4, seed=0, log=print, bucket_variants=None, split_k=False):
     """Tune the bucket variants (or take ``bucket_variants``, one id per
     bucket), check the grouped launches on a few problems per bucket against
     the FP64 reference, then time per-problem launches, grouped launches and
@@ -227,7 +235,8 @@ def run(count=2000, nb=4, seed=0, log=print, bucket_variants=None):
     fp32 = [vid for vid, _, prec in read_manifest(with_prec=True) if prec == 0]
     shapes = batch_shapes(count, seed)
     batch = Batch(shapes, seed=seed)
-    bucket_of = buckets_of(shapes, nb)
+    bucket_of = buckets_of(shapes, nb, split_k)
+    nb = int(bucket_of.max()) + 1
     t0 = time.perf_counter()
     if bucket_variants is None:
         best = tune_buckets(batch, bucket_of, nb, fp32, log)
@@ -295,7 +304,7 @@ def run(count=2000, nb=4, seed=0, log=print, bucket_variants=None):
         raise RuntimeError("the concurrent graph fails the screen")
     ms_graph_c = time_it(graph_c.replay, reps=20, warmup=2)
     tf = lambda ms: batch.flops / ms / 1e9  # noqa: E731
-    rep = {"count": count, "buckets": nb, "seed": seed, "gflop": batch.flops / 1e9,
+    rep = {"count": count, "buckets": nb, "split_k": split_k, "seed": seed, "gflop": batch.flops / 1e9,
            "algorithmic_gbytes": sum(4.0 * (M * K + K * N + M * N) for M, N, K in shapes) / 1e9,
            "bucket_variants": {str(b): {"variant": v, "name": abi.variant_info(v).split()[1], "ms": ms,
                                         "problems": int(np.sum(bucket_of == b))}
@@ -321,9 +330,12 @@ def main(argv=None):
     ap.add_argument("--out", default=None)
     ap.add_argument("--bucket-variants", default=None,
                     help="comma-separated variant ids, one per bucket (skips the bucket tuning)")
+    ap.add_argument("--split-k", action="store_true",
+                    help="cut the largest size bucket again at its median K (one more bucket)")
     args = ap.parse_args(argv)
     bv = [int(x) for x in args.bucket_variants.split(",")] if args.bucket_variants else None
-    rep = run(args.count, args.buckets, args.seed, log=lambda s: print(s, flush=True), bucket_variants=bv)
+    rep = run(args.count, args.buckets, args.seed, log=lambda s: print(s, flush=True), bucket_variants=bv,
+              split_k=args.split_k)
     if args.out:
         with open(args.out, "w") as f:
             json.dump(rep, f, indent=1)

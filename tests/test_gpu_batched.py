@@ -209,13 +209,15 @@ def test_plan_rejects_bad_problems(loaded):
 
 
 def _committed_bucket_variants():
-    """Variant ids of the committed batched run's bucket variants."""
+    """(count, bucket variant ids, size buckets before any K cut, whether the
+    largest was cut at its median K) of the committed batched run."""
     import json
     rep = json.load(open(os.path.join(os.path.dirname(tuned.VARIANT_DIR), "data", "mi355x_batched.json")))
     names = [rep["bucket_variants"][str(b)]["name"] for b in range(rep["buckets"])]
     ids = {l.split()[1]: int(l.split()[0]) for l in open(os.path.join(tuned.VARIANT_DIR, "manifest.txt"))
            if not l.startswith("#")}
-    return rep["count"], [ids[n] for n in names]
+    split_k = bool(rep.get("split_k", False))
+    return rep["count"], [ids[n] for n in names], rep["buckets"] - int(split_k), split_k
 
 
 def test_full_batch_2000_against_oracle(loaded):
@@ -225,13 +227,14 @@ def test_full_batch_2000_against_oracle(loaded):
     # bucket variants, then the same launches replayed from a HIP graph.
     # Every problem is checked against the oracle on sampled rows and
     # columns, and over its whole result through C x against A (B x).
-    count, bucket_vids = _committed_bucket_variants()
+    count, bucket_vids, nb, split_k = _committed_bucket_variants()
     assert count == 2000
     shapes = batched.batch_shapes(count, 0)
     ops = [(datagen.uniform((62, i, 0), M, K), datagen.uniform((62, i, 1), K, N))
            for i, (M, N, K) in enumerate(shapes)]
     batch = batched.Batch(shapes, host_ops=ops)
-    bucket_of = batched.buckets_of(shapes, len(bucket_vids))
+    bucket_of = batched.buckets_of(shapes, nb, split_k)
+    assert int(bucket_of.max()) + 1 == len(bucket_vids)
     plans = [batched.GroupedPlan(batch, batched.bucket_members(shapes, bucket_of, b), vid)
              for b, vid in enumerate(bucket_vids)]
     assert sum(p.count for p in plans) == count

@@ -117,6 +117,26 @@ def test_noalloc_through_committed_sets(form):
     _two_calls(fid, form, [(1024, 1024, 1024), (256, 256, 4096)], 80)
 
 
+def test_noalloc_through_the_mixed_set():
+    # The mixed set (members of several forms): one shape its rule sends to
+    # an fp16x3 member, then one it sends to an FP32 member, each to its
+    # member form's oracle and bitwise equal to sgemm_form.
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    assert abi.variant_set_load(tuned.set_path(4, "mixed")) == 4
+    seen = []
+    for i, (M, N, K) in enumerate([(1024, 4096, 256), (256, 256, 4096)]):
+        vid = abi.variant_select_form(abi.FF_FORM_MIXED, M, N, K)
+        form = abi.FORM_NAMES[int(abi.variant_info(vid).split()[13])]
+        seen.append(form)
+        A, B, C0 = _operands(90 + i, M, N, K, form)
+        want = _run(abi.sgemm_form, abi.FF_FORM_MIXED, A, B, C0)
+        got = _run(abi.sgemm_form_noalloc, abi.FF_FORM_MIXED, A, B, C0)
+        assert np.array_equal(got, want), ((M, N, K), form, "differs from sgemm_form")
+        _check_oracle(got, A, B, C0, form)
+    assert seen == ["fp16x3", "fp32"], seen
+
+
 def test_noalloc_rejects_beyond_the_array(tmp_path):
     # bf16x6 pieces of 8192 x 8192 x 4096 take 2 * 3 * 16384 * 4096 bytes
     # (384 MiB), beyond the 256 MiB array: refused before any launch, C
