@@ -298,6 +298,29 @@ def accuracy_report(rows, variants, target=ACCURACY_TARGET, write_sets=False, lo
     return out
 
 
+SWEEP_TARGETS = (3e-4, 1e-5, 1e-6, 5e-7)
+
+
+def accuracy_sweep(rows, variants, targets=SWEEP_TARGETS, log=print):
+    """The accuracy target against speed: for each target the per-shape best
+    geomean over every form's variants that meet it, and the k = 4 set chosen
+    under it (its forms and realised geomean)."""
+    out = []
+    for tau in targets:
+        r = accuracy_report(rows, variants, target=tau, log=lambda *_: None)
+        if r is None:
+            return None
+        s4 = r["sets"]["4"]
+        out.append({"target_err_norm": tau, "per_shape_best_geomean_tflops": r["per_shape_best_geomean_tflops"]["mixed"],
+                    "k4_kappa": s4["kappa"], "k4_forms": s4["forms"],
+                    "k4_geomean_tflops_realised": s4["geomean_tflops_realised"],
+                    "k4_realised_meeting_target": s4["realised_meeting_target"],
+                    "k4_realised_max_err_norm": s4["realised_max_err_norm"]})
+        log(f"[accuracy sweep] err <= {tau:g}: best {out[-1]['per_shape_best_geomean_tflops']:.1f}, k=4 "
+            f"{s4['geomean_tflops_realised']:.1f} TFLOP/s ({', '.join(s4['forms'])})")
+    return out
+
+
 def read_set(path):
     """(members, training shapes, ntrain x k member log-slowdowns) of a set file."""
     members, train, cost = [], [], []
@@ -622,6 +645,8 @@ def run(table=TABLE, write_sets=False, splits=5, log=print):
     report["fleet"] = fleet_comparison(t, shapes, log=log)
     report["precision"] = precision_report(rows, variants, write_sets, log)
     report["accuracy"] = accuracy_report(rows, variants, write_sets=write_sets, log=log)
+    if report["accuracy"] is not None:
+        report["accuracy"]["sweep"] = accuracy_sweep(rows, variants, log=log)
     report["fresh"] = fresh_report(rows, variants, log)
     report["ragged"] = ragged_report(rows, variants, log)
     if os.path.exists(TABLE2):

@@ -457,3 +457,21 @@ def test_accuracy_report_on_a_synthetic_table():
         assert all(r["form"] == "fp16x3" for r in sel["per_shape"] if r["K"] == 4096)
     assert set(rep["sets"]["4"]["forms"]) == {"fp32", "fp16x3"}
     assert rep["fp32_k4_unconstrained"]["realised_meeting_target"] == 18
+
+
+def test_accuracy_sweep_is_monotone_on_a_synthetic_table():
+    # A looser target admits more variants, so the per-shape best can only
+    # rise; every target's k = 4 set meets it on every shape it dispatches.
+    from paper_2507_15277_amd import portability
+    variants = portability.read_variants()
+    rng = np.random.default_rng(89)
+    errs = {0: 5e-7, 1: 3e-6, 2: 2e-7, 3: 2e-4, 4: 3e-7}
+    rows = [{"M": s[0], "N": s[1], "K": s[2], "beta": 0.0, "status": "ok", "variant": v, "data": "lognormal",
+             "ms": float(np.exp(rng.normal(-0.3 * variants[v].prec, 0.5))),
+             "err_norm": errs[variants[v].prec] * (2.0 if s[2] == 4096 else 1.0)}
+            for s in datagen.grid27() for v in variants]
+    sweep = portability.accuracy_sweep(rows, variants, targets=(1e-3, 1e-5, 1e-6, 5e-7), log=lambda *_: None)
+    best = [r["per_shape_best_geomean_tflops"] for r in sweep]
+    assert all(a >= b for a, b in zip(best, best[1:])), best
+    for r in sweep:
+        assert r["k4_realised_meeting_target"] == 27 and r["k4_realised_max_err_norm"] <= r["target_err_norm"]
