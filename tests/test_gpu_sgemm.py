@@ -68,10 +68,13 @@ def test_default_variant_first_workload(loaded):
     assert np.all(np.abs(C - Cref) <= 4 * K * 2.0 ** -24 * T)
 
 
-@pytest.mark.parametrize("shape", [(133, 97, 75), (64, 64, 16), (1, 1, 1), (257, 33, 129)])
+@pytest.mark.parametrize("shape", [(133, 97, 75), (64, 64, 16), (1, 1, 1), (257, 33, 129), (70, 6, 37)])
 def test_every_variant_ragged_padded(loaded, shape):
     # Ragged sizes over several tiles, leading dimensions larger than the
-    # widths (padding is NaN), alpha/beta both active.
+    # widths (padding is NaN), alpha/beta both active.  70 x 6 x 37: N below
+    # one tile and not a multiple of 4 (the load vector straddling N is the
+    # tile's second), K inside one slab of most variants and not a multiple
+    # of 4 (element-wise last slab).
     M, N, K = shape
     lda, ldb, ldc = K + 3, N + 5, N + 2
     A = datagen.uniform((20, M, N, K, 0), M, K)
