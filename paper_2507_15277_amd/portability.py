@@ -38,6 +38,9 @@ TABLE = os.path.join(DATA_DIR, "mi355x_table.jsonl")
 # A second, independent FP32 table of the grid (another lease), for the
 # robustness of the selection.
 TABLE2 = os.path.join(DATA_DIR, "mi355x_table_run2.jsonl")
+# Every form on the fresh shapes with lognormal operands (kept apart: only
+# the accuracy-targeted set's generalisation report reads it).
+TABLE_FRESH_LN = os.path.join(DATA_DIR, "mi355x_table_fresh_lognormal.jsonl")
 KS = (1, 2, 4, 8)
 
 
@@ -295,6 +298,47 @@ def accuracy_report(rows, variants, target=ACCURACY_TARGET, write_sets=False, lo
     out["fp32_k4_unconstrained"] = {"kappa": list(kappa), "geomean_tflops_realised": ev["geomean_tflops_realised"],
                                     "realised_meeting_target": sum(1 for e in errs if e <= target),
                                     "realised_max_err_norm": max(errs)}
+    return out
+
+
+def accuracy_fresh_report(rows, variants, target=ACCURACY_TARGET, log=print):
+    """The committed mixed set and the FP32 k = 4 set, frozen, on the fresh
+    shapes with lognormal operands (timed after the sets were chosen): each
+    shape dispatched by the runtime's rule, its member's time and measured
+    normwise error against the fastest variant of any form that meets the
+    target on that shape."""
+    shapes = datagen.fresh_shapes()
+    nv = len(variants)
+    t = matrix(rows, shapes, 0.0, nv, data="lognormal")
+    en = matrix(rows, shapes, 0.0, nv, data="lognormal", field="err_norm")
+    if not np.isfinite(t).any(axis=0).all():
+        return None
+    tt = np.where(np.isfinite(en) & (en <= target), t, np.inf)
+    best = np.min(tt, axis=0)
+    n_grid = 37
+    out = {"target_err_norm": target, "n_shapes": len(shapes), "n_paper_grid": n_grid,
+           "per_shape_best_geomean_tflops": geomean(tflops(s, best[j]) for j, s in enumerate(shapes)), "sets": {}}
+    for label, path in (("mixed_k4", tuned.set_path(4, "mixed")), ("fp32_k4", tuned.set_path(4))):
+        members, train, cost = read_set(path)
+        picks = [dispatch(train, members, cost, *s) for s in shapes]
+        ts = [float(t[p, j]) for j, p in enumerate(picks)]
+        es = [float(en[p, j]) for j, p in enumerate(picks)]
+        ok = [j for j in range(len(shapes)) if np.isfinite(ts[j])]
+        met = [j for j in ok if es[j] <= target]
+        # Speed as a fraction of the fastest variant meeting the target, on
+        # the shapes where the dispatched member meets it too.
+        frac = lambda idx: geomean(best[j] / ts[j] for j in idx if np.isfinite(best[j]))  # noqa: E731
+        out["sets"][label] = {
+            "geomean_tflops_realised": geomean(tflops(shapes[j], ts[j]) for j in ok),
+            "frac_of_best_meeting_target": frac(met),
+            "frac_paper_grid": frac([j for j in met if j < n_grid]),
+            "frac_random": frac([j for j in met if j >= n_grid]),
+            "meeting_target": len(met), "timed": len(ok),
+            "max_err_norm": max(es[j] for j in ok),
+            "missed": [{"M": shapes[j][0], "N": shapes[j][1], "K": shapes[j][2], "err_norm": es[j],
+                        "form": abi.FORM_NAMES[variants[picks[j]].prec]} for j in ok if es[j] > target]}
+        log(f"[accuracy fresh] {label}: geomean {out['sets'][label]['geomean_tflops_realised']:.1f} TFLOP/s, "
+            f"{out['sets'][label]['meeting_target']}/{len(ok)} shapes meet {target:g}")
     return out
 
 
@@ -647,6 +691,9 @@ def run(table=TABLE, write_sets=False, splits=5, log=print):
     report["accuracy"] = accuracy_report(rows, variants, write_sets=write_sets, log=log)
     if report["accuracy"] is not None:
         report["accuracy"]["sweep"] = accuracy_sweep(rows, variants, log=log)
+        if os.path.exists(TABLE_FRESH_LN):
+            report["accuracy"]["fresh"] = accuracy_fresh_report(load_rows(TABLE_FRESH_LN, current_hashes()),
+                                                                variants, log=log)
     report["fresh"] = fresh_report(rows, variants, log)
     report["ragged"] = ragged_report(rows, variants, log)
     if os.path.exists(TABLE2):

@@ -40,7 +40,7 @@ KERNEL_SRC = os.path.join(PKG, "csrc", "sgemm_variant.hip")
 SPLIT_SRC = os.path.join(PKG, "csrc", "sgemm_split.hip")
 
 # Seed tags of the workloads (first element of every seed tuple).
-CFG_SQUARE, CFG_GRID, CFG_PRECISION, CFG_FRESH, CFG_RAGGED = 2, 3, 5, 6, 7
+CFG_SQUARE, CFG_GRID, CFG_PRECISION, CFG_FRESH, CFG_RAGGED, CFG_FRESH_LOGNORMAL = 2, 3, 5, 6, 7, 8
 
 # Per-product truncation error of each 16-bit form, as a multiple of |a||b|,
 # and its number of term products.  Round-to-nearest bf16 keeps 8 bits
@@ -112,6 +112,10 @@ def workload(sets):
         # Shapes that chose nothing: timed after the sets and the dispatch
         # rule are frozen, to measure how the sets generalise.
         jobs += [(CFG_FRESH, M, N, K, 0.0, "uniform") for (M, N, K) in datagen.fresh_shapes()]
+    if "fresh_lognormal" in sets:
+        # The same shapes on the precision workload (every form): how the
+        # accuracy-targeted set generalises, in speed and in error.
+        jobs += [(CFG_FRESH_LOGNORMAL, M, N, K, 0.0, "lognormal") for (M, N, K) in datagen.fresh_shapes()]
     # A shape shared by two sets is timed once (the first set's inputs).
     seen, out = set(), []
     for j in jobs:

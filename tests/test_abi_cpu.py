@@ -475,3 +475,25 @@ def test_accuracy_sweep_is_monotone_on_a_synthetic_table():
     assert all(a >= b for a, b in zip(best, best[1:])), best
     for r in sweep:
         assert r["k4_realised_meeting_target"] == 27 and r["k4_realised_max_err_norm"] <= r["target_err_norm"]
+
+
+def test_accuracy_fresh_report_on_a_synthetic_table():
+    # The committed mixed and FP32 sets dispatched on the fresh shapes: a
+    # shape's member must be one of the set's, and the counts of shapes
+    # meeting the target follow the planted errors (FP32 misses it where
+    # K > 4096).
+    from paper_2507_15277_amd import portability
+    variants = portability.read_variants()
+    rng = np.random.default_rng(97)
+    rows = [{"M": s[0], "N": s[1], "K": s[2], "beta": 0.0, "status": "ok", "variant": v, "data": "lognormal",
+             "ms": float(np.exp(rng.normal(0, 0.5))),
+             "err_norm": (2e-6 if s[2] > 4096 else 5e-7) if variants[v].prec == 0 else 3e-7}
+            for s in datagen.fresh_shapes() for v in variants]
+    rep = portability.accuracy_fresh_report(rows, variants, log=lambda *_: None)
+    long_k = sum(1 for s in datagen.fresh_shapes() if s[2] > 4096)
+    assert long_k > 0
+    fp32 = rep["sets"]["fp32_k4"]
+    assert fp32["timed"] == 57 and fp32["meeting_target"] == 57 - long_k
+    assert all(m["K"] > 4096 and m["form"] == "fp32" for m in fp32["missed"])
+    mixed = rep["sets"]["mixed_k4"]
+    assert mixed["timed"] == 57 and 0 < mixed["frac_of_best_meeting_target"] <= 1.0
