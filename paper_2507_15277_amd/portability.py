@@ -342,6 +342,44 @@ def accuracy_fresh_report(rows, variants, target=ACCURACY_TARGET, log=print):
     return out
 
 
+def accuracy_training_report(rows, variants, target=ACCURACY_TARGET, log=print):
+    """Whether more training shapes help the accuracy-targeted selection on
+    unseen ones: the constrained selection trained on the 14 checkerboard
+    grid shapes and on the paper's whole 64-shape {256, 512, 1024, 4096}^3
+    grid (the 27 grid shapes plus the 37 fresh ones off it), each scored by
+    dispatch on the 20 random fresh shapes, which neither saw.  ``rows``
+    must hold the lognormal rows of both the grid and the fresh shapes."""
+    grid, fresh = datagen.grid27(), datagen.fresh_shapes()
+    shapes = list(grid) + list(fresh)
+    nv = len(variants)
+    t = matrix(rows, shapes, 0.0, nv, data="lognormal")
+    en = matrix(rows, shapes, 0.0, nv, data="lognormal", field="err_norm")
+    if not np.isfinite(t).any(axis=0).all():
+        return None
+    tt = np.where(np.isfinite(en) & (en <= target), t, np.inf)
+    best = np.min(tt, axis=0)
+    train14, _ = datagen.checkerboard_split(grid)
+    trainings = {"grid14": [shapes.index(s) for s in train14],
+                 "paper_grid64": list(range(len(grid) + 37))}
+    held = list(range(len(grid) + 37, len(shapes)))
+    out = {"target_err_norm": target, "held_out": [list(shapes[j]) for j in held], "sets": {}}
+    for label, tr in trainings.items():
+        train = [shapes[j] for j in tr]
+        for k in (4, 8):
+            kappa, cost, _ = abi.ptune_select(tt, k, shapes=tr, method=-1)
+            costs = member_costs(tt, kappa, tr)
+            picks = {j: dispatch(train, kappa, costs, *shapes[j]) for j in held}
+            rec = {"kappa": list(kappa), "forms": [abi.FORM_NAMES[variants[v].prec] for v in kappa],
+                   "train_frac": 1.0 / cost,
+                   "heldout_frac": geomean(best[j] / t[picks[j], j] for j in held),
+                   "heldout_geomean_tflops": geomean(tflops(shapes[j], t[picks[j], j]) for j in held),
+                   "heldout_meeting_target": sum(1 for j in held if en[picks[j], j] <= target)}
+            out["sets"][f"{label}_k{k}"] = rec
+            log(f"[accuracy training] {label} k={k}: held-out fraction {rec['heldout_frac']:.3f}, "
+                f"{rec['heldout_meeting_target']}/{len(held)} meet {target:g}")
+    return out
+
+
 SWEEP_TARGETS = (3e-4, 1e-5, 1e-6, 5e-7)
 
 
@@ -692,8 +730,9 @@ def run(table=TABLE, write_sets=False, splits=5, log=print):
     if report["accuracy"] is not None:
         report["accuracy"]["sweep"] = accuracy_sweep(rows, variants, log=log)
         if os.path.exists(TABLE_FRESH_LN):
-            report["accuracy"]["fresh"] = accuracy_fresh_report(load_rows(TABLE_FRESH_LN, current_hashes()),
-                                                                variants, log=log)
+            rows_fl = load_rows(TABLE_FRESH_LN, current_hashes())
+            report["accuracy"]["fresh"] = accuracy_fresh_report(rows_fl, variants, log=log)
+            report["accuracy"]["training"] = accuracy_training_report(rows + rows_fl, variants, log=log)
     report["fresh"] = fresh_report(rows, variants, log)
     report["ragged"] = ragged_report(rows, variants, log)
     if os.path.exists(TABLE2):

@@ -497,3 +497,20 @@ def test_accuracy_fresh_report_on_a_synthetic_table():
     assert all(m["K"] > 4096 and m["form"] == "fp32" for m in fp32["missed"])
     mixed = rep["sets"]["mixed_k4"]
     assert mixed["timed"] == 57 and 0 < mixed["frac_of_best_meeting_target"] <= 1.0
+
+
+def test_accuracy_training_report_on_a_synthetic_table():
+    # Selections on 14 and on 64 training shapes, scored on the 20 random
+    # fresh shapes: sizes and fractions in range, every member of a set.
+    from paper_2507_15277_amd import portability
+    variants = portability.read_variants()
+    rng = np.random.default_rng(101)
+    shapes = datagen.grid27() + datagen.fresh_shapes()
+    rows = [{"M": s[0], "N": s[1], "K": s[2], "beta": 0.0, "status": "ok", "variant": v, "data": "lognormal",
+             "ms": float(np.exp(rng.normal(0, 0.5))), "err_norm": 5e-7}
+            for s in shapes for v in variants if variants[v].prec in (0, 4)]
+    rep = portability.accuracy_training_report(rows, variants, log=lambda *_: None)
+    assert len(rep["held_out"]) == 20
+    for label, rec in rep["sets"].items():
+        assert len(rec["kappa"]) == int(label[-1]) and 0 < rec["heldout_frac"] <= 1.0
+        assert rec["heldout_meeting_target"] == 20 and rec["train_frac"] <= 1.0 + 1e-12
