@@ -8,7 +8,12 @@ back-to-back calls bracketed by HIP events, the median of six trials per
 side, interleaved with the order alternating.
 Context for the results, not part of the measured path.
 
-    python -m paper_2507_15277_amd.vendor_compare [--k 4] [--out vendor.json]
+With ``--dense16`` it times the vendor's dense FP16 and BF16 products
+instead (torch.mm on 16-bit operands, FP32 accumulation inside the library)
+on the same shapes: the 16-bit MFMA rate this device reaches in practice,
+the ceiling against which the split-precision forms' MFMA work is read.
+
+    python -m paper_2507_15277_amd.vendor_compare [--k 4] [--dense16] [--out vendor.json]
 """
 from __future__ import annotations
 
@@ -89,12 +94,43 @@ def run(k=4, log=print):
     return rep
 
 
+def run_dense16(log=print):
+    """The vendor's FP16 and BF16 matrix products on the 27 grid shapes
+    (seeded normal operands, contiguous), TFLOP/s per shape and type."""
+    import torch
+
+    g = torch.Generator(device="cuda")
+    g.manual_seed(0)
+    rows = []
+    for (M, N, K) in datagen.grid27():
+        fl = 2.0 * M * N * K
+        row = {"M": M, "N": N, "K": K}
+        for name, dt in (("fp16", torch.float16), ("bf16", torch.bfloat16)):
+            a = torch.randn(M, K, device="cuda", generator=g).to(dt)
+            b = torch.randn(K, N, device="cuda", generator=g).to(dt)
+            c = torch.empty(M, N, device="cuda", dtype=dt)
+
+            def vendor():
+                torch.mm(a, b, out=c)
+
+            t1 = _time_loop(vendor, 3, trials=1)
+            reps = max(1, min(1000, int(round(TARGET_MS / max(t1, 1e-4)))))
+            row[f"tflops_{name}"] = fl / _time_loop(vendor, reps, trials=5) / 1e9
+        rows.append(row)
+        log(f"[vendor16] {M}x{N}x{K}: fp16 {row['tflops_fp16']:7.1f} TFLOP/s, bf16 {row['tflops_bf16']:7.1f} TFLOP/s")
+    gm = lambda key: math.exp(sum(math.log(r[key]) for r in rows) / len(rows))  # noqa: E731
+    return {"shapes": rows, "geomean_tflops_fp16": gm("tflops_fp16"), "geomean_tflops_bf16": gm("tflops_bf16"),
+            "vendor": f"torch {torch.__version__} torch.mm (FP16, BF16)"}
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--k", type=int, default=4)
+    ap.add_argument("--dense16", action="store_true", help="time the vendor's FP16 and BF16 products instead")
     ap.add_argument("--out", default=None)
     args = ap.parse_args(argv)
-    rep = run(args.k, log=lambda s: print(s, flush=True))
+    log = lambda s: print(s, flush=True)  # noqa: E731
+    rep = run_dense16(log) if args.dense16 else run(args.k, log=log)
     if args.out:
         with open(args.out, "w") as f:
             json.dump(rep, f, indent=1)
