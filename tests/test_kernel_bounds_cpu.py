@@ -20,6 +20,18 @@ import numpy as np
 import pytest
 
 from paper_2507_15277_amd import space
+from paper_2507_15277_amd.tune import kernel_hash
+
+# Build hash of the kernel source whose load arithmetic the model below was
+# last checked against, line by line.  A change to the kernel source fails
+# the first test until the model has been re-read against it.
+MODELLED_KERNEL = "5462ee79f990"
+
+
+def test_model_follows_the_current_kernel_source():
+    assert kernel_hash() == MODELLED_KERNEL, (
+        "csrc/sgemm_variant.hip changed since this load model was checked against it: re-check gload's "
+        "clamps and the PD = 1 / PD = 2 call sequences, then update MODELLED_KERNEL")
 
 
 def _loads(v, M, N, K, lda, ldb, tm, tn, kt0, kt1, V=None):
