@@ -18,7 +18,7 @@ Readings of the paper taken here (also listed in the design notes):
 * Ties (equal cost) are broken towards the lexicographically smallest tuple
   of variant ids, as produced by ``itertools.combinations``.
 * The runtime dispatch rule for unseen shapes is not given by the paper
-  (Sec. V-I lists it as a limitation); this build takes the training shapes
+  (Sec. V-I lists it as a limitation); the rule taken here uses the training shapes
   nearest in (log2 M, log2 N, log2 K) under the L1 distance and, among the
   members of kappa, the one with the smallest summed log-slowdown over them
   (ties to the member listed first); a training shape gets its own winner.
@@ -156,7 +156,7 @@ def fleet_rate(runtime, qty_device, qty_input):
     return rate
 
 
-# --- Runtime dispatch (Fig. 1 online step; rule of this build) -----------------
+# --- Runtime dispatch (Fig. 1 online step; the rule chosen here) --------------
 
 def assign_winners(times, kappa, train_shapes_idx):
     """For each training shape, the member of kappa with the lowest time

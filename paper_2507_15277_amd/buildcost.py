@@ -3,7 +3,7 @@
 
 Table II sets the median time to compile one kernel variant against the
 median time of one run of a variant; Table III gives the average size of one
-compiled variant.  Here both come from this build: ``variants/build_stats.txt``
+compiled variant.  Here both come from the compiled family: ``variants/build_stats.txt``
 (hipcc seconds and code-object bytes per variant, written by
 ``build.build_variants``) and the execution-time table (FP32 rows of the
 uniform workload).  The same two costs are summed over each committed set,
