@@ -166,3 +166,53 @@ def test_dispatch_path_graph_replays(cus):
         torch.cuda.synchronize()
         assert torch.equal(C1, eager1), f"replay {r}: K-split FP32 result differs"
         assert torch.equal(C2, eager2), f"replay {r}: pre-split result differs"
+
+
+def test_mixed_set_graph_replays():
+    # The accuracy-targeted set as a captured caller would use it: a shape its
+    # rule sends to the fp16x3 pre-split member (scale passes, split passes,
+    # GEMM) and one it sends to an FP32 member, through sgemm_form and the
+    # allocation-free entry point, captured once and replayed three times with
+    # eager work in between; every replay reproduces the eager result exactly.
+    assert abi.variant_set_load(tuned.set_path(4, "mixed")) == 4
+    shapes = [(1024, 4096, 256), (256, 256, 4096)]
+    forms = [abi.FORM_NAMES[int(abi.variant_info(abi.variant_select_form(abi.FF_FORM_MIXED, *s)).split()[13])]
+             for s in shapes]
+    assert forms == ["fp16x3", "fp32"], forms
+    ops = []
+    for i, (M, N, K) in enumerate(shapes):
+        A, B, C0 = datagen.gemm_operands(61 + i, M, N, K, beta=0.5)
+        ops.append((M, N, K, torch.from_numpy(A).cuda(), torch.from_numpy(B).cuda(), torch.from_numpy(C0).cuda()))
+    outs = [C0.clone() for (_, _, _, _, _, C0) in ops] + [ops[0][5].clone()]
+
+    def calls(stream):
+        for (M, N, K, dA, dB, _), C in zip(ops, outs):
+            abi.sgemm_form(abi.FF_FORM_MIXED, M, N, K, 1.25, dA, K, dB, N, 0.5, C, N, stream)
+        M, N, K, dA, dB, _ = ops[0]
+        abi.sgemm_form_noalloc(abi.FF_FORM_MIXED, M, N, K, 1.25, dA, K, dB, N, 0.5, outs[2], N, stream)
+
+    def reset():
+        for C, src in zip(outs, [o[5] for o in ops] + [ops[0][5]]):
+            C.copy_(src)
+
+    calls(torch.cuda.current_stream())
+    torch.cuda.synchronize()
+    eager = [C.clone() for C in outs]
+    assert torch.equal(eager[2], eager[0]), "the allocation-free call differs from sgemm_form"
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    reset()
+    with torch.cuda.stream(side):
+        calls(side)                                      # warm the side stream
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        calls(torch.cuda.current_stream())
+    for r in range(3):
+        reset()                                          # eager work between replays
+        torch.cuda.synchronize()
+        graph.replay()
+        torch.cuda.synchronize()
+        for j, (C, E) in enumerate(zip(outs, eager)):
+            assert torch.equal(C, E), f"replay {r}: output {j} differs from the eager result"
